@@ -1,0 +1,228 @@
+"""Seeded workload definitions and nucleus placement (input data only).
+
+Every run in this repository starts from a parameter dictionary returned by
+``workload(name)`` or ``small_case(name)`` and from the nucleus list returned by
+``place_nuclei``.  The physical constants that the benchmark configurations leave
+open are filled from the parameter sets printed in the paper's figure captions
+(Sec. 4.3-4.5: k_H = 5e-3, RT = 50, k_Pi = 5e-3) and from the sources listed in
+the design doc.  Randomness: SplitMix64 (Steele, Lea and Flood, 2014) as the integer
+stream and U(0,1) = (u >> 11) * 2**-53.
+
+Nucleus placement is dart throwing: per attempt draw r ~ U[r_min, r_max], then the
+centre coordinates in axis order, each uniform over the liquid box that keeps the
+sphere ``r + 2`` cells away from walls and from the headspace; accept if the centre
+distance to every accepted nucleus is at least ``min_sep`` (or r_i + r_j + 4 when
+``min_sep`` is None).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+_MASK = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 generator (Steele, Lea & Flood, OOPSLA 2014)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        return (self.next_u64() >> 11) * (2.0 ** -53)
+
+    def uniform_range(self, lo: float, hi: float) -> float:
+        return lo + (hi - lo) * self.uniform()
+
+
+_COMMON = dict(
+    periodic=[0, 0, 0],
+    precision="fp64",
+    rheology="newtonian",
+    tau=0.8,
+    pl_n=1.0,
+    pl_nu_ref=0.1,
+    pl_gdot_ref=1e-3,
+    tau_min=0.51,
+    tau_max=2.0,
+    sigma=0.0,
+    D=0.05,
+    q=0.0,
+    kH=5e-3,
+    RT=50.0,
+    k_pi=0.0,
+    d_max=4.0,
+    S0=1.0,
+    p_atm=1.0 / 3.0,
+    eps=1e-3,
+    cleanup=1,
+    max_ids=4096,
+    curvature="plain",
+    steps=100,
+    seed=0,
+    nuclei=None,
+)
+
+
+def _mk(**kw):
+    d = copy.deepcopy(_COMMON)
+    d.update(kw)
+    if d.get("gas_from") is None:
+        last = d["ny"] if d["dim"] == 2 else d["nz"]
+        d["gas_from"] = int(math.floor(0.75 * last))
+    return d
+
+
+# The five benchmark configurations (lattice units; grids include the wall layer).
+WORKLOADS = {
+    # 2D D2Q9 + D2Q5, one bubble of radius 8 at the centre with a seeded sub-cell offset.
+    "c1_2d_128": _mk(
+        name="c1_2d_128", dim=2, nx=128, ny=128, nz=1, precision="fp64", tau=0.8,
+        sigma=1e-3, D=0.05, S0=1.2, steps=1000, seed=1,
+        nuclei=dict(n=1, r_min=8.0, r_max=8.0, center="jitter", p0=1.05 / 3.0),
+    ),
+    # 3D D3Q19 + D3Q7, 32 bubbles, disjoining pressure on lamellae thinner than 2 cells.
+    "c2_3d_128": _mk(
+        name="c2_3d_128", dim=3, nx=128, ny=128, nz=128, precision="fp32", tau=0.7,
+        sigma=5e-4, S0=1.5, k_pi=5e-3, d_max=2.0, steps=5000, seed=2,
+        nuclei=dict(n=32, r_min=3.0, r_max=5.0, min_sep=12.0),
+    ),
+    # 3D 384^3 power-law foam with 2000 bubbles and coalescence.
+    "c3_foam_384": _mk(
+        name="c3_foam_384", dim=3, nx=384, ny=384, nz=384, precision="fp32",
+        rheology="power_law", pl_n=0.6, pl_nu_ref=0.1, pl_gdot_ref=1e-3,
+        tau_min=0.51, tau_max=2.0, tau=0.8, sigma=5e-4, S0=1.5, k_pi=0.0,
+        steps=10000, seed=3, max_ids=16384,
+        nuclei=dict(n=2000, r_min=2.0, r_max=4.0, min_sep=None),
+    ),
+    # 256^3 foam run of the learned-curvature configuration (config-2 style).
+    "c4_foam_256": _mk(
+        name="c4_foam_256", dim=3, nx=256, ny=256, nz=256, precision="fp32", tau=0.7,
+        sigma=5e-4, S0=1.5, k_pi=5e-3, d_max=2.0, steps=5000, seed=41,
+        curvature="mlp", max_ids=8192,
+        nuclei=dict(n=500, r_min=3.0, r_max=5.0, min_sep=12.0),
+    ),
+}
+
+
+def workload(name: str, **overrides) -> dict:
+    d = copy.deepcopy(WORKLOADS[name])
+    d.update(overrides)
+    return d
+
+
+def small_case(name: str, **overrides) -> dict:
+    """Small seeded cases that the oracle finishes in seconds (parity tests)."""
+    cases = {
+        # config-1 physics on a 48x48 grid (several 64-wide tiles are not needed in 2D;
+        # the ragged tail is the 48-wide row).
+        "c1_small": _mk(
+            name="c1_small", dim=2, nx=48, ny=48, nz=1, tau=0.8, sigma=1e-3, S0=1.2,
+            steps=200, seed=1,
+            nuclei=dict(n=1, r_min=6.0, r_max=6.0, center="jitter", p0=1.05 / 3.0),
+        ),
+        "c1_full": copy.deepcopy(WORKLOADS["c1_2d_128"]),
+        # 2D foam with several bubbles that grow and coalesce.
+        "foam2d": _mk(
+            name="foam2d", dim=2, nx=96, ny=80, nz=1, tau=0.8, sigma=1e-3, S0=3.0,
+            kH=5e-3, RT=50.0, steps=300, seed=11,
+            nuclei=dict(n=8, r_min=2.5, r_max=4.0, min_sep=None),
+        ),
+        # 3D config-2 physics on a small ragged grid.
+        "c2_small": _mk(
+            name="c2_small", dim=3, nx=70, ny=40, nz=36, precision="fp64", tau=0.7,
+            sigma=5e-4, S0=1.5, k_pi=5e-3, d_max=2.0, steps=60, seed=2,
+            nuclei=dict(n=6, r_min=3.0, r_max=5.0, min_sep=10.0),
+        ),
+        # 3D power-law foam (config-3 physics) on a small grid.
+        "c3_small": _mk(
+            name="c3_small", dim=3, nx=72, ny=40, nz=40, precision="fp64",
+            rheology="power_law", pl_n=0.6, pl_nu_ref=0.1, pl_gdot_ref=1e-3,
+            tau_min=0.51, tau_max=2.0, tau=0.8, sigma=5e-4, S0=1.5,
+            steps=60, seed=3,
+            nuclei=dict(n=12, r_min=2.0, r_max=4.0, min_sep=None),
+        ),
+    }
+    d = cases[name]
+    d.update(overrides)
+    return d
+
+
+def _liquid_box(wl: dict, r: float):
+    """Bounds of admissible centre coordinates for a nucleus of radius r."""
+    dims = [wl["nx"], wl["ny"], wl["nz"]][: wl["dim"]]
+    lo, hi = [], []
+    for a, n in enumerate(dims):
+        wall = 0 if wl["periodic"][a] else 1
+        lo.append(wall + r + 2.0 - 0.5)
+        top = n - 1 - wall
+        if a == wl["dim"] - 1 and wl["gas_from"] >= 0:
+            top = min(top, wl["gas_from"] - 1)
+        hi.append(top - r - 2.0 + 0.5)
+    return lo, hi
+
+
+def place_nuclei(wl: dict):
+    """Return (centers[n,3], radii[n], p0[n]) for the workload's nucleus recipe."""
+    spec = wl["nuclei"]
+    dim = wl["dim"]
+    if not spec:
+        return np.zeros((0, 3)), np.zeros(0), np.zeros(0)
+    rng = SplitMix64(wl["seed"])
+    n = spec["n"]
+    centers, radii = [], []
+    if spec.get("center") == "jitter":
+        # one nucleus at the grid centre plus a seeded sub-cell offset in [-1/2, 1/2)
+        r = spec["r_min"]
+        c = [0.5 * (wl["nx"] - 1) + 0.5, 0.5 * (wl["ny"] - 1) + 0.5, 0.0]
+        c = [math.floor(c[0]), math.floor(c[1]), 0.0]
+        for a in range(dim):
+            c[a] += rng.uniform() - 0.5
+        if dim == 3:
+            c[2] = math.floor(0.5 * wl["nz"]) + rng.uniform() - 0.5
+        centers.append(c)
+        radii.append(r)
+    else:
+        acc = np.zeros((0, 3))
+        accr = np.zeros(0)
+        attempts = 0
+        while len(radii) < n:
+            attempts += 1
+            if attempts > 1_000_000:
+                raise ValueError(f"could not place {n} nuclei (placed {len(radii)})")
+            r = rng.uniform_range(spec["r_min"], spec["r_max"])
+            lo, hi = _liquid_box(wl, r)
+            c = [0.0, 0.0, 0.0]
+            for a in range(dim):
+                c[a] = rng.uniform_range(lo[a], hi[a])
+            if len(radii):
+                d2 = ((acc[:, :dim] - np.array(c[:dim])) ** 2).sum(axis=1)
+                if spec.get("min_sep") is None:
+                    need = accr + r + 4.0
+                else:
+                    need = np.full(len(accr), float(spec["min_sep"]))
+                if np.any(d2 < need * need):
+                    continue
+            centers.append(c)
+            radii.append(r)
+            acc = np.vstack([acc, np.array(c)[None, :]])
+            accr = np.append(accr, r)
+    centers = np.array(centers, dtype=np.float64).reshape(-1, 3)
+    radii = np.array(radii, dtype=np.float64)
+    if spec.get("p0") is not None:
+        p0 = np.full(len(radii), float(spec["p0"]))
+    else:
+        # Initial nucleus pressure: ambient plus the Laplace jump of a sphere (3D)
+        # or a circle (2D) of the nucleus radius.
+        jump = (2.0 if dim == 3 else 1.0) * wl["sigma"] / radii
+        p0 = wl["p_atm"] + jump
+    return centers, radii, p0

@@ -1,0 +1,313 @@
+"""Pins of the oracle's free-surface and bubble bookkeeping.
+
+P13 hand-worked cell conversions with excess-mass redistribution (Sec. 2.1, last
+paragraph); P14 bubble labelling against scipy.ndimage.label and hand-worked merge /
+split gas bookkeeping (Sec. 3.6); P5-P7 the conservation ledgers and the ideal-gas law
+(Eq. idealgas); P8 the Laplace jump of a static bubble through the gas density of
+Eq. rhob; P12 dissolution of a bubble in gas-free liquid (Sec. 4.3).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+from oracle import Oracle
+from synth import place_nuclei, small_case
+from synth.workloads import _mk
+
+G, I, L, W = 0, 1, 2, 3
+
+
+def _rest_box(nx=9, ny=9, **kw):
+    wl = _mk(name="hand", dim=2, nx=nx, ny=ny, nz=1, gas_from=-1, nuclei=None, S0=0.0,
+             kH=0.0, sigma=0.0, tau=0.8, **kw)
+    o = Oracle(wl)
+    e, w, wg, opp = o.lattice()
+    return o, w
+
+
+def _setup(o, cells):
+    """cells: dict (x,y) -> (type, M); everything else in the interior is liquid."""
+    ny, nx = o.shape[1], o.shape[2]
+    T = np.full((1, ny, nx), L, np.uint8)
+    T[0, 0, :] = T[0, -1, :] = W
+    T[0, :, 0] = T[0, :, -1] = W
+    lab = np.full((1, ny, nx), -1, np.int32)
+    M = np.ones((1, ny, nx))
+    for (x, y), (t, m) in cells.items():
+        T[0, y, x] = t
+        lab[0, y, x] = 1
+        M[0, y, x] = m
+    o.write("type", T)
+    o.write("label", lab)
+    o.write("mass", M)
+    o.write("alpha", M)
+    o.write("rho", np.ones((1, ny, nx)))
+    o.set_bubble(1, 0.1, 5.0, 1 / 3)
+    o.geometry()
+
+
+def _ring(fill=None, mass=0.5):
+    cells = {(4, 4): (G, 0.0)}
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            if dx or dy:
+                cells[(4 + dx, 4 + dy)] = (I, mass)
+    if fill:
+        cells.update(fill)
+    return cells
+
+
+def _liquid_total(o):
+    T = o.read("type")[0]
+    rho = o.read("f").sum(0)[0]
+    M = o.read("mass")[0]
+    return rho[T == L].sum() + M[T == I].sum() + o.ledgers()["lost_liquid"]
+
+
+def test_fill_converts_gas_neighbour_and_spreads_excess():
+    o, w = _rest_box()
+    _setup(o, _ring({(5, 4): (I, 1.2)}))
+    before = _liquid_total(o)
+    o.step(1)
+    T = o.read("type")[0]
+    M = o.read("mass")[0]
+    assert T[4, 5] == L                      # the filled cell
+    assert T[4, 4] == I                      # its gas neighbour became interface
+    # excess 1.2 - rho over the 5 interface neighbours of (5,4) under the new types:
+    # (4,3), (4,4), (4,5), (5,3), (5,5)
+    share = 0.2 / 5
+    for (x, y) in [(4, 3), (4, 5), (5, 3), (5, 5)]:
+        assert abs(M[y, x] - (0.5 + share)) < 1e-14
+    assert abs(M[4, 4] - share) < 1e-14
+    for (x, y) in [(3, 3), (3, 4), (3, 5)]:
+        assert M[y, x] == 0.5
+    # the new interface cell starts from the mean state of its neighbours (at rest)
+    f = o.read("f")[:, 0, 4, 4]
+    assert np.abs(f - w).max() < 1e-15
+    b = o.bubbles()
+    assert list(b["id"]) == [1]
+    assert abs(b["V"][0] - (3 * 0.5 + 4 * (1 - 0.5 - share) + (1 - share))) < 1e-13
+    assert abs(_liquid_total(o) - before) < 1e-13
+
+
+def test_empty_converts_liquid_neighbours():
+    o, w = _rest_box()
+    _setup(o, _ring({(3, 4): (I, -0.01)}))
+    before = _liquid_total(o)
+    o.step(1)
+    T = o.read("type")[0]
+    M = o.read("mass")[0]
+    lab = o.read("label")[0]
+    assert T[4, 3] == G
+    for (x, y) in [(2, 3), (2, 4), (2, 5)]:
+        assert T[y, x] == I and lab[y, x] == 1
+    # shortage -0.01 over the 7 interface neighbours of (3,4) under the new types
+    share = -0.01 / 7
+    rho = o.read("f").sum(0)[0]
+    for (x, y) in [(2, 3), (2, 4), (2, 5)]:
+        assert abs(M[y, x] - (rho[y, x] + share)) < 1e-14
+    for (x, y) in [(3, 3), (3, 5), (4, 3), (4, 5)]:
+        assert abs(M[y, x] - (0.5 + share)) < 1e-14
+    assert T[4, 4] == G
+    assert abs(_liquid_total(o) - before) < 1e-13
+
+
+def test_empty_next_to_fill_is_cancelled():
+    o, w = _rest_box()
+    _setup(o, _ring({(3, 4): (I, -0.01), (3, 3): (I, 1.3)}))
+    o.step(1)
+    T = o.read("type")[0]
+    M = o.read("mass")[0]
+    assert T[3, 3] == L                       # filled
+    assert T[4, 3] == I                       # emptied cell next to it is kept
+    assert T[4, 4] == I                       # the gas centre touches the filled cell
+    # (3,4) keeps its negative mass plus its share of the fill excess; the filled cell
+    # (3,3) spreads over its interface neighbours under the new types
+    nb = [(3 + dx, 3 + dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1) if dx or dy]
+    nI = sum(1 for (x, y) in nb if T[y, x] == I)
+    share = (1.3 - 1.0) / nI
+    assert abs(M[4, 3] - (-0.01 + share)) < 1e-12
+
+
+def test_cleanup_fills_stranded_interface():
+    o, w = _rest_box()
+    cells = {(4, 4): (I, 0.5)}   # an interface cell with no gas neighbour
+    _setup(o, cells)
+    o.step(1)
+    T = o.read("type")[0]
+    assert T[4, 4] == L
+    assert o.bubbles()["id"].size == 0
+
+
+def _random_mask_state(dim, shape, seed):
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        wl = _mk(name="ccl", dim=2, nx=shape[1], ny=shape[0], nz=1, gas_from=-1, nuclei=None)
+    else:
+        wl = _mk(name="ccl", dim=3, nx=shape[2], ny=shape[1], nz=shape[0], gas_from=-1,
+                 nuclei=None)
+    o = Oracle(wl)
+    full = o.shape
+    r = rng.uniform(size=full)
+    T = np.where(r < 0.3, G, np.where(r < 0.45, I, L)).astype(np.uint8)
+    inner = tuple(slice(1, -1) if s > 1 else slice(None) for s in full)
+    Tw = np.full(full, W, np.uint8)
+    Tw[inner] = T[inner]
+    T = Tw
+    lab = np.where((T == G) | (T == I), rng.integers(1, 4, size=full), -1).astype(np.int32)
+    al = np.where(T == I, rng.uniform(0.05, 0.95, size=full), np.where(T == L, 1.0, 0.0))
+    o.write("type", T)
+    o.write("label", lab)
+    o.write("alpha", al)
+    for b, m in ((1, 1.0), (2, 2.0), (3, 4.0)):
+        o.set_bubble(b, m, 1.0, 1 / 3)
+    return o, T, lab, al
+
+
+@pytest.mark.parametrize("dim,shape,seed", [(2, (14, 17), 1), (2, (20, 23), 2),
+                                            (3, (9, 10, 11), 3), (3, (12, 9, 10), 4)])
+def test_labelling_matches_scipy(dim, shape, seed):
+    o, T, lab0, al = _random_mask_state(dim, shape, seed)
+    present = {b for b in (1, 2, 3) if np.any(lab0 == b)}
+    m_before = sum({1: 1.0, 2: 2.0, 3: 4.0}[b] for b in present)
+    o.relabel()
+    lab = o.read("label")
+    mask = (T == G) | (T == I)
+    st = ndi.generate_binary_structure(dim, dim if dim == 2 else 2)
+    if dim == 2:
+        comp, ncomp = ndi.label(mask[0], structure=st)
+        comp = comp[None]
+    else:
+        comp, ncomp = ndi.label(mask, structure=st)
+    # same partition: one id per scipy component and different ids for different ones
+    ids = {}
+    for k in range(1, ncomp + 1):
+        vals = np.unique(lab[comp == k])
+        assert vals.size == 1
+        ids[k] = int(vals[0])
+    assert len(set(ids.values())) == ncomp
+    # canonical ids: components in ascending smallest cell index take the smallest
+    # old id present that is not yet taken, else a fresh id
+    flat_comp = comp.ravel()
+    roots = sorted(range(1, ncomp + 1), key=lambda k: np.flatnonzero(flat_comp == k)[0])
+    taken, nxt = set(), 4
+    b = o.bubbles()
+    V = dict(zip(b["id"], b["V"]))
+    for k in roots:
+        old = sorted(set(lab0.ravel()[flat_comp == k].tolist()))
+        cand = [j for j in old if j not in taken]
+        want = cand[0] if cand else nxt
+        if not cand:
+            nxt += 1
+        taken.add(want)
+        assert ids[k] == want
+        vol = (1 - np.where(T == I, al, 0.0)).ravel()[flat_comp == k].sum()
+        assert abs(V[want] - vol) < 1e-12
+    # gas is only redistributed
+    assert abs(b["m"].sum() - m_before) < 1e-13
+    # ideal-gas law (Eq. idealgas) with the volume floor
+    assert np.allclose(b["p"] * np.maximum(b["V"], 0.5), b["m"] * o.wl["RT"], rtol=1e-15, atol=0)
+
+
+def test_merge_and_split_bookkeeping():
+    wl = _mk(name="ms", dim=2, nx=12, ny=8, nz=1, gas_from=-1, nuclei=None, RT=2.0)
+    o = Oracle(wl)
+    T = np.full((1, 8, 12), L, np.uint8)
+    T[0, 0, :] = T[0, -1, :] = W
+    T[0, :, 0] = T[0, :, -1] = W
+    lab = np.full((1, 8, 12), -1, np.int32)
+    # bubble 1: x in 2..4, bubble 2: x in 5..7 (touching -> merge), rows 2..4
+    T[0, 2:5, 2:8] = G
+    lab[0, 2:5, 2:5] = 1
+    lab[0, 2:5, 5:8] = 2
+    # bubble 3: two separate blobs (-> split), volumes 2 and 4
+    T[0, 6, 2:4] = G
+    T[0, 6, 6:10] = G
+    lab[0, 6, 2:4] = 3
+    lab[0, 6, 6:10] = 3
+    o.write("type", T)
+    o.write("label", lab)
+    o.write("alpha", np.where(T == L, 1.0, 0.0))
+    o.set_bubble(1, 0.3, 9.0, 0.0)
+    o.set_bubble(2, 0.5, 9.0, 0.0)
+    o.set_bubble(3, 0.6, 6.0, 0.0)
+    o.relabel()
+    b = o.bubbles()
+    got = {int(i): (m, V, p) for i, m, V, p in zip(b["id"], b["m"], b["V"], b["p"])}
+    # merge: m = m1 + m2, V = V1 + V2, p = (m1+m2) RT / (V1+V2)
+    assert abs(got[1][0] - 0.8) < 1e-15 and got[1][1] == 18.0
+    assert abs(got[1][2] - 0.8 * 2.0 / 18.0) < 1e-15
+    assert 2 not in got
+    # split: the blob with the smaller root keeps id 3, the other gets a fresh id (4);
+    # gas goes in proportion to volume
+    assert abs(got[3][0] - 0.6 * 2 / 6) < 1e-15 and got[3][1] == 2.0
+    assert abs(got[4][0] - 0.6 * 4 / 6) < 1e-15 and got[4][1] == 4.0
+
+
+def _ledgers(o, wl):
+    t = o.totals()
+    gas = t["dissolved"] + t["bubble_gas"] + t["atm_gas"] + t["collapsed_gas"]
+    return t["liquid"] + t["lost_liquid"], gas
+
+
+@pytest.mark.parametrize("case,steps", [("foam2d", 300), ("c1_small", 200), ("c2_small", 40),
+                                        ("c3_small", 30)])
+def test_conservation_and_ideal_gas(case, steps):
+    wl = small_case(case)
+    o = Oracle(wl)
+    o.nucleate(*place_nuclei(wl))
+    liq0, gas0 = _ledgers(o, wl)
+    chunk = max(1, steps // 5)
+    done = 0
+    while done < steps:
+        o.step(chunk)
+        done += chunk
+        liq, gas = _ledgers(o, wl)
+        assert abs(liq - liq0) / liq0 < 1e-12
+        assert abs(gas - gas0) / gas0 < 1e-12
+        b = o.bubbles()
+        assert np.allclose(b["p"] * np.maximum(b["V"], 0.5), b["m"] * wl["RT"], rtol=1e-15, atol=0)
+
+
+def test_laplace_jump_2d():
+    """A bubble in a closed, gas-free liquid relaxes to p_bubble - p_liquid = 2 sigma
+    kappa = sigma / R in 2D (Eq. rhob with kappa = 1/(2R))."""
+    n = 64
+    sigma = 0.02
+    wl = _mk(name="lap", dim=2, nx=n, ny=n, nz=1, gas_from=-1, nuclei=None, sigma=sigma,
+             kH=0.0, S0=0.0, tau=1.0, RT=1.0)
+    o = Oracle(wl)
+    R = 10.0
+    o.nucleate(np.array([[31.7, 32.2, 0.0]]), np.array([R]),
+               np.array([wl["p_atm"] + sigma / R]))
+    o.step(2500)
+    T = o.read("type")[0]
+    rho = o.read("f").sum(0)[0]
+    b = o.bubbles()
+    Reff = math.sqrt(b["V"][0] / math.pi)
+    yy, xx = np.mgrid[0:n, 0:n]
+    far = (T == L) & (np.hypot(xx - 31.7, yy - 32.2) > R + 6)
+    p_liq = rho[far].mean() / 3
+    jump = b["p"][0] - p_liq
+    assert abs(jump / (sigma / Reff) - 1) < 0.1
+
+
+def test_dissolution_volume_decreases():
+    """Gas-free liquid dissolves a bubble (Sec. 4.3 parameters): the bubble volume falls
+    and its gas ends in the liquid."""
+    wl = _mk(name="diss", dim=2, nx=48, ny=48, nz=1, gas_from=-1, nuclei=None,
+             tau=0.98, D=0.1, RT=500.0, S0=0.0, kH=5e-3, sigma=4.2e-3)
+    o = Oracle(wl)
+    o.nucleate(np.array([[23.6, 24.3, 0.0]]), np.array([5.0]), np.array([1 / 3 + 4.2e-3 / 5]))
+    liq0, gas0 = _ledgers(o, wl)
+    vols = [o.bubbles()["V"][0]]
+    for _ in range(8):
+        o.step(100)
+        b = o.bubbles()
+        vols.append(b["V"][0] if b["V"].size else 0.0)
+    assert vols[-1] < 0.6 * vols[0]
+    assert all(vols[k + 1] <= vols[k] + 0.5 for k in range(len(vols) - 1))
+    liq, gas = _ledgers(o, wl)
+    assert abs(gas - gas0) / gas0 < 1e-12
