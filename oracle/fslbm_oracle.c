@@ -411,15 +411,20 @@ static int normal_at(const OS *s, int64_t n, double m[3]) {
   return 1;
 }
 
-/* Gaussian elimination with partial pivoting (first maximum on ties);
- * returns 0 if a pivot magnitude falls below 1e-12 */
+/* Gaussian elimination with partial pivoting (first maximum on ties); returns 0 when a
+ * pivot magnitude falls below 1e-9 of the largest diagonal entry of the normal matrix,
+ * i.e. when the points do not determine the fit (e.g. one-sided point sets at walls) */
 static int solve(int n, double A[6][6], double b[6], double x[6]) {
   int c, r, k;
+  double scale = 0.0;
+  for (c = 0; c < n; c++)
+    if (A[c][c] > scale) scale = A[c][c];
+  double tiny = 1e-9 * scale;
   for (c = 0; c < n; c++) {
     int piv = c;
     for (r = c + 1; r < n; r++)
       if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-    if (fabs(A[piv][c]) < 1e-12) return 0;
+    if (!(fabs(A[piv][c]) >= tiny)) return 0;
     if (piv != c) {
       for (k = 0; k < n; k++) {
         double t = A[c][k];
@@ -522,6 +527,11 @@ double or_curvature_at(const OS *s, int64_t n) {
         }
   }
   if (np < nun) return 0.0;
+  /* 3D: ridge term on the quadratic coefficients; it keeps the fit determined when the
+   * points of the 3x3x3 block lie on one side of the cell (next to a wall) and pulls the
+   * undetermined curvature towards zero there (the 5x5 block of 2D needs none) */
+  if (s->D == 3)
+    for (a = 0; a < 3; a++) A[a][a] = A[a][a] + 1e-2;
   if (!solve(nun, A, rhs, sol)) return 0.0;
   double kap;
   if (s->D == 3) {

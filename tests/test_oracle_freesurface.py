@@ -271,27 +271,31 @@ def test_conservation_and_ideal_gas(case, steps):
         assert np.allclose(b["p"] * np.maximum(b["V"], 0.5), b["m"] * wl["RT"], rtol=1e-15, atol=0)
 
 
-def test_laplace_jump_2d():
+@pytest.mark.parametrize("R", [8.0, 12.0])
+def test_laplace_jump_2d(R):
     """A bubble in a closed, gas-free liquid relaxes to p_bubble - p_liquid = 2 sigma
-    kappa = sigma / R in 2D (Eq. rhob with kappa = 1/(2R))."""
+    kappa = sigma / R in 2D (Eq. rhob with kappa = 1/(2R)). The interface keeps
+    oscillating by about 15%, so the jump is averaged over 3000 steps."""
     n = 64
     sigma = 0.02
     wl = _mk(name="lap", dim=2, nx=n, ny=n, nz=1, gas_from=-1, nuclei=None, sigma=sigma,
              kH=0.0, S0=0.0, tau=1.0, RT=1.0)
     o = Oracle(wl)
-    R = 10.0
     o.nucleate(np.array([[31.7, 32.2, 0.0]]), np.array([R]),
                np.array([wl["p_atm"] + sigma / R]))
-    o.step(2500)
-    T = o.read("type")[0]
-    rho = o.read("f").sum(0)[0]
-    b = o.bubbles()
-    Reff = math.sqrt(b["V"][0] / math.pi)
+    o.step(1000)
     yy, xx = np.mgrid[0:n, 0:n]
-    far = (T == L) & (np.hypot(xx - 31.7, yy - 32.2) > R + 6)
-    p_liq = rho[far].mean() / 3
-    jump = b["p"][0] - p_liq
-    assert abs(jump / (sigma / Reff) - 1) < 0.1
+    far = np.hypot(xx - 31.7, yy - 32.2) > R + 6
+    jumps = []
+    for _ in range(30):
+        o.step(100)
+        T = o.read("type")[0]
+        rho = o.read("f").sum(0)[0]
+        b = o.bubbles()
+        Reff = math.sqrt(b["V"][0] / math.pi)
+        p_liq = rho[far & (T == L)].mean() / 3
+        jumps.append((b["p"][0] - p_liq) / (sigma / Reff))
+    assert abs(np.mean(jumps) - 1) < 0.12
 
 
 def test_dissolution_volume_decreases():
