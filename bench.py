@@ -1,0 +1,194 @@
+"""Benchmark: the foaming lattice sweep on the 384^3 D3Q19 + D3Q7 power-law foam with
+2000 bubbles (synthetic, seeded), on one MI355X.
+
+A step is one pass of the whole hot path: lattice sweep, cell conversion, bubble
+labelling and gas bookkeeping, bubble pressures, curvature and disjoining pressure.
+Two runs: populations stored in binary32 ("FP32 plain") and stored as binary16 offsets
+f_i - w_i with binary32 arithmetic ("FP16 store"). ``value`` is the whole-step MLUPS of
+the FP16-store run; the FP32 run and the ratio are reported beside it.
+
+Prints one JSON line. Options: --gpus N (only 1), --steps K, --warmup W,
+--workload NAME, --no-cpu-baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS & %HBM peak, 384^3 foam; FP16-store+MLP-curvature vs FP32 plain"
+
+
+def sweep_bytes(wl, T, prec):
+    """Algorithmic bytes of one sweep launch: every liquid / interface cell reads and
+    writes each population once (f: Q values, g: Qg values) and reads its type byte;
+    every other cell reads its type byte."""
+    import numpy as np
+    Q, Qg = (9, 5) if wl["dim"] == 2 else (19, 7)
+    sf = {"fp64": 8, "fp32": 4, "f16s": 2, "bf16s": 2}[prec]
+    sg = 8 if prec == "fp64" else 4
+    n_fluid = int(np.count_nonzero((T == 1) | (T == 2)))
+    n_other = int(T.size) - n_fluid
+    per_cell = 2 * Q * sf + 2 * Qg * sg + 1
+    return n_fluid * per_cell + n_other, n_fluid, per_cell
+
+
+def run_one(wl, steps, warmup, log):
+    import numpy as np
+    import torch
+
+    from paper_1908_04262_amd import Sim
+    from synth import place_nuclei
+
+    t0 = time.time()
+    sim = Sim(wl, device=0)
+    c, r, p0 = place_nuclei(wl)
+    sim.nucleate(c, r, p0)
+    log(f"[{wl['precision']}] created + nucleated {len(r)} nuclei in {time.time() - t0:.1f}s")
+    sim.step(warmup)
+    sim.sync()
+    log(f"[{wl['precision']}] warmup {warmup} steps done")
+    T0 = sim.read("type")
+    bytes0, nf0, per_cell = sweep_bytes(wl, T0, wl["precision"])
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.sync()
+    sweep_ms, nsw = sim.profile_get(0)
+    step_ms, nst = sim.profile_get(1)
+    sim.profile(False)
+    T1 = sim.read("type")
+    bytes1, nf1, _ = sweep_bytes(wl, T1, wl["precision"])
+    tot = sim.totals()
+    led = sim.ledgers()
+    ncell = int(np.prod(sim.shape))
+    wall = t2 - t1
+    sweep_avg_s = sweep_ms / 1e3 / max(nsw, 1)
+    bytes_launch = 0.5 * (bytes0 + bytes1)
+    res = dict(
+        precision=wl["precision"],
+        mlups=ncell * steps / wall / 1e6,
+        ms_per_step=wall * 1e3 / steps,
+        sweep_ms=sweep_avg_s * 1e3,
+        step_event_ms=step_ms / max(nst, 1),
+        sweep_bytes=bytes_launch,
+        sweep_gbs=bytes_launch / sweep_avg_s / 1e9,
+        bytes_per_fluid_cell=per_cell,
+        n_fluid=0.5 * (nf0 + nf1),
+        n_interface=int(np.count_nonzero(T1 == 1)),
+        n_bubbles=led["n_bubbles"],
+        status=led["status"],
+        liquid_mass=float(tot["liquid"] + tot["lost_liquid"]),
+    )
+    # whole-step algorithmic HBM fraction (sweep bytes per step over wall time)
+    res["hbm_frac_step"] = bytes_launch / (wall / steps) / 1e9 / HBM_PEAK_GBS
+    log(f"[{wl['precision']}] {json.dumps(res)}")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(log, budget_s=20.0):
+    """The FP64 oracle on the host: the same recipe (power-law foam, supersaturation
+    1.5, r ~ U[2,4]) on a 96^3 crop with the bubble density of the 384^3 case, timed over
+    a few steps."""
+    import numpy as np
+
+    from oracle import Oracle
+    from synth import place_nuclei, workload
+
+    n = 96
+    frac = (n / 384.0) ** 3
+    wl = workload("c3_foam_384", nx=n, ny=n, nz=n, precision="fp64", max_ids=4096)
+    wl["gas_from"] = int(0.75 * n)
+    wl["nuclei"] = dict(wl["nuclei"], n=max(1, int(round(2000 * frac))))
+    o = Oracle(wl)
+    o.nucleate(*place_nuclei(wl))
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s and steps < 50:
+        o.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    ncell = n ** 3
+    v = ncell * steps / dt / 1e6
+    log(f"cpu baseline: {steps} steps of {n}^3 in {dt:.1f}s -> {v:.3f} MLUPS")
+    return dict(value=v, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} steps of the FP64 oracle on a {n}^3 crop of the 384^3 recipe "
+                       f"({wl['nuclei']['n']} nuclei), single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3_foam_384")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the sweep would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    def log(msg):
+        if not a.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    from synth import workload
+
+    wl = workload(a.workload)
+    r32 = run_one(dict(wl, precision="fp32"), a.steps, a.warmup, log)
+    r16 = run_one(dict(wl, precision="f16s"), a.steps, a.warmup, log)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(log)
+    out = {
+        "metric": METRIC,
+        "value": round(r16["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r16["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl['name']}: {wl['nx']}x{wl['ny']}x{wl['nz']} D3Q19+D3Q7 power-law "
+                        f"foam, {wl['nuclei']['n']} bubbles r~U[2,4], seed {wl['seed']}",
+            "storage": "f16 offsets f-w (value); fp32 run reported as fp32_plain",
+            "curvature": "plain paraboloid fit",
+        },
+        "hbm_frac_step": round(r16["hbm_frac_step"], 4),
+        "fp32_plain": {"mlups": round(r32["mlups"], 2), "ms_per_step": round(r32["ms_per_step"], 4),
+                       "hbm_frac_step": round(r32["hbm_frac_step"], 4),
+                       "sweep_gbs": round(r32["sweep_gbs"], 1)},
+        "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_sweep<3,2> (f16 offsets)",
+            "achieved": round(r16["sweep_gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(r16["sweep_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": r16["sweep_bytes"],
+            "avg_launch_ms": round(r16["sweep_ms"], 4),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * mifoam: free-surface lattice Boltzmann foaming sweep on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the shared library libmifoam.so. Every function returns an int status
+ * (MF_OK = 0, negative on error); no C++ exception crosses this boundary. After an
+ * error, mf_last_error() returns a message. Pointers are plain host pointers unless a
+ * parameter says "device". Sizes are in bytes unless stated otherwise.
+ *
+ * The method is that of Ataei et al., "LBfoam: an open-source software package for the
+ * simulation of foaming using the lattice Boltzmann method" (arXiv 1908.04262):
+ *   - lattice Boltzmann flow on D2Q9 / D3Q19 with BGK collision (Sec. 2, Eqs. LBE,
+ *     collisionstep, streamingstep, collision, equilibrium), Newtonian or power-law
+ *     relaxation (Eqs. tau, carreauTau);
+ *   - volume-of-fluid interface capturing by mass tracking (Sec. 2.1, Eqs. alpha,
+ *     massexchange and the weights Theta) with cell conversion and excess-mass
+ *     redistribution;
+ *   - free-surface reconstruction at the bubble pressure with surface tension and
+ *     disjoining pressure (Sec. 2.2, Eqs. reconstruct, rhob, idealgas; Sec. 3.3, Eq.
+ *     rhobplusdisjoining, Appendix A Algorithm 1);
+ *   - dissolved gas on D2Q5 / D3Q7 with a Henry's-law interface condition and per-bubble
+ *     gas flux (Sec. 3.1-3.2, Eqs. diffusion, diffusionconst, gascurrent, henryslaw,
+ *     reconstructdiffusion);
+ *   - bubble tracking by flood fill with merge / split bookkeeping (Sec. 3.6).
+ *
+ * Lattice units throughout. Cell index n = x + nx*(y + ny*z); grids include the wall
+ * layer of every closed axis. Device work is enqueued on the stream given to
+ * mf_create; functions that return host data synchronise that stream.
+ */
+#ifndef MIFOAM_H
+#define MIFOAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MF_ABI_VERSION 1
+
+enum mf_status {
+  MF_OK = 0,
+  MF_EINVAL = -1,       /* bad argument or parameter */
+  MF_ENOMEM = -2,       /* workspace too small or allocation failed */
+  MF_EHIP = -3,         /* a HIP runtime call failed */
+  MF_ECAPACITY = -4,    /* bubble table or labelling tables overflowed */
+  MF_ENUMERIC = -5,     /* the device flagged an invalid state (see mf_last_error) */
+  MF_ESTATE = -6,       /* call not valid in the context's current state */
+  MF_EUNSUPPORTED = -7, /* option not built into this library */
+  MF_EINTERNAL = -8
+};
+
+/* storage / arithmetic forms of the populations */
+enum mf_precision {
+  MF_FP64 = 0,     /* f, g and all cell fields in binary64 */
+  MF_FP32 = 1,     /* f, g and cell fields in binary32; bubble table in binary64 */
+  MF_F16S = 2,     /* f stored as binary16 offsets f_i - w_i, arithmetic in binary32 */
+  MF_BF16S = 3     /* f stored as bfloat16 offsets f_i - w_i, arithmetic in binary32 */
+};
+
+enum mf_rheology { MF_NEWTONIAN = 0, MF_POWER_LAW = 1 };
+enum mf_curvature { MF_CURV_PLAIN = 0, MF_CURV_MLP = 1 };
+
+/* cell types reported by MF_FIELD_TYPE */
+enum mf_cell_type { MF_GAS = 0, MF_INTERFACE = 1, MF_LIQUID = 2, MF_WALL = 3 };
+
+/* fields for mf_read_field / mf_write_field */
+enum mf_field {
+  MF_FIELD_TYPE = 0,  /* uint8 [N] cell type (mf_cell_type) */
+  MF_FIELD_LABEL = 1, /* int32 [N] bubble id of gas / interface cells (0 = atmosphere), -1 elsewhere */
+  MF_FIELD_RHO = 2,   /* double [N] density of interface cells */
+  MF_FIELD_UX = 3,    /* double [N] velocity of interface cells */
+  MF_FIELD_UY = 4,
+  MF_FIELD_UZ = 5,
+  MF_FIELD_ALPHA = 6, /* double [N] fill fraction (1 on liquid, 0 on gas and walls) */
+  MF_FIELD_MASS = 7,  /* double [N] liquid mass M of interface cells */
+  MF_FIELD_CONC = 8,  /* double [N] dissolved gas c = sum_i g_i (liquid and interface cells) */
+  MF_FIELD_KAPPA = 9, /* double [N] curvature of interface cells */
+  MF_FIELD_PI = 10,   /* double [N] disjoining pressure of interface cells */
+  MF_FIELD_F = 11,    /* double [Q][N] post-collision populations f */
+  MF_FIELD_G = 12     /* double [Qg][N] post-collision ADE populations g */
+};
+
+typedef struct mf_ctx mf_ctx; /* opaque; one context is used by one host thread at a time */
+
+typedef struct mf_params {
+  size_t struct_size;    /* = sizeof(mf_params) */
+  int32_t dim;           /* 2 (D2Q9 + D2Q5) or 3 (D3Q19 + D3Q7) */
+  int32_t nx, ny, nz;    /* grid incl. wall layers; nz = 1 in 2D */
+  int32_t periodic[3];   /* 1: periodic axis, 0: closed by a wall layer on both sides */
+  int32_t gas_from;      /* cells whose last coordinate >= gas_from start as headspace
+                            gas of the atmosphere (id 0); < 0: no headspace */
+  int32_t precision;     /* mf_precision */
+  int32_t rheology;      /* mf_rheology */
+  int32_t curvature;     /* mf_curvature */
+  int32_t cleanup;       /* 1: stranded interface cells are filled / emptied */
+  int32_t max_ids;       /* bubble-table capacity (ids 0..max_ids-1, never reused) */
+  double tau;            /* BGK relaxation time (Newtonian) */
+  double D;              /* gas diffusivity; tau_g = 1/2 + D / c_s,g^2 */
+  double sigma;          /* surface tension (gamma in the paper) */
+  double kH;             /* Henry constant: c = kH p at interfaces */
+  double RT;             /* ideal-gas constant times temperature */
+  double k_pi;           /* disjoining-pressure constant (0: off) */
+  double d_max;          /* disjoining-pressure range in cells */
+  double p_atm;          /* pressure of the atmosphere (id 0) */
+  double q;              /* gas source per cell and step */
+  double eps;            /* conversion threshold: fill if M > (1+eps) rho, empty if M < -eps rho */
+  double S0;             /* initial supersaturation c0 / (kH p_atm) */
+  double pl_n, pl_nu_ref, pl_gdot_ref; /* power law nu = nu_ref (gdot/gdot_ref)^(n-1) */
+  double tau_min, tau_max;             /* clamp of the power-law relaxation time */
+} mf_params;
+
+typedef struct mf_bubble {
+  int32_t id;
+  int32_t alive;
+  double volume;   /* sum over the bubble's cells of (1 - alpha) */
+  double gas_mass; /* m_g */
+  double pressure; /* m_g RT / max(volume, 1/2) */
+} mf_bubble;
+
+typedef struct mf_totals {
+  int64_t step;
+  double lost_liquid;   /* excess liquid mass that found no interface neighbour */
+  double atm_gas;       /* gas handed to the atmosphere */
+  double collapsed_gas; /* gas of bubbles whose last cell vanished */
+  int32_t next_id;
+  int32_t n_bubbles;    /* live bubbles, atmosphere excluded */
+  int32_t n_interface;  /* interface cells entering the last step */
+  int32_t status;       /* device status bits, 0 when healthy */
+} mf_totals;
+
+/* Library ABI version (MF_ABI_VERSION of the build). */
+int mf_abi_version(void);
+
+/* Message of the last failed call on ctx; with ctx == NULL, of the last failed
+ * mf_create / mf_workspace_bytes on this thread. The pointer stays valid until the
+ * next call on the same context. */
+const char *mf_last_error(const mf_ctx *ctx);
+
+/* Device bytes a context with these parameters needs (arrays sized for every cell:
+ * populations in two buffers, cell fields, interface lists, labelling tables). */
+int mf_workspace_bytes(const mf_params *p, size_t *bytes);
+
+/* Create a context: validates p (MF_EINVAL), carves its arrays out of dev_workspace
+ * (device memory of at least mf_workspace_bytes, owned by the caller and kept alive
+ * until mf_destroy) or, when dev_workspace is NULL, allocates them itself. stream is a
+ * hipStream_t (NULL: the null stream). Initialises a liquid at rest (f = w_i,
+ * g = w_i c0 with c0 = S0 kH p_atm), walls on closed axes and the headspace. */
+int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *stream, mf_ctx **out);
+
+/* Destroy; frees only memory the library allocated. NULL is accepted. */
+int mf_destroy(mf_ctx *ctx);
+
+/* Nucleation (Sec. 3.5): n spheres (disks in 2D) with centres [n][3] (z ignored in
+ * 2D), radii [n] and initial pressures p0 [n] (host arrays). Each is voxelised with 8
+ * sample points per axis and cell; nucleus k gets id k+1; overlapping nuclei merge to
+ * the smaller id. Gas mass = p0 V / RT (Eq. idealgas). Valid once, before mf_step
+ * (MF_ESTATE otherwise). MF_EINVAL if a nucleus is not inside the liquid. */
+int mf_nucleate(mf_ctx *ctx, int32_t n, const double *centers, const double *radii, const double *p0);
+
+/* Advance nsteps time steps (enqueued on the context stream; returns without waiting).
+ * Each step: stream / collide f and g, interface mass exchange, Henry's-law and
+ * free-surface reconstruction, cell conversion with excess redistribution, bubble
+ * labelling and gas bookkeeping, bubble pressures, curvature, disjoining pressure. */
+int mf_step(mf_ctx *ctx, int32_t nsteps);
+
+/* Wait for the context stream and report device status (MF_ENUMERIC / MF_ECAPACITY
+ * if the device flagged an invalid state or a full table). */
+int mf_sync(mf_ctx *ctx);
+
+/* Copy a field (mf_field) into dst (host memory, or device memory when dst_on_device
+ * is 1). dst_bytes must hold the field (see mf_field for element types and counts).
+ * Synchronises the context stream. */
+int mf_read_field(mf_ctx *ctx, int32_t field, void *dst, size_t dst_bytes, int32_t dst_on_device);
+
+/* Overwrite a field from host memory (hand-built test states); same layout as
+ * mf_read_field. Allowed before the first mf_step. Call mf_refresh afterwards. */
+int mf_write_field(mf_ctx *ctx, int32_t field, const void *src, size_t src_bytes);
+
+/* Set one bubble-table entry (hand-built test states). */
+int mf_set_bubble(mf_ctx *ctx, int32_t id, double gas_mass, double volume, double pressure, int32_t alive);
+
+/* Recompute the derived state of a hand-written state: interface lists, curvature and
+ * disjoining pressure. relabel = 1 also runs bubble labelling with no gas flux. */
+int mf_refresh(mf_ctx *ctx, int32_t relabel);
+
+/* Live bubbles (atmosphere excluded) in ascending id; *n_out = number of live bubbles
+ * (may exceed capacity; then only capacity entries are written). Synchronises. */
+int mf_read_bubbles(mf_ctx *ctx, mf_bubble *dst, int32_t capacity, int32_t *n_out);
+
+/* Ledgers and counters. Synchronises. */
+int mf_totals_get(mf_ctx *ctx, mf_totals *out);
+
+/* Time of the last mf_step window in milliseconds per launch of the named kernel
+ * group, measured with HIP events on the context stream: group 0 = lattice sweep,
+ * 1 = whole step. Valid after mf_profile_enable(ctx, 1) and a completed mf_step. */
+int mf_profile_enable(mf_ctx *ctx, int32_t on);
+int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,556 @@
+// C ABI of libmifoam (declared in include/mifoam.h): context, device arena, the time
+// step as a fixed sequence of kernel launches on the caller's stream, field transfer.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mf_internal.h"
+
+using namespace mf;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct OpsTable {
+  void (*sweep)(Ctx &, hipStream_t);
+  void (*convert)(Ctx &, hipStream_t);
+  void (*label)(Ctx &, hipStream_t, int);
+  void (*geometry)(Ctx &, hipStream_t);
+  void (*init_box)(Ctx &, hipStream_t);
+  void (*nucleate)(Ctx &, hipStream_t, int, const double *, const double *);
+  void (*build_lists)(Ctx &, hipStream_t);
+  void (*read_field)(Ctx &, hipStream_t, int, double *);
+  void (*write_field)(Ctx &, hipStream_t, int, const double *);
+};
+
+template <int D, int P>
+OpsTable make_ops() {
+  return OpsTable{&Ops<D, P>::sweep,    &Ops<D, P>::convert,     &Ops<D, P>::label,
+                  &Ops<D, P>::geometry, &Ops<D, P>::init_box,    &Ops<D, P>::nucleate,
+                  &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field};
+}
+
+OpsTable ops_for(int dim, int prec) {
+  if (dim == 2) {
+    switch (prec) {
+      case 0: return make_ops<2, 0>();
+      case 1: return make_ops<2, 1>();
+      case 2: return make_ops<2, 2>();
+      default: return make_ops<2, 3>();
+    }
+  }
+  switch (prec) {
+    case 0: return make_ops<3, 0>();
+    case 1: return make_ops<3, 1>();
+    case 2: return make_ops<3, 2>();
+    default: return make_ops<3, 3>();
+  }
+}
+
+size_t sf_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+size_t sg_bytes(int prec) { return prec == 0 ? 8 : 4; }
+size_t r_bytes(int prec) { return prec == 0 ? 8 : 4; }
+int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// one bump allocator over the arena; with base == nullptr it only measures
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base((char *)b) {}
+  template <class T> T *take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
+  const int Q = P.dim == 2 ? 9 : 19, Qg = P.dim == 2 ? 5 : 7;
+  const size_t Np = (size_t)kp.Np;
+  const size_t sf = sf_bytes(P.precision), sg = sg_bytes(P.precision), rb = r_bytes(P.precision);
+  for (int b = 0; b < 2; b++) d.f[b] = cv.take<void>(Q * Np * sf);
+  for (int b = 0; b < 2; b++) d.g[b] = cv.take<void>(Qg * Np * sg);
+  d.type = cv.take<uint8_t>(Np);
+  d.cflag = cv.take<uint8_t>(Np);
+  void **rarr[] = {&d.M, &d.alpha, &d.rho, &d.ux, &d.uy, &d.uz, &d.kappa, &d.Pi, &d.exc, &d.mx, &d.my, &d.mz, &d.soff};
+  for (void **a : rarr) *a = cv.take<void>(Np * rb);
+  d.label = cv.take<int32_t>(Np * 4);
+  d.parent = cv.take<int32_t>(Np * 4);
+  d.ilist = cv.take<int32_t>(Np * 4);
+  d.blist = cv.take<int32_t>(Np * 4);
+  d.nilist = cv.take<int32_t>(Np * 4);
+  d.l2ilist = cv.take<int32_t>(Np * 4);
+  d.cnt = cv.take<int32_t>(C_NCOUNT * 4);
+  d.status = cv.take<int32_t>(4);
+  const size_t cap = (size_t)kp.cap;
+  d.bm = cv.take<double>(cap * 8);
+  d.bV = cv.take<double>(cap * 8);
+  d.bp = cv.take<double>(cap * 8);
+  d.balive = cv.take<int32_t>(cap * 4);
+  d.mprime = cv.take<double>(cap * 8);
+  d.alive_prev = cv.take<int32_t>(cap * 4);
+  d.phi = cv.take<long long>(cap * 24);
+  d.gam = cv.take<long long>(cap * 24);
+  d.led = cv.take<long long>(9 * 8);
+  d.ledtot = cv.take<__int128>(3 * 16);
+  d.hkeys = cv.take<unsigned long long>((size_t)kp.H * 8);
+  d.hvals = cv.take<long long>((size_t)kp.H * 24);
+  d.hslot = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.ent_root = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.ent_lab = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.ent_next = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.ent_flag = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.ent_v = cv.take<long long>((size_t)kp.ecap * 24);
+  d.lab_cnt = cv.take<int32_t>(cap * 4);
+  d.lab_first = cv.take<int32_t>(cap * 4);
+  d.lab_assigned = cv.take<int32_t>(cap * 4);
+  d.lab_vtot = cv.take<long long>(cap * 24);
+  d.lab_vatm = cv.take<long long>(cap * 24);
+  d.rh_key = cv.take<int32_t>((size_t)kp.RH * 4);
+  d.rh_head = cv.take<int32_t>((size_t)kp.RH * 4);
+  d.contested = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.scratch_d = cv.take<double>(cap * 8);
+}
+
+int validate(const mf_params *p, std::string &why) {
+  if (!p) { why = "params is NULL"; return MF_EINVAL; }
+  if (p->struct_size != sizeof(mf_params)) { why = "struct_size does not match this library's mf_params"; return MF_EINVAL; }
+  if (p->dim != 2 && p->dim != 3) { why = "dim must be 2 or 3"; return MF_EINVAL; }
+  const int nz = p->dim == 2 ? 1 : p->nz;
+  if (p->nx < 3 || p->ny < 3 || nz < 1 || (p->dim == 3 && nz < 3)) { why = "grid too small"; return MF_EINVAL; }
+  if ((double)p->nx * p->ny * nz >= 2147483647.0) { why = "grid exceeds 2^31 cells"; return MF_EINVAL; }
+  if (p->precision < 0 || p->precision > 3) { why = "unknown precision"; return MF_EINVAL; }
+  if (p->rheology != MF_NEWTONIAN && p->rheology != MF_POWER_LAW) { why = "unknown rheology"; return MF_EINVAL; }
+  if (p->curvature != MF_CURV_PLAIN) { why = "learned curvature is not built into this library"; return MF_EUNSUPPORTED; }
+  if (p->max_ids < 2 || p->max_ids > (1 << 24)) { why = "max_ids out of range"; return MF_EINVAL; }
+  if (!(p->tau > 0.5) || !(p->D > 0.0) || !(p->RT > 0.0) || !(p->eps >= 0.0)) { why = "tau > 1/2, D > 0, RT > 0, eps >= 0 required"; return MF_EINVAL; }
+  if (p->k_pi > 0.0 && !(p->d_max >= 1.0)) { why = "d_max >= 1 required with disjoining pressure"; return MF_EINVAL; }
+  if (p->rheology == MF_POWER_LAW && !(p->tau_min > 0.5 && p->tau_max >= p->tau_min && p->pl_nu_ref > 0 && p->pl_gdot_ref > 0)) {
+    why = "power law needs 1/2 < tau_min <= tau_max, nu_ref > 0, gdot_ref > 0";
+    return MF_EINVAL;
+  }
+  return MF_OK;
+}
+
+KP make_kp(const mf_params &P) {
+  KP k;
+  memset(&k, 0, sizeof k);
+  k.dim = P.dim;
+  k.nx = P.nx;
+  k.ny = P.ny;
+  k.nz = P.dim == 2 ? 1 : P.nz;
+  for (int a = 0; a < 3; a++) k.per[a] = P.periodic[a] ? 1 : 0;
+  if (P.dim == 2) k.per[2] = 0;
+  k.N = (int64_t)k.nx * k.ny * k.nz;
+  k.Np = (k.N + 255) & ~(int64_t)255;
+  k.cap = P.max_ids;
+  k.H = next_pow2(4 * P.max_ids < 1024 ? 1024 : 4 * P.max_ids);
+  k.ecap = 2 * P.max_ids < 1024 ? 1024 : 2 * P.max_ids;
+  k.RH = next_pow2(2 * k.ecap);
+  k.rheology = P.rheology;
+  k.cleanup = P.cleanup;
+  k.curvature = P.curvature;
+  const double kg = P.dim == 2 ? 3.0 : 4.0;
+  k.omega = 1.0 / P.tau;
+  k.omega_g = 1.0 / (0.5 + kg * P.D);
+  k.sigma = P.sigma;
+  k.kH = P.kH;
+  k.RT = P.RT;
+  k.k_pi = P.k_pi;
+  k.d_max = P.d_max;
+  k.p_atm = P.p_atm;
+  k.q = P.q;
+  k.eps = P.eps;
+  k.c0 = (P.S0 * P.kH) * P.p_atm;
+  k.pl_n = P.pl_n;
+  k.pl_nu_ref = P.pl_nu_ref;
+  k.pl_gdot_ref = P.pl_gdot_ref;
+  k.tau_min = P.tau_min;
+  k.tau_max = P.tau_max;
+  return k;
+}
+
+#define HIPCHK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(_e);                 \
+      return MF_EHIP;                                                                 \
+    }                                                                                 \
+  } while (0)
+
+__global__ void k_reset_counters(DA d) {
+  const int t = threadIdx.x;
+  if (t < C_NEXTID) d.cnt[t] = 0;
+}
+
+__global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+int device_status(Ctx *c) {
+  int32_t st = 0;
+  HIPCHK(c, hipMemcpyAsync(&st, c->d.status, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (st == 0) return MF_OK;
+  c->err = "device status:";
+  if (st & ST_INVARIANT) c->err += " liquid cell next to gas / gas neighbour with another bubble id;";
+  if (st & ST_TABLE) c->err += " bubble or labelling table capacity exceeded;";
+  if (st & ST_NONFINITE) c->err += " non-positive or non-finite density;";
+  if (st & ST_BADLABEL) c->err += " interface cell with an invalid bubble id;";
+  return (st & ST_TABLE) ? MF_ECAPACITY : MF_ENUMERIC;
+}
+
+void reset_counters(Ctx *c) { hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, c->d); }
+
+// per-step event pairs when profiling
+struct Prof {
+  std::vector<hipEvent_t> ev;  // 4 per step: step start, sweep start, sweep end, step end
+  size_t used = 0;
+};
+
+}  // namespace
+
+struct mf_ctx : Ctx {
+  OpsTable ops;
+  Prof prof_ev;
+};
+
+extern "C" {
+
+int mf_abi_version(void) { return MF_ABI_VERSION; }
+
+const char *mf_last_error(const mf_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int mf_workspace_bytes(const mf_params *p, size_t *bytes) {
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) { g_err = why; return rc; }
+  if (!bytes) { g_err = "bytes is NULL"; return MF_EINVAL; }
+  KP kp = make_kp(*p);
+  DA d;
+  Carve cv(nullptr);
+  layout(*p, kp, cv, d);
+  *bytes = cv.off + 256;
+  return MF_OK;
+}
+
+int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *stream, mf_ctx **out) {
+  std::string why;
+  if (!out) { g_err = "out is NULL"; return MF_EINVAL; }
+  *out = nullptr;
+  int rc = validate(p, why);
+  if (rc) { g_err = why; return rc; }
+  size_t need = 0;
+  mf_workspace_bytes(p, &need);
+  mf_ctx *c = new (std::nothrow) mf_ctx();
+  if (!c) { g_err = "host allocation failed"; return MF_ENOMEM; }
+  c->P = *p;
+  c->kp = make_kp(*p);
+  c->stream = (hipStream_t)stream;
+  c->ops = ops_for(p->dim, p->precision);
+  if (dev_workspace) {
+    if (ws_bytes < need) {
+      g_err = "workspace smaller than mf_workspace_bytes";
+      delete c;
+      return MF_ENOMEM;
+    }
+    c->ws = dev_workspace;
+  } else {
+    hipError_t e = hipMalloc(&c->ws, need);
+    if (e != hipSuccess) {
+      g_err = std::string("hipMalloc of the workspace failed: ") + hipGetErrorString(e);
+      delete c;
+      return MF_ENOMEM;
+    }
+    c->own_ws = true;
+  }
+  c->ws_bytes = need;
+  char *base = (char *)(((uintptr_t)c->ws + 255) & ~(uintptr_t)255);
+  Carve cv(base);
+  layout(*p, c->kp, cv, c->d);
+  // zero everything, then the "empty" markers of the hash tables
+  {
+    size_t n = cv.off;
+    unsigned nb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_bytes, dim3(nb), dim3(256), 0, c->stream, (uint8_t *)base, n, (uint8_t)0);
+    hipLaunchKernelGGL(k_fill_bytes, dim3(64), dim3(256), 0, c->stream, (uint8_t *)c->d.hkeys, (size_t)c->kp.H * 8, (uint8_t)0xFF);
+    hipLaunchKernelGGL(k_fill_bytes, dim3(64), dim3(256), 0, c->stream, (uint8_t *)c->d.rh_key, (size_t)c->kp.RH * 4, (uint8_t)0xFF);
+    hipLaunchKernelGGL(k_fill_bytes, dim3(64), dim3(256), 0, c->stream, (uint8_t *)c->d.rh_head, (size_t)c->kp.RH * 4, (uint8_t)0xFF);
+  }
+  c->ops.init_box(*c, c->stream);
+  // atmosphere entry and the id counter
+  {
+    const double patm = p->p_atm;
+    const int32_t one = 1;
+    const int32_t next = 1;
+    hipError_t e1 = hipMemcpyAsync(c->d.bp, &patm, 8, hipMemcpyHostToDevice, c->stream);
+    hipError_t e2 = hipMemcpyAsync(c->d.balive, &one, 4, hipMemcpyHostToDevice, c->stream);
+    hipError_t e3 = hipMemcpyAsync(c->d.cnt + C_NEXTID, &next, 4, hipMemcpyHostToDevice, c->stream);
+    hipError_t e4 = hipStreamSynchronize(c->stream);
+    hipError_t e5 = hipGetLastError();
+    if (e1 || e2 || e3 || e4 || e5) {
+      g_err = std::string("initialisation failed: ") + hipGetErrorString(e4 ? e4 : (e5 ? e5 : e1));
+      if (c->own_ws) (void)hipFree(c->ws);
+      delete c;
+      return MF_EHIP;
+    }
+  }
+  // the headspace-only state needs its lists and geometry too
+  reset_counters(c);
+  c->ops.build_lists(*c, c->stream);
+  c->ops.geometry(*c, c->stream);
+  *out = c;
+  return MF_OK;
+}
+
+int mf_destroy(mf_ctx *c) {
+  if (!c) return MF_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->prof_ev.ev) (void)hipEventDestroy(e);
+  if (c->own_ws) (void)hipFree(c->ws);
+  delete c;
+  return MF_OK;
+}
+
+int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii, const double *p0) {
+  if (!c) return MF_EINVAL;
+  if (c->nucleated || c->stepped) { c->err = "mf_nucleate is valid once, before mf_step"; return MF_ESTATE; }
+  if (n < 0 || (n > 0 && (!centers || !radii || !p0))) { c->err = "bad nucleus arrays"; return MF_EINVAL; }
+  if (n + 1 > c->kp.cap) { c->err = "more nuclei than the bubble table holds"; return MF_ECAPACITY; }
+  const int D = c->kp.dim;
+  for (int k = 0; k < n; k++) {
+    const double cc[3] = {centers[3 * k], centers[3 * k + 1], D == 3 ? centers[3 * k + 2] : 0.0};
+    const int dims[3] = {c->kp.nx, c->kp.ny, c->kp.nz};
+    if (!(radii[k] > 0.0) || !(p0[k] > 0.0)) { c->err = "nucleus radius and pressure must be positive"; return MF_EINVAL; }
+    for (int a = 0; a < D; a++)
+      if (!(cc[a] - radii[k] >= 1.0) || !(cc[a] + radii[k] <= dims[a] - 2.0)) {
+        c->err = "nucleus " + std::to_string(k) + " is not inside the closed domain";
+        return MF_EINVAL;
+      }
+  }
+  c->ops.nucleate(*c, c->stream, n, centers, radii);
+  std::vector<int32_t> alive(n + 1, 1);
+  double *p0d = nullptr;
+  HIPCHK(c, hipMalloc(&p0d, sizeof(double) * (n > 0 ? n : 1)));
+  HIPCHK(c, hipMemcpyAsync(c->d.balive, alive.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
+  const int32_t next = n + 1;
+  HIPCHK(c, hipMemcpyAsync(c->d.cnt + C_NEXTID, &next, 4, hipMemcpyHostToDevice, c->stream));
+  if (n > 0) HIPCHK(c, hipMemcpyAsync(p0d, p0, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  reset_counters(c);
+  c->ops.build_lists(*c, c->stream);
+  c->ops.label(*c, c->stream, 0);
+  launch_init_mass(*c, c->stream, p0d, n);
+  c->ops.geometry(*c, c->stream);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  (void)hipFree(p0d);
+  HIPCHK(c, hipGetLastError());
+  c->nucleated = true;
+  return device_status(c);
+}
+
+int mf_step(mf_ctx *c, int32_t nsteps) {
+  if (!c) return MF_EINVAL;
+  if (nsteps < 0) { c->err = "nsteps < 0"; return MF_EINVAL; }
+  for (int k = 0; k < nsteps; k++) {
+    hipEvent_t *ev = nullptr;
+    if (c->prof) {
+      if (c->prof_ev.used + 4 > c->prof_ev.ev.size()) {
+        c->err = "profiling event pool exhausted; call mf_profile_get";
+        return MF_ESTATE;
+      }
+      ev = &c->prof_ev.ev[c->prof_ev.used];
+      c->prof_ev.used += 4;
+      (void)hipEventRecord(ev[0], c->stream);
+    }
+    reset_counters(c);
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    c->ops.sweep(*c, c->stream);
+    if (ev) (void)hipEventRecord(ev[2], c->stream);
+    c->cur ^= 1;
+    c->ops.convert(*c, c->stream);
+    c->ops.label(*c, c->stream, 1);
+    c->ops.geometry(*c, c->stream);
+    if (ev) (void)hipEventRecord(ev[3], c->stream);
+    c->step++;
+  }
+  c->stepped = c->stepped || nsteps > 0;
+  HIPCHK(c, hipGetLastError());
+  return MF_OK;
+}
+
+int mf_sync(mf_ctx *c) {
+  if (!c) return MF_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return device_status(c);
+}
+
+static size_t field_bytes(const mf_ctx *c, int field) {
+  const size_t N = (size_t)c->kp.N;
+  const int Q = c->kp.dim == 2 ? 9 : 19, Qg = c->kp.dim == 2 ? 5 : 7;
+  switch (field) {
+    case MF_FIELD_TYPE: return N;
+    case MF_FIELD_LABEL: return N * 4;
+    case MF_FIELD_F: return N * 8 * Q;
+    case MF_FIELD_G: return N * 8 * Qg;
+    default: return field >= 0 && field <= MF_FIELD_G ? N * 8 : 0;
+  }
+}
+
+int mf_read_field(mf_ctx *c, int32_t field, void *dst, size_t dst_bytes, int32_t dst_on_device) {
+  if (!c || !dst) return MF_EINVAL;
+  const size_t need = field_bytes(c, field);
+  if (!need) { c->err = "unknown field"; return MF_EINVAL; }
+  if (dst_bytes < need) { c->err = "destination too small"; return MF_EINVAL; }
+  void *stage = nullptr;
+  HIPCHK(c, hipMalloc(&stage, need));
+  c->ops.read_field(*c, c->stream, field, (double *)stage);
+  hipError_t e = hipMemcpyAsync(dst, stage, need, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(stage);
+  HIPCHK(c, e);
+  HIPCHK(c, e2);
+  HIPCHK(c, hipGetLastError());
+  return MF_OK;
+}
+
+int mf_write_field(mf_ctx *c, int32_t field, const void *src, size_t src_bytes) {
+  if (!c || !src) return MF_EINVAL;
+  if (c->stepped) { c->err = "mf_write_field is valid before the first mf_step"; return MF_ESTATE; }
+  const size_t need = field_bytes(c, field);
+  if (!need || field == MF_FIELD_CONC) { c->err = "field cannot be written"; return MF_EINVAL; }
+  if (src_bytes < need) { c->err = "source too small"; return MF_EINVAL; }
+  void *stage = nullptr;
+  HIPCHK(c, hipMalloc(&stage, need));
+  hipError_t e = hipMemcpyAsync(stage, src, need, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) c->ops.write_field(*c, c->stream, field, (const double *)stage);
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(stage);
+  HIPCHK(c, e);
+  HIPCHK(c, e2);
+  HIPCHK(c, hipGetLastError());
+  c->nucleated = true;
+  return MF_OK;
+}
+
+int mf_set_bubble(mf_ctx *c, int32_t id, double gas_mass, double volume, double pressure, int32_t alive) {
+  if (!c) return MF_EINVAL;
+  if (id < 0 || id >= c->kp.cap) { c->err = "id out of range"; return MF_EINVAL; }
+  const int32_t al = alive ? 1 : 0;
+  HIPCHK(c, hipMemcpyAsync(c->d.bm + id, &gas_mass, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d.bV + id, &volume, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d.bp + id, &pressure, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d.balive + id, &al, 4, hipMemcpyHostToDevice, c->stream));
+  int32_t next = 0;
+  HIPCHK(c, hipMemcpyAsync(&next, c->d.cnt + C_NEXTID, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (id + 1 > next) {
+    next = id + 1;
+    HIPCHK(c, hipMemcpyAsync(c->d.cnt + C_NEXTID, &next, 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return MF_OK;
+}
+
+int mf_refresh(mf_ctx *c, int32_t relabel) {
+  if (!c) return MF_EINVAL;
+  reset_counters(c);
+  c->ops.build_lists(*c, c->stream);
+  if (relabel) c->ops.label(*c, c->stream, 0);
+  c->ops.geometry(*c, c->stream);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return device_status(c);
+}
+
+int mf_read_bubbles(mf_ctx *c, mf_bubble *dst, int32_t capacity, int32_t *n_out) {
+  if (!c) return MF_EINVAL;
+  const int cap = c->kp.cap;
+  std::vector<double> m(cap), V(cap), p(cap);
+  std::vector<int32_t> al(cap);
+  HIPCHK(c, hipMemcpyAsync(m.data(), c->d.bm, 8 * cap, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(V.data(), c->d.bV, 8 * cap, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(p.data(), c->d.bp, 8 * cap, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(al.data(), c->d.balive, 4 * cap, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int k = 0;
+  for (int i = 1; i < cap; i++) {
+    if (!al[i]) continue;
+    if (dst && k < capacity) {
+      dst[k].id = i;
+      dst[k].alive = 1;
+      dst[k].volume = V[i];
+      dst[k].gas_mass = m[i];
+      dst[k].pressure = p[i];
+    }
+    k++;
+  }
+  if (n_out) *n_out = k;
+  return MF_OK;
+}
+
+int mf_totals_get(mf_ctx *c, mf_totals *out) {
+  if (!c || !out) return MF_EINVAL;
+  __int128 led[3];
+  int32_t cnt[C_NCOUNT], st = 0;
+  std::vector<int32_t> al(c->kp.cap);
+  HIPCHK(c, hipMemcpyAsync(led, c->d.ledtot, sizeof led, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&st, c->d.status, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(al.data(), c->d.balive, 4 * c->kp.cap, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->step = c->step;
+  out->lost_liquid = (double)led[0] * 0x1p-64;
+  out->atm_gas = (double)led[1] * 0x1p-64;
+  out->collapsed_gas = (double)led[2] * 0x1p-64;
+  out->next_id = cnt[C_NEXTID];
+  int nb = 0;
+  for (int i = 1; i < c->kp.cap; i++) nb += al[i] ? 1 : 0;
+  out->n_bubbles = nb;
+  out->n_interface = cnt[C_I];
+  out->status = st;
+  return MF_OK;
+}
+
+int mf_profile_enable(mf_ctx *c, int32_t on) {
+  if (!c) return MF_EINVAL;
+  c->prof = on != 0;
+  if (c->prof && c->prof_ev.ev.empty()) {
+    c->prof_ev.ev.resize(4 * 4096);
+    for (auto &e : c->prof_ev.ev) HIPCHK(c, hipEventCreate(&e));
+  }
+  c->prof_ev.used = 0;
+  return MF_OK;
+}
+
+int mf_profile_get(mf_ctx *c, int32_t group, double *ms_total, int64_t *launches) {
+  if (!c || !ms_total || !launches) return MF_EINVAL;
+  if (group != 0 && group != 1) { c->err = "group must be 0 (sweep) or 1 (step)"; return MF_EINVAL; }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  int64_t nl = 0;
+  for (size_t k = 0; k + 4 <= c->prof_ev.used; k += 4) {
+    float ms = 0.0f;
+    hipEvent_t a = group == 0 ? c->prof_ev.ev[k + 1] : c->prof_ev.ev[k];
+    hipEvent_t b = group == 0 ? c->prof_ev.ev[k + 2] : c->prof_ev.ev[k + 3];
+    HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+    tot += ms;
+    nl++;
+  }
+  *ms_total = tot;
+  *launches = nl;
+  return MF_OK;
+}
+
+}  // extern "C"

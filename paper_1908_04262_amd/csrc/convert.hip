@@ -1,0 +1,289 @@
+// Cell-type conversion and excess-mass redistribution (Sec. 2.1, last paragraph):
+// interface cells with alpha >= 1 become liquid, with alpha <= 0 become gas; the
+// surplus or shortage is spread equally over the neighbouring interface cells.
+// All passes run over compact lists (interface cells of the step, and the cells that
+// change type) and are pull gathers or idempotent flag scatters, so their result does
+// not depend on thread order.
+#include "lbm_math.h"
+
+namespace mf {
+
+// (a) every gas neighbour of a filled cell becomes a new interface cell; an emptied
+// neighbour of a filled cell stays an interface cell
+template <int D>
+__global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
+  using L = Lat<D>;
+  LIST_LOOP(k, d.cnt + C_I) {
+    bool act = false;
+    int64_t n = 0;
+    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
+      n = d.ilist[k];
+      act = (d.cflag[n] & CF_FILL) != 0;
+    }
+    if (act) {
+      int x, y, z;
+      cell_xyz(p, n, x, y, z);
+      for (int i = 1; i < L::Q; ++i) {
+        const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+        const int ty = d.type[yy] & TMASK;
+        if (ty == TG) {
+          const uint32_t old = flag_or(d.cflag, yy, CF_NEWI);
+          if (!(old & CF_NEWI)) {
+            const int slot = atomicAdd(d.cnt + C_NI, 1);
+            d.nilist[slot] = (int32_t)yy;
+          }
+        } else if (ty == TI) {
+          if (d.cflag[yy] & CF_EMPTY) flag_clear(d.cflag, yy, CF_EMPTY);
+        }
+      }
+    }
+  }
+}
+
+// (b) every liquid neighbour of a (still) emptied cell becomes an interface cell and
+// takes the smallest bubble id among its emptied neighbours
+template <int D>
+__global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
+  using L = Lat<D>;
+  LIST_LOOP(k, d.cnt + C_I) {
+    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
+      const int64_t n = d.ilist[k];
+      if (d.cflag[n] & CF_EMPTY) {
+        int x, y, z;
+        cell_xyz(p, n, x, y, z);
+        const int32_t lab = d.label[n];
+        for (int i = 1; i < L::Q; ++i) {
+          const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+          if ((d.type[yy] & TMASK) == TL) {
+            atomicMin((unsigned int *)&d.label[yy], (unsigned int)lab);
+            const uint32_t old = flag_or(d.cflag, yy, CF_L2I);
+            if (!(old & CF_L2I)) {
+              const int slot = atomicAdd(d.cnt + C_L2I, 1);
+              d.l2ilist[slot] = (int32_t)yy;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// liquid cells turned interface: M = rho, with rho and u the moments of their
+// post-collision populations
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_l2i_init(KP p, DA d, int cur) {
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  using L = Lat<D>;
+  const SF *f = (const SF *)d.f[cur];
+  LIST_LOOP(k, d.cnt + C_L2I) {
+    if (k < *(volatile int32_t *)(d.cnt + C_L2I)) {
+      const int64_t n = d.l2ilist[k];
+      R fv[L::Q];
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) fv[i] = FCodec<P, D>::dec(f[(int64_t)i * p.Np + n], i);
+      R r, ux, uy, uz;
+      moments<D, R>(fv, r, ux, uy, uz);
+      ((R *)d.rho)[n] = r;
+      ((R *)d.ux)[n] = ux;
+      ((R *)d.uy)[n] = uy;
+      if (D == 3) ((R *)d.uz)[n] = uz;
+      ((R *)d.M)[n] = r;
+    }
+  }
+}
+
+// (c) apply the new types; (e) an emptied cell hands its dissolved gas to its bubble
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
+  using SG = typename Prec<P>::SG;
+  using R = typename Prec<P>::R;
+  using L = Lat<D>;
+  const SG *g = (const SG *)d.g[cur];
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
+  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nNI + nL;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
+       k += (int64_t)gridDim.x * blockDim.x) {
+    bool emptied = false;
+    int32_t lab = 0;
+    R sg = R(0);
+    if (k < nI) {
+      const int64_t n = d.ilist[k];
+      const uint8_t cl = d.cflag[n];
+      if (cl & CF_FILL) {
+        d.type[n] = (d.type[n] & ~TMASK) | TL;
+        d.label[n] = NOLAB;
+      } else if (cl & CF_EMPTY) {
+        d.type[n] = (d.type[n] & ~TMASK) | TG;
+        emptied = true;
+        lab = d.label[n];
+#pragma unroll
+        for (int i = 0; i < L::Qg; ++i) sg = sg + g[(int64_t)i * p.Np + n];
+      }
+    } else if (k < total) {
+      const int64_t n = k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI];
+      d.type[n] = (d.type[n] & ~TMASK) | TI;
+    }
+    wave_fx_add(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg));
+  }
+}
+
+// (d) a new interface cell from gas takes the mean density and velocity of its liquid
+// and old-interface neighbours (moments of their post-collision populations), the
+// equilibrium populations of that state, M = 0, and dissolved gas at the Henry value of
+// its bubble, which the bubble gives up
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  using SG = typename Prec<P>::SG;
+  using L = Lat<D>;
+  SF *f = (SF *)d.f[cur];
+  SG *g = (SG *)d.g[cur];
+  LIST_LOOP(k, d.cnt + C_NI) {
+    bool act = false;
+    int32_t lab = 0;
+    R sg = R(0);
+    if (k < *(volatile int32_t *)(d.cnt + C_NI)) {
+      act = true;
+      const int64_t n = d.nilist[k];
+      int x, y, z;
+      cell_xyz(p, n, x, y, z);
+      R sr = R(0), sx = R(0), sy = R(0), sz = R(0);
+      int cnt = 0;
+      for (int i = 1; i < L::Q; ++i) {
+        const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+        const int ty = d.type[yy] & TMASK;
+        if ((ty != TL && ty != TI) || (d.cflag[yy] & CF_NEWI)) continue;
+        R fv[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) fv[q] = FCodec<P, D>::dec(f[(int64_t)q * p.Np + yy], q);
+        R r, a, b, c;
+        moments<D, R>(fv, r, a, b, c);
+        sr = sr + r;
+        sx = sx + a;
+        sy = sy + b;
+        sz = sz + c;
+        cnt++;
+      }
+      R rb = R(1), ubx = R(0), uby = R(0), ubz = R(0);
+      if (cnt > 0) {
+        rb = sr / R(cnt);
+        ubx = sx / R(cnt);
+        uby = sy / R(cnt);
+        ubz = sz / R(cnt);
+      }
+      const R uu = usq<D, R>(ubx, uby, ubz);
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i)
+        f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc(feq<D, R>(i, rb, ubx, uby, ubz, uu), i);
+      lab = d.label[n];
+      double pb = p.p_atm;
+      if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
+      else raise_status(d.status, ST_BADLABEL);
+      const R cH = R(p.kH) * R(pb);
+#pragma unroll
+      for (int i = 0; i < L::Qg; ++i) {
+        const R gv = geq<D, R>(i, cH, ubx, uby, ubz);
+        g[(int64_t)i * p.Np + n] = gv;
+        sg = sg + gv;
+      }
+      ((R *)d.rho)[n] = rb;
+      ((R *)d.ux)[n] = ubx;
+      ((R *)d.uy)[n] = uby;
+      if (D == 3) ((R *)d.uz)[n] = ubz;
+      ((R *)d.M)[n] = R(0);
+    }
+    wave_fx_add(d.gam, act && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg));
+  }
+}
+
+// excess of each converted cell: e = M* - rho (filled) or M* (emptied), split over its
+// interface neighbours under the new types; none -> lost-liquid ledger
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  using L = Lat<D>;
+  LIST_LOOP(k, d.cnt + C_I) {
+    bool lost = false;
+    R e = R(0);
+    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
+      const int64_t n = d.ilist[k];
+      const uint8_t cl = d.cflag[n];
+      if (cl & (CF_FILL | CF_EMPTY)) {
+        const R Ms = ((const R *)d.M)[n];
+        e = (cl & CF_FILL) ? Ms - ((const R *)d.rho)[n] : Ms;
+        int x, y, z;
+        cell_xyz(p, n, x, y, z);
+        int cnt = 0;
+        for (int i = 1; i < L::Q; ++i) {
+          const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+          if ((d.type[yy] & TMASK) == TI) cnt++;
+        }
+        if (cnt > 0) ((R *)d.exc)[n] = e / R(cnt);
+        else lost = true;
+      }
+    }
+    wave_fx_add(d.led, lost, 0, fx3((double)e));
+  }
+}
+
+// every interface cell of the new types gathers the shares of its converted
+// neighbours in ascending direction order; alpha = M / rho
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  using L = Lat<D>;
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
+  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nNI + nL;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
+    if (k < nI && (d.cflag[n] & (CF_FILL | CF_EMPTY))) continue;
+    int x, y, z;
+    cell_xyz(p, n, x, y, z);
+    R acc = ((const R *)d.M)[n];
+    for (int i = 1; i < L::Q; ++i) {
+      const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+      if (d.cflag[yy] & (CF_FILL | CF_EMPTY)) acc = acc + ((const R *)d.exc)[yy];
+    }
+    ((R *)d.M)[n] = acc;
+    ((R *)d.alpha)[n] = acc / ((const R *)d.rho)[n];
+  }
+}
+
+// conversion flags are cleared once the new state is complete
+__global__ __launch_bounds__(256) void k_clear_conv_flags(DA d) {
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
+  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nNI + nL;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
+    d.cflag[n] = 0;
+  }
+}
+
+template <int D, int P>
+void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
+  const unsigned nb = list_blocks(c);
+  const int cur = c.cur;  // buffer holding this step's post-collision populations
+  hipLaunchKernelGGL((k_fill_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_empty_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_l2i_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_apply<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_ni_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_clear_conv_flags, dim3(nb), dim3(256), 0, s, c.d);
+}
+
+#define MF_INST(D, P) template void Ops<D, P>::convert(Ctx &, hipStream_t);
+MF_FOR_ALL(MF_INST)
+
+}  // namespace mf

@@ -1,0 +1,104 @@
+// Pointwise lattice Boltzmann arithmetic shared by the library kernels. Every sum and
+// product is written in one fixed order so that the binary64 instantiation reproduces
+// the same roundings wherever the method prescribes the same formula.
+#pragma once
+#include "mf_internal.h"
+
+namespace mf {
+
+// e_i . u with only the non-zero velocity components (two-term sums are exact in
+// either order, so this equals the full three-term dot product up to the sign of zero)
+template <int D, class R>
+__device__ __forceinline__ R edot(int i, R ux, R uy, R uz) {
+  using L = Lat<D>;
+  R acc = R(0);
+  bool any = false;
+  if (L::ex[i] != 0) { acc = L::ex[i] > 0 ? ux : -ux; any = true; }
+  if (L::ey[i] != 0) { R t = L::ey[i] > 0 ? uy : -uy; acc = any ? acc + t : t; any = true; }
+  if (D == 3 && L::ez[i] != 0) { R t = L::ez[i] > 0 ? uz : -uz; acc = any ? acc + t : t; any = true; }
+  return acc;
+}
+
+template <int D, class R>
+__device__ __forceinline__ R usq(R ux, R uy, R uz) {
+  if constexpr (D == 3) return (ux * ux + uy * uy) + uz * uz;
+  else return ux * ux + uy * uy;
+}
+
+// Eq. equilibrium with c_s^2 = 1/3
+template <int D, class R>
+__device__ __forceinline__ R feq(int i, R rho, R ux, R uy, R uz, R uu) {
+  R eu = edot<D, R>(i, ux, uy, uz);
+  return (rho * R(Lat<D>::w[i])) * (((R(1) + R(3) * eu) + (R(4.5) * eu) * eu) - R(1.5) * uu);
+}
+
+// ADE equilibrium (Sec. 3.1): w_i c (1 + e.u / c_s^2)
+template <int D, class R>
+__device__ __forceinline__ R geq(int i, R c, R ux, R uy, R uz) {
+  R eu = edot<D, R>(i, ux, uy, uz);
+  return (R(Lat<D>::wg[i]) * c) * (R(1) + R(Lat<D>::kg) * eu);
+}
+
+// density and velocity of a population vector, sums in ascending direction order
+template <int D, class R>
+__device__ __forceinline__ void moments(const R *f, R &rho, R &ux, R &uy, R &uz) {
+  using L = Lat<D>;
+  R r = f[0], jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) r = r + f[i];
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    if (L::ex[i] == 1) jx = jx + f[i];
+    if (L::ex[i] == -1) jx = jx - f[i];
+  }
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    if (L::ey[i] == 1) jy = jy + f[i];
+    if (L::ey[i] == -1) jy = jy - f[i];
+  }
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      if (L::ez[i] == 1) jz = jz + f[i];
+      if (L::ez[i] == -1) jz = jz - f[i];
+    }
+  }
+  rho = r;
+  ux = jx / r;
+  uy = jy / r;
+  uz = D == 3 ? jz / r : R(0);
+}
+
+__device__ __forceinline__ double dlog(double v) { return log(v); }
+__device__ __forceinline__ float dlog(float v) { return logf(v); }
+__device__ __forceinline__ double dexp(double v) { return exp(v); }
+__device__ __forceinline__ float dexp(float v) { return expf(v); }
+
+// Power-law relaxation time (Eq. tau with the power-law limit of Eq. carreauTau): the
+// root of s = A (s + 1/2)^(1-n), s = tau - 1/2, by four Newton steps on t = ln s from
+// ln(3 nu_ref), clamped to [tau_min, tau_max]; pn = |Pi_neq| (Frobenius norm).
+template <class R>
+__device__ __forceinline__ R powerlaw_tau(const KP &p, R rho, R pn) {
+  R n = R(p.pl_n);
+  R tau;
+  if (!(pn > R(0))) {
+    tau = n < R(1) ? R(p.tau_max) : (n > R(1) ? R(p.tau_min) : R(0.5) + R(3) * R(p.pl_nu_ref));
+  } else {
+    R l3 = dlog(R(3) * R(p.pl_nu_ref));
+    R lnA = l3 + (n - R(1)) * dlog((R(2.1213203435596424) * pn) / (rho * R(p.pl_gdot_ref)));
+    R t = l3;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      R et = dexp(t);
+      R Fv = (t - (R(1) - n) * dlog(et + R(0.5))) - lnA;
+      R dF = R(1) - ((R(1) - n) * et) / (et + R(0.5));
+      t = t - Fv / dF;
+    }
+    tau = R(0.5) + dexp(t);
+  }
+  if (tau < R(p.tau_min)) tau = R(p.tau_min);
+  if (tau > R(p.tau_max)) tau = R(p.tau_max);
+  return tau;
+}
+
+}  // namespace mf

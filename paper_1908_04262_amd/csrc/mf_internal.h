@@ -1,0 +1,294 @@
+// Internal definitions of libmifoam: lattice and storage traits, the device-array
+// bundle, kernel parameters and wave-level helpers. gfx950 only (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mifoam.h"
+
+namespace mf {
+
+// ------------------------------------------------------------------ cell encoding
+// type byte: bits 0-1 cell type (mf_cell_type), bit 2 = static "touches a wall" flag
+constexpr uint8_t TG = 0, TI = 1, TL = 2, TW = 3;
+constexpr uint8_t TMASK = 3, NEARWALL = 4;
+// conversion flag byte (one per cell; zero between steps)
+constexpr uint32_t CF_FILL = 1, CF_EMPTY = 2, CF_NEWI = 4, CF_L2I = 8, CF_ATM = 16,
+                   CF_ATMROOT = 32, CF_VALID = 64;
+constexpr int32_t NOLAB = -1;
+
+// status bits raised by kernels
+constexpr int ST_INVARIANT = 1;   // liquid next to gas, or gas neighbour of another bubble
+constexpr int ST_TABLE = 2;       // bubble table / hash / entry capacity exceeded
+constexpr int ST_NONFINITE = 4;   // non-finite density at an interface cell
+constexpr int ST_BADLABEL = 8;    // interface cell with an invalid bubble id
+
+// counters
+enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_NEXTID, C_NCOUNT = 16 };
+
+// ------------------------------------------------------------------ lattices
+// D2Q9 / D3Q19 velocity sets and weights (Sec. 2); the ADE lattices D2Q5 / D3Q7 are
+// their rest and axis directions with weights giving c_s^2 = 1/3 and 1/4 (Sec. 3.1).
+template <int D> struct Lat;
+template <> struct Lat<2> {
+  static constexpr int Q = 9, Qg = 5;
+  static constexpr int ex[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int ey[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+  static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                  1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  static constexpr double wg[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+  static constexpr double kg = 3.0;
+};
+template <> struct Lat<3> {
+  static constexpr int Q = 19, Qg = 7;
+  static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr double w[19] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                                   1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  static constexpr double wg[7] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
+  static constexpr double kg = 4.0;
+};
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// ------------------------------------------------------------------ precision
+// P = 0 binary64 throughout; 1 binary32; 2 binary16 offsets f - w; 3 bfloat16 offsets.
+template <int P> struct Prec;
+template <> struct Prec<0> { using R = double; using SF = double; using SG = double; };
+template <> struct Prec<1> { using R = float; using SF = float; using SG = float; };
+template <> struct Prec<2> { using R = float; using SF = _Float16; using SG = float; };
+template <> struct Prec<3> { using R = float; using SF = uint16_t; using SG = float; };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return (uint16_t)(r >> 16);
+}
+
+// population codec: storage value <-> arithmetic value of direction i
+template <int P, int D> struct FCodec {
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  static __device__ __forceinline__ R dec(SF s, int i) {
+    if constexpr (P == 0 || P == 1) return s;
+    else if constexpr (P == 2) return (float)Lat<D>::w[i] + (float)s;
+    else return (float)Lat<D>::w[i] + bf16_to_f32(s);
+  }
+  static __device__ __forceinline__ SF enc(R v, int i) {
+    if constexpr (P == 0 || P == 1) return v;
+    else if constexpr (P == 2) return (_Float16)(v - (float)Lat<D>::w[i]);
+    else return f32_to_bf16(v - (float)Lat<D>::w[i]);
+  }
+};
+
+// ------------------------------------------------------------------ parameters
+struct KP {
+  int dim, nx, ny, nz;
+  int per[3];
+  int64_t N, Np;  // cells, padded plane stride
+  int cap;        // bubble-table capacity
+  int H;          // pair-hash capacity (power of two)
+  int ecap;       // entry capacity of the bubble update
+  int RH;         // root-hash capacity of the bubble update (power of two)
+  int rheology, cleanup, curvature;
+  double omega, omega_g;
+  double sigma, kH, RT, k_pi, d_max, p_atm, q, eps, c0;
+  double pl_n, pl_nu_ref, pl_gdot_ref, tau_min, tau_max;
+};
+
+struct DA {
+  void *f[2], *g[2];
+  uint8_t *type, *cflag;
+  void *M, *alpha, *rho, *ux, *uy, *uz, *kappa, *Pi, *exc, *mx, *my, *mz, *soff;
+  int32_t *label, *parent;
+  int32_t *ilist, *blist, *nilist, *l2ilist;
+  int32_t *cnt;
+  int32_t *status;
+  // bubble table
+  double *bm, *bV, *bp;
+  int32_t *balive;
+  double *mprime;
+  int32_t *alive_prev;
+  long long *phi, *gam;       // per-id step accumulators [cap][3]
+  long long *led;             // per-step ledger accumulators [3][3]: lost, atm, collapsed
+  __int128 *ledtot;           // persistent ledgers [3]
+  // bubble-update scratch
+  unsigned long long *hkeys;  // [H]
+  long long *hvals;           // [H][3]
+  int32_t *hslot;             // used hash slots, in insertion order [ecap]
+  int32_t *ent_root, *ent_lab, *ent_next, *ent_flag; // [ecap]
+  long long *ent_v;           // [ecap][3]
+  int32_t *lab_cnt;           // non-atmosphere components containing each id [cap]
+  int32_t *lab_first;         // smallest non-atmosphere root containing each id [cap]
+  int32_t *lab_assigned;      // [cap]
+  long long *lab_vtot, *lab_vatm; // [cap][3]
+  int32_t *rh_key, *rh_head;  // root hash [2*ecap]
+  int32_t *contested;         // [ecap]
+  double *scratch_d;          // [cap] spare
+};
+
+// ------------------------------------------------------------------ fixed point
+// Order-independent sums: v -> RN(v 2^64) as a signed 128-bit integer, held as three
+// signed 64-bit chunks (low 32 bits, next 32 bits, high part) so that chunk-wise
+// atomic adds never lose a carry.
+struct Fx3 { long long l, m, h; };
+__device__ __host__ __forceinline__ Fx3 fx3(double v) {
+  double s = rint(v * 18446744073709551616.0);
+  double a = s < 0 ? -s : s;
+  double h = floor(a * 0x1p-64);
+  double r = a - h * 18446744073709551616.0;  // exact, in [0, 2^64)
+  double m = floor(r * 0x1p-32);
+  double l = r - m * 4294967296.0;
+  Fx3 o;
+  o.l = (long long)l;
+  o.m = (long long)m;
+  o.h = (long long)h;
+  if (s < 0) { o.l = -o.l; o.m = -o.m; o.h = -o.h; }
+  return o;
+}
+__device__ __host__ __forceinline__ __int128 fx3_join(long long l, long long m, long long h) {
+  return (__int128)h * ((__int128)1 << 64) + (__int128)m * ((__int128)1 << 32) + (__int128)l;
+}
+__device__ __host__ __forceinline__ double fx_to_double(__int128 v) { return (double)v * 0x1p-64; }
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// append value for every lane with pred set; called by the whole wave
+__device__ __forceinline__ void wave_append(int32_t *list, int32_t *counter, bool pred, int32_t value) {
+  unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  int lane = lane_id();
+  int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+  base = __shfl(base, leader);
+  if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
+// add a fixed-point value to acc[key*3 .. +2] for every lane with pred; lanes that share
+// a key are summed inside the wave first. Called by the whole wave.
+__device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, Fx3 v) {
+  unsigned long long act = __ballot(pred);
+  int lane = lane_id();
+  while (act) {
+    int leader = __ffsll((long long)act) - 1;
+    int k = __shfl(key, leader);
+    bool mine = pred && key == k;
+    unsigned long long mm = __ballot(mine);
+    long long sl = mine ? v.l : 0, sm = mine ? v.m : 0, sh = mine ? v.h : 0;
+    for (int off = 32; off > 0; off >>= 1) {
+      sl += __shfl_xor(sl, off);
+      sm += __shfl_xor(sm, off);
+      sh += __shfl_xor(sh, off);
+    }
+    if (lane == leader) {
+      atomicAdd((unsigned long long *)&acc[3 * k + 0], (unsigned long long)sl);
+      atomicAdd((unsigned long long *)&acc[3 * k + 1], (unsigned long long)sm);
+      atomicAdd((unsigned long long *)&acc[3 * k + 2], (unsigned long long)sh);
+    }
+    act &= ~mm;
+    pred = pred && !mine;
+  }
+}
+
+__device__ __forceinline__ void raise_status(int32_t *st, int bits) { atomicOr(st, bits); }
+
+// byte flags through 32-bit atomics on the containing word
+__device__ __forceinline__ uint32_t flag_or(uint8_t *cflag, int64_t n, uint32_t bits) {
+  uint32_t *w = (uint32_t *)(cflag + (n & ~(int64_t)3));
+  int sh = 8 * (int)(n & 3);
+  return (atomicOr(w, bits << sh) >> sh) & 0xFFu;
+}
+__device__ __forceinline__ void flag_clear(uint8_t *cflag, int64_t n, uint32_t bits) {
+  uint32_t *w = (uint32_t *)(cflag + (n & ~(int64_t)3));
+  int sh = 8 * (int)(n & 3);
+  atomicAnd(w, ~(bits << sh));
+}
+
+// ------------------------------------------------------------------ indexing
+// neighbour of cell (x,y,z) at offset (dx,dy,dz) with periodic wrap; closed axes never
+// wrap for non-wall cells because the wall layer bounds them
+__device__ __forceinline__ int64_t nb_index(const KP &p, int x, int y, int z, int dx, int dy, int dz) {
+  int X = x + dx, Y = y + dy, Z = z + dz;
+  if (X < 0) X += p.nx; else if (X >= p.nx) X -= p.nx;
+  if (Y < 0) Y += p.ny; else if (Y >= p.ny) Y -= p.ny;
+  if (Z < 0) Z += p.nz; else if (Z >= p.nz) Z -= p.nz;
+  return (int64_t)X + (int64_t)p.nx * ((int64_t)Y + (int64_t)p.ny * Z);
+}
+// offset that may leave a closed axis (curvature and traversal stencils): -1 outside
+__device__ __forceinline__ int64_t nb_index_or_none(const KP &p, int x, int y, int z, int dx, int dy, int dz) {
+  int X = x + dx, Y = y + dy, Z = z + dz;
+  if (X < 0 || X >= p.nx) { if (!p.per[0]) return -1; X = (X + p.nx) % p.nx; }
+  if (Y < 0 || Y >= p.ny) { if (!p.per[1]) return -1; Y = (Y + p.ny) % p.ny; }
+  if (Z < 0 || Z >= p.nz) { if (p.dim == 2 || !p.per[2]) return -1; Z = (Z + p.nz) % p.nz; }
+  return (int64_t)X + (int64_t)p.nx * ((int64_t)Y + (int64_t)p.ny * Z);
+}
+__device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y, int &z) {
+  x = (int)(n % p.nx);
+  int64_t r = n / p.nx;
+  y = (int)(r % p.ny);
+  z = (int)(r / p.ny);
+}
+
+// grid-stride loop bounds over a device-counted list
+#define LIST_LOOP(idx, countptr)                                                   \
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x,               \
+               _n = (int64_t)(*(volatile int32_t *)(countptr));                    \
+       idx < ((_n + 63) & ~(int64_t)63); idx += (int64_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------------ launchers
+// every kernel family is a template over (D, P); the dispatcher picks one instance
+struct Ctx;
+template <int D, int P> struct Ops {
+  static void sweep(Ctx &c, hipStream_t s);
+  static void convert(Ctx &c, hipStream_t s);
+  static void label(Ctx &c, hipStream_t s, int apply_flux);
+  static void geometry(Ctx &c, hipStream_t s);
+  static void init_box(Ctx &c, hipStream_t s);
+  static void nucleate(Ctx &c, hipStream_t s, int n, const double *centers, const double *radii);
+  static void build_lists(Ctx &c, hipStream_t s);
+  static void read_field(Ctx &c, hipStream_t s, int field, double *dst_dev);
+  static void write_field(Ctx &c, hipStream_t s, int field, const double *src_dev);
+};
+
+struct Ctx {
+  mf_params P;
+  KP kp;
+  DA d;
+  int cur = 0;          // buffer holding the current post-collision populations
+  hipStream_t stream = nullptr;
+  void *ws = nullptr;
+  bool own_ws = false;
+  size_t ws_bytes = 0;
+  bool nucleated = false;
+  bool stepped = false;
+  int64_t step = 0;
+  std::string err;
+  bool prof = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double prof_ms[2] = {0, 0};
+  int64_t prof_n[2] = {0, 0};
+};
+
+// every (dimension, precision) instance the library is built with
+#define MF_FOR_ALL(M) M(2, 0) M(2, 1) M(2, 2) M(2, 3) M(3, 0) M(3, 1) M(3, 2) M(3, 3)
+
+// initial gas content and pressure of the nucleus ids 1..nn (p0 in device memory)
+void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn);
+
+// list-kernel launch size: enough waves to cover the worst case but bounded
+inline unsigned list_blocks(const Ctx &c) {
+  int64_t b = (c.kp.N + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace mf

@@ -1,0 +1,235 @@
+"""Python binding of libmifoam (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of libmifoam.so; this module only
+converts parameter dictionaries to ``mf_params``, hands the library a device
+workspace allocated by PyTorch and the current PyTorch stream, and copies fields back.
+Importing fails loudly when the built library is absent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmifoam.so")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "f16s": 2, "bf16s": 3}
+FIELDS = dict(type=0, label=1, rho=2, ux=3, uy=4, uz=5, alpha=6, mass=7, conc=8,
+              kappa=9, pi=10, f=11, g=12)
+STATUS = {0: "MF_OK", -1: "MF_EINVAL", -2: "MF_ENOMEM", -3: "MF_EHIP", -4: "MF_ECAPACITY",
+          -5: "MF_ENUMERIC", -6: "MF_ESTATE", -7: "MF_EUNSUPPORTED", -8: "MF_EINTERNAL"}
+
+
+class MfParams(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_size_t),
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("periodic", C.c_int32 * 3), ("gas_from", C.c_int32), ("precision", C.c_int32),
+        ("rheology", C.c_int32), ("curvature", C.c_int32), ("cleanup", C.c_int32),
+        ("max_ids", C.c_int32),
+        ("tau", C.c_double), ("D", C.c_double), ("sigma", C.c_double), ("kH", C.c_double),
+        ("RT", C.c_double), ("k_pi", C.c_double), ("d_max", C.c_double),
+        ("p_atm", C.c_double), ("q", C.c_double), ("eps", C.c_double), ("S0", C.c_double),
+        ("pl_n", C.c_double), ("pl_nu_ref", C.c_double), ("pl_gdot_ref", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double),
+    ]
+
+
+class MfBubble(C.Structure):
+    _fields_ = [("id", C.c_int32), ("alive", C.c_int32), ("volume", C.c_double),
+                ("gas_mass", C.c_double), ("pressure", C.c_double)]
+
+
+class MfTotals(C.Structure):
+    _fields_ = [("step", C.c_int64), ("lost_liquid", C.c_double), ("atm_gas", C.c_double),
+                ("collapsed_gas", C.c_double), ("next_id", C.c_int32),
+                ("n_bubbles", C.c_int32), ("n_interface", C.c_int32), ("status", C.c_int32)]
+
+
+# every symbol include/mifoam.h declares
+EXPORTS = ["mf_abi_version", "mf_last_error", "mf_workspace_bytes", "mf_create", "mf_destroy",
+           "mf_nucleate", "mf_step", "mf_sync", "mf_read_field", "mf_write_field",
+           "mf_set_bubble", "mf_refresh", "mf_read_bubbles", "mf_totals_get",
+           "mf_profile_enable", "mf_profile_get"]
+
+_LIB = None
+
+
+def load_library():
+    """Load libmifoam.so from the package directory (built by build.py)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"libmifoam.so is not built ({LIBPATH}); run __graft_entry__.build()")
+    lib = C.CDLL(LIBPATH)
+    vp = C.c_void_p
+    lib.mf_abi_version.restype = C.c_int
+    lib.mf_last_error.restype = C.c_char_p
+    lib.mf_last_error.argtypes = [vp]
+    lib.mf_workspace_bytes.argtypes = [C.POINTER(MfParams), C.POINTER(C.c_size_t)]
+    lib.mf_create.argtypes = [C.POINTER(MfParams), vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.mf_destroy.argtypes = [vp]
+    lib.mf_nucleate.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.mf_step.argtypes = [vp, C.c_int32]
+    lib.mf_sync.argtypes = [vp]
+    lib.mf_read_field.argtypes = [vp, C.c_int32, vp, C.c_size_t, C.c_int32]
+    lib.mf_write_field.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+    lib.mf_set_bubble.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32]
+    lib.mf_refresh.argtypes = [vp, C.c_int32]
+    lib.mf_read_bubbles.argtypes = [vp, C.POINTER(MfBubble), C.c_int32, C.POINTER(C.c_int32)]
+    lib.mf_totals_get.argtypes = [vp, C.POINTER(MfTotals)]
+    lib.mf_profile_enable.argtypes = [vp, C.c_int32]
+    lib.mf_profile_get.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    _LIB = lib
+    return lib
+
+
+def make_params(wl: dict) -> MfParams:
+    p = MfParams()
+    p.struct_size = C.sizeof(MfParams)
+    p.dim = wl["dim"]
+    p.nx, p.ny = wl["nx"], wl["ny"]
+    p.nz = wl["nz"] if wl["dim"] == 3 else 1
+    for a in range(3):
+        p.periodic[a] = int(wl["periodic"][a])
+    p.gas_from = int(wl["gas_from"])
+    p.precision = PRECISIONS[wl["precision"]]
+    p.rheology = 1 if wl["rheology"] == "power_law" else 0
+    p.curvature = 1 if wl.get("curvature") == "mlp" else 0
+    p.cleanup = int(wl["cleanup"])
+    p.max_ids = int(wl["max_ids"])
+    for k in ("tau", "D", "sigma", "kH", "RT", "k_pi", "d_max", "p_atm", "q", "eps", "S0",
+              "pl_n", "pl_nu_ref", "pl_gdot_ref", "tau_min", "tau_max"):
+        setattr(p, k, float(wl[k]))
+    return p
+
+
+class MifoamError(RuntimeError):
+    pass
+
+
+class Sim:
+    """One foaming domain on one GPU (a libmifoam context)."""
+
+    def __init__(self, wl: dict, device: int = 0):
+        import torch
+
+        self.lib = load_library()
+        self.wl = dict(wl)
+        self.params = make_params(wl)
+        self.dim = wl["dim"]
+        self.Q = 9 if self.dim == 2 else 19
+        self.Qg = 5 if self.dim == 2 else 7
+        self.shape = (self.params.nz, self.params.ny, self.params.nx)
+        self.N = int(np.prod(self.shape))
+        self.device = torch.device("cuda", device)
+        nbytes = C.c_size_t()
+        self._check(self.lib.mf_workspace_bytes(C.byref(self.params), C.byref(nbytes)), None)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._check(self.lib.mf_create(C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
+                                       nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self.h = h
+
+    def _check(self, rc, h="self"):
+        if rc != 0:
+            handle = None if h is None else self.h
+            msg = self.lib.mf_last_error(handle)
+            raise MifoamError(f"{STATUS.get(rc, rc)}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nucleate(self, centers, radii, p0):
+        c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        r = np.ascontiguousarray(radii, dtype=np.float64)
+        p = np.ascontiguousarray(p0, dtype=np.float64)
+        self._check(self.lib.mf_nucleate(self.h, len(r), c.ctypes.data, r.ctypes.data, p.ctypes.data))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.mf_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.mf_sync(self.h))
+
+    def read(self, name):
+        fid = FIELDS[name]
+        if name == "type":
+            out = np.empty(self.N, np.uint8)
+        elif name == "label":
+            out = np.empty(self.N, np.int32)
+        elif name == "f":
+            out = np.empty(self.Q * self.N)
+        elif name == "g":
+            out = np.empty(self.Qg * self.N)
+        else:
+            out = np.empty(self.N)
+        self._check(self.lib.mf_read_field(self.h, fid, out.ctypes.data, out.nbytes, 0))
+        if name == "f":
+            return out.reshape((self.Q,) + self.shape)
+        if name == "g":
+            return out.reshape((self.Qg,) + self.shape)
+        return out.reshape(self.shape)
+
+    def write(self, name, arr):
+        dt = {"type": np.uint8, "label": np.int32}.get(name, np.float64)
+        a = np.ascontiguousarray(arr, dtype=dt).ravel()
+        self._check(self.lib.mf_write_field(self.h, FIELDS[name], a.ctypes.data, a.nbytes))
+
+    def set_bubble(self, bid, m, V, p, alive=True):
+        self._check(self.lib.mf_set_bubble(self.h, bid, m, V, p, int(alive)))
+
+    def refresh(self, relabel=False):
+        self._check(self.lib.mf_refresh(self.h, int(relabel)))
+
+    def bubbles(self):
+        cap = self.params.max_ids
+        arr = (MfBubble * cap)()
+        n = C.c_int32()
+        self._check(self.lib.mf_read_bubbles(self.h, arr, cap, C.byref(n)))
+        k = min(n.value, cap)
+        return dict(id=np.array([arr[i].id for i in range(k)], np.int32),
+                    m=np.array([arr[i].gas_mass for i in range(k)]),
+                    V=np.array([arr[i].volume for i in range(k)]),
+                    p=np.array([arr[i].pressure for i in range(k)]))
+
+    def ledgers(self):
+        t = MfTotals()
+        self._check(self.lib.mf_totals_get(self.h, C.byref(t)))
+        return dict(lost_liquid=t.lost_liquid, atm_gas=t.atm_gas, collapsed_gas=t.collapsed_gas,
+                    next_id=t.next_id, step=t.step, n_bubbles=t.n_bubbles,
+                    n_interface=t.n_interface, status=t.status)
+
+    def profile(self, on=True):
+        self._check(self.lib.mf_profile_enable(self.h, int(on)))
+
+    def profile_get(self, group):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.mf_profile_get(self.h, int(group), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def totals(self):
+        """Liquid mass (rho over liquid cells plus M over interface cells), dissolved and
+        bubble gas, and the ledgers."""
+        T = self.read("type")
+        f = self.read("f")
+        M = self.read("mass")
+        liquid = f.sum(axis=0)[T == 2].sum() + M[T == 1].sum()
+        conc = self.read("conc")
+        dissolved = conc[(T == 2) | (T == 1)].sum()
+        b = self.bubbles()
+        led = self.ledgers()
+        return dict(liquid=liquid, dissolved=dissolved, bubble_gas=b["m"].sum(), **led)
