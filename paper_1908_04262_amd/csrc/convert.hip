@@ -82,8 +82,8 @@ __global__ __launch_bounds__(256) void k_l2i_init(KP p, DA d, int cur) {
       R fv[L::Q];
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) fv[i] = FCodec<P, D>::dec(f[(int64_t)i * p.Np + n], i);
-      R r, ux, uy, uz;
-      moments<D, R>(fv, r, ux, uy, uz);
+      R r, dr, ux, uy, uz;
+      Arith<D, P>::mom(fv, r, dr, ux, uy, uz);
       ((R *)d.rho)[n] = r;
       ((R *)d.ux)[n] = ux;
       ((R *)d.uy)[n] = uy;
@@ -119,8 +119,10 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
         d.type[n] = (d.type[n] & ~TMASK) | TG;
         emptied = true;
         lab = d.label[n];
+        R gv[L::Qg], dc;
 #pragma unroll
-        for (int i = 0; i < L::Qg; ++i) sg = sg + g[(int64_t)i * p.Np + n];
+        for (int i = 0; i < L::Qg; ++i) gv[i] = g[(int64_t)i * p.Np + n];
+        sg = Arith<D, P>::conc(gv, R(p.c0), dc);
       }
     } else if (k < total) {
       const int64_t n = k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI];
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
       const int64_t n = d.nilist[k];
       int x, y, z;
       cell_xyz(p, n, x, y, z);
-      R sr = R(0), sx = R(0), sy = R(0), sz = R(0);
+      R sr = R(0), sdr = R(0), sx = R(0), sy = R(0), sz = R(0);
       int cnt = 0;
       for (int i = 1; i < L::Q; ++i) {
         const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
@@ -160,17 +162,22 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
         R fv[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) fv[q] = FCodec<P, D>::dec(f[(int64_t)q * p.Np + yy], q);
-        R r, a, b, c;
-        moments<D, R>(fv, r, a, b, c);
+        R r, dr, a, b, c;
+        Arith<D, P>::mom(fv, r, dr, a, b, c);
         sr = sr + r;
+        sdr = sdr + dr;
         sx = sx + a;
         sy = sy + b;
         sz = sz + c;
         cnt++;
       }
-      R rb = R(1), ubx = R(0), uby = R(0), ubz = R(0);
+      R rb = R(1), drb = R(0), ubx = R(0), uby = R(0), ubz = R(0);
       if (cnt > 0) {
         rb = sr / R(cnt);
+        if constexpr (P != 0) {
+          drb = sdr / R(cnt);
+          rb = R(1) + drb;
+        }
         ubx = sx / R(cnt);
         uby = sy / R(cnt);
         ubz = sz / R(cnt);
@@ -178,18 +185,19 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
       const R uu = usq<D, R>(ubx, uby, ubz);
 #pragma unroll
       for (int i = 0; i < L::Q; ++i)
-        f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc(feq<D, R>(i, rb, ubx, uby, ubz, uu), i);
+        f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc(Arith<D, P>::eq(i, rb, drb, ubx, uby, ubz, uu), i);
       lab = d.label[n];
       double pb = p.p_atm;
       if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
       else raise_status(d.status, ST_BADLABEL);
       const R cH = R(p.kH) * R(pb);
+      R gv[L::Qg], dcz;
 #pragma unroll
       for (int i = 0; i < L::Qg; ++i) {
-        const R gv = geq<D, R>(i, cH, ubx, uby, ubz);
-        g[(int64_t)i * p.Np + n] = gv;
-        sg = sg + gv;
+        gv[i] = Arith<D, P>::geqv(i, cH, cH - R(p.c0), ubx, uby, ubz);
+        g[(int64_t)i * p.Np + n] = gv[i];
       }
+      sg = Arith<D, P>::conc(gv, R(p.c0), dcz);
       ((R *)d.rho)[n] = rb;
       ((R *)d.ux)[n] = ubx;
       ((R *)d.uy)[n] = uby;

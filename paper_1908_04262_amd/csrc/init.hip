@@ -29,12 +29,13 @@ __global__ __launch_bounds__(256) void k_init_box(KP p, DA d, int gas_from) {
     for (int b = 0; b < 2; b++) {
       SF *f = (SF *)d.f[b];
       SG *g = (SG *)d.g[b];
+      // rest state: f = w_i, g = w_i c0 (zero offsets in the shifted instances)
 #pragma unroll
       for (int i = 0; i < L::Q; ++i)
-        f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc(t == TW ? R(0) : R(L::w[i]), i);
+        f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc((t == TW || P != 0) ? R(0) : R(L::w[i]), i);
 #pragma unroll
       for (int i = 0; i < L::Qg; ++i)
-        g[(int64_t)i * p.Np + n] = t == TW ? R(0) : R(L::wg[i] * p.c0);
+        g[(int64_t)i * p.Np + n] = (t == TW || P != 0) ? R(0) : R(L::wg[i] * p.c0);
     }
     const R one = t == TL ? R(1) : R(0);
     ((R *)d.alpha)[n] = one;
@@ -224,21 +225,24 @@ __global__ __launch_bounds__(256) void k_read(KP p, DA d, int cur, int field, do
       case MF_FIELD_ALPHA: out[n] = t == TI ? (double)((const R *)d.alpha)[n] : (t == TL ? 1.0 : 0.0); break;
       case MF_FIELD_MASS: out[n] = t == TI ? (double)((const R *)d.M)[n] : (t == TL ? 1.0 : 0.0); break;
       case MF_FIELD_CONC: {
-        R c = R(0);
+        double c = 0.0;
         if (t == TL || t == TI) {
-          c = g[n];
-          for (int i = 1; i < L::Qg; ++i) c = c + g[(int64_t)i * p.Np + n];
+          R gv[L::Qg], dc;
+          for (int i = 0; i < L::Qg; ++i) gv[i] = g[(int64_t)i * p.Np + n];
+          c = (double)Arith<D, P>::conc(gv, R(p.c0), dc);
+          if (P != 0) c = p.c0 + (double)dc;
         }
-        out[n] = (double)c;
+        out[n] = c;
         break;
       }
       case MF_FIELD_KAPPA: out[n] = t == TI ? (double)((const R *)d.kappa)[n] : 0.0; break;
       case MF_FIELD_PI: out[n] = t == TI ? (double)((const R *)d.Pi)[n] : 0.0; break;
       case MF_FIELD_F:
-        for (int i = 0; i < L::Q; ++i) out[(int64_t)i * p.N + n] = (double)FCodec<P, D>::dec(f[(int64_t)i * p.Np + n], i);
+        for (int i = 0; i < L::Q; ++i) out[(int64_t)i * p.N + n] = FCodec<P, D>::full(f[(int64_t)i * p.Np + n], i);
         break;
       case MF_FIELD_G:
-        for (int i = 0; i < L::Qg; ++i) out[(int64_t)i * p.N + n] = (double)g[(int64_t)i * p.Np + n];
+        for (int i = 0; i < L::Qg; ++i)
+          out[(int64_t)i * p.N + n] = (double)g[(int64_t)i * p.Np + n] + (P != 0 ? L::wg[i] * p.c0 : 0.0);
         break;
     }
   }
@@ -265,10 +269,11 @@ __global__ __launch_bounds__(256) void k_write(KP p, DA d, int cur, int field, c
       case MF_FIELD_KAPPA: ((R *)d.kappa)[n] = (R)in[n]; break;
       case MF_FIELD_PI: ((R *)d.Pi)[n] = (R)in[n]; break;
       case MF_FIELD_F:
-        for (int i = 0; i < L::Q; ++i) f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc((R)in[(int64_t)i * p.N + n], i);
+        for (int i = 0; i < L::Q; ++i) f[(int64_t)i * p.Np + n] = FCodec<P, D>::from_full(in[(int64_t)i * p.N + n], i);
         break;
       case MF_FIELD_G:
-        for (int i = 0; i < L::Qg; ++i) g[(int64_t)i * p.Np + n] = (SG)in[(int64_t)i * p.N + n];
+        for (int i = 0; i < L::Qg; ++i)
+          g[(int64_t)i * p.Np + n] = (SG)(in[(int64_t)i * p.N + n] - (P != 0 ? L::wg[i] * p.c0 : 0.0));
         break;
     }
   }

@@ -39,9 +39,9 @@ __device__ __forceinline__ R geq(int i, R c, R ux, R uy, R uz) {
   return (R(Lat<D>::wg[i]) * c) * (R(1) + R(Lat<D>::kg) * eu);
 }
 
-// density and velocity of a population vector, sums in ascending direction order
+// zeroth and first moments of a population vector, sums in ascending direction order
 template <int D, class R>
-__device__ __forceinline__ void moments(const R *f, R &rho, R &ux, R &uy, R &uz) {
+__device__ __forceinline__ void sums(const R *f, R &r_out, R &jx_out, R &jy_out, R &jz_out) {
   using L = Lat<D>;
   R r = f[0], jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
@@ -63,11 +63,71 @@ __device__ __forceinline__ void moments(const R *f, R &rho, R &ux, R &uy, R &uz)
       if (L::ez[i] == -1) jz = jz - f[i];
     }
   }
+  r_out = r;
+  jx_out = jx;
+  jy_out = jy;
+  jz_out = jz;
+}
+
+// density and velocity of a population vector
+template <int D, class R>
+__device__ __forceinline__ void moments(const R *f, R &rho, R &ux, R &uy, R &uz) {
+  R r, jx, jy, jz;
+  sums<D, R>(f, r, jx, jy, jz);
   rho = r;
   ux = jx / r;
   uy = jy / r;
   uz = D == 3 ? jz / r : R(0);
 }
+
+// Equilibria and moments in the register convention of instance P: plain values for
+// P = 0, offsets from the rest state (f - w_i, g - w_i c0) otherwise. drho = rho - 1 and
+// dc = c - c0 are the offsets of density and concentration.
+template <int D, int P> struct Arith {
+  using R = typename Prec<P>::R;
+  static constexpr bool SH = P != 0;
+  static __device__ __forceinline__ R eq(int i, R rho, R drho, R ux, R uy, R uz, R uu) {
+    if constexpr (!SH) {
+      return feq<D, R>(i, rho, ux, uy, uz, uu);
+    } else {
+      const R eu = edot<D, R>(i, ux, uy, uz);
+      const R pol = (R(3) * eu + (R(4.5) * eu) * eu) - R(1.5) * uu;
+      return R(Lat<D>::w[i]) * drho + (rho * R(Lat<D>::w[i])) * pol;
+    }
+  }
+  static __device__ __forceinline__ R geqv(int i, R c, R dc, R ux, R uy, R uz) {
+    if constexpr (!SH) {
+      return geq<D, R>(i, c, ux, uy, uz);
+    } else {
+      const R eu = edot<D, R>(i, ux, uy, uz);
+      return R(Lat<D>::wg[i]) * dc + (R(Lat<D>::wg[i]) * c) * (R(Lat<D>::kg) * eu);
+    }
+  }
+  // density (and its offset) and velocity of a population vector in this convention
+  // (sum w_i = 1 and sum w_i e_i = 0, so on offsets the sums give rho - 1 and rho u)
+  static __device__ __forceinline__ void mom(const R *f, R &rho, R &drho, R &ux, R &uy, R &uz) {
+    if constexpr (!SH) {
+      moments<D, R>(f, rho, ux, uy, uz);
+      drho = rho - R(1);
+    } else {
+      R s, jx, jy, jz;
+      sums<D, R>(f, s, jx, jy, jz);
+      drho = s;
+      rho = R(1) + s;
+      ux = jx / rho;
+      uy = jy / rho;
+      uz = D == 3 ? jz / rho : R(0);
+    }
+  }
+  // concentration of a cell from its ADE populations
+  static __device__ __forceinline__ R conc(const R *g, R c0, R &dc) {
+    R s = g[0];
+#pragma unroll
+    for (int i = 1; i < Lat<D>::Qg; ++i) s = s + g[i];
+    if constexpr (SH) { dc = s; return c0 + s; }
+    else { dc = s - c0; return s; }
+  }
+};
 
 __device__ __forceinline__ double dlog(double v) { return log(v); }
 __device__ __forceinline__ float dlog(float v) { return logf(v); }

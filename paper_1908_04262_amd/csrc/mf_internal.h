@@ -71,19 +71,33 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(r >> 16);
 }
 
-// population codec: storage value <-> arithmetic value of direction i
+// Population codec. The binary64 instance stores and computes f itself. The binary32
+// and 16-bit instances store and compute offsets from the fluid at rest,
+// f_i - w_i and g_i - w_i c0: a cell at rest is then exactly zero, so rounding cannot
+// create mass or gas there, and the small offsets keep their relative precision in
+// 16-bit storage. dec/enc convert between storage and the register convention.
 template <int P, int D> struct FCodec {
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
-  static __device__ __forceinline__ R dec(SF s, int i) {
+  static constexpr bool SHIFT = P != 0;
+  static __device__ __forceinline__ R dec(SF s, int) {
     if constexpr (P == 0 || P == 1) return s;
-    else if constexpr (P == 2) return (float)Lat<D>::w[i] + (float)s;
-    else return (float)Lat<D>::w[i] + bf16_to_f32(s);
+    else if constexpr (P == 2) return (float)s;
+    else return bf16_to_f32(s);
   }
-  static __device__ __forceinline__ SF enc(R v, int i) {
+  static __device__ __forceinline__ SF enc(R v, int) {
     if constexpr (P == 0 || P == 1) return v;
-    else if constexpr (P == 2) return (_Float16)(v - (float)Lat<D>::w[i]);
-    else return f32_to_bf16(v - (float)Lat<D>::w[i]);
+    else if constexpr (P == 2) return (_Float16)v;
+    else return f32_to_bf16(v);
+  }
+  // full population value in binary64 (field transfer)
+  static __device__ __forceinline__ double full(SF s, int i) {
+    if constexpr (P == 0) return s;
+    else return Lat<D>::w[i] + (double)dec(s, i);
+  }
+  static __device__ __forceinline__ SF from_full(double v, int i) {
+    if constexpr (P == 0) return v;
+    else return enc((R)(v - Lat<D>::w[i]), i);
   }
 };
 

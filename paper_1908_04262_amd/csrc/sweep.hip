@@ -23,6 +23,7 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
   using SF = typename Prec<P>::SF;
   using SG = typename Prec<P>::SG;
   using FC = FCodec<P, D>;
+  using A = Arith<D, P>;
   constexpr int Q = L::Q, Qg = L::Qg;
 
   // tile of 64 x 4 cells; consecutive tiles of one z-range go to the same XCD
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
         const int64_t s = nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
         tsrc[i] = d.type[s] & TMASK;
       }
-      R rg = R(1), uox = R(0), uoy = R(0), uoz = R(0), uou = R(0), cH = R(0);
+      R rg = R(1), uox = R(0), uoy = R(0), uoz = R(0), uou = R(0), cH = R(0), dcH = R(0);
       if (isI) {
         double pb = p.p_atm;
         if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
         const R kap = ((const R *)d.kappa)[n], pi = ((const R *)d.Pi)[n];
         rg = R(3) * ((R(pb) - R(2) * R(p.sigma) * kap) - pi);
         cH = R(p.kH) * R(pb);
+        dcH = cH - R(p.c0);
         uox = ((const R *)d.ux)[n];
         uoy = ((const R *)d.uy)[n];
         uoz = D == 3 ? ((const R *)d.uz)[n] : R(0);
@@ -98,7 +100,8 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
           ft[i] = own[opp(i)];
         } else if (tsrc[i] == TG) {
           if (!isI) raise_status(d.status, ST_INVARIANT);
-          ft[i] = (feq<D, R>(i, rg, uox, uoy, uoz, uou) + feq<D, R>(opp(i), rg, uox, uoy, uoz, uou)) - own[opp(i)];
+          ft[i] = (A::eq(i, rg, rg - R(1), uox, uoy, uoz, uou) + A::eq(opp(i), rg, rg - R(1), uox, uoy, uoz, uou)) -
+                  own[opp(i)];
         }
       }
 #pragma unroll
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
         if (tsrc[i] == TW) {
           gt[i] = gown[opp(i)];
         } else if (tsrc[i] == TG) {
-          gt[i] = (geq<D, R>(i, cH, uox, uoy, uoz) + geq<D, R>(opp(i), cH, uox, uoy, uoz)) - gown[opp(i)];
+          gt[i] = (A::geqv(i, cH, dcH, uox, uoy, uoz) + A::geqv(opp(i), cH, dcH, uox, uoy, uoz)) - gown[opp(i)];
           phic = phic + (gown[opp(i)] - gt[i]);
           hasgas = true;
         }
@@ -130,8 +133,8 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
       }
     }
     // moments and collision
-    R rho, ux, uy, uz;
-    moments<D, R>(ft, rho, ux, uy, uz);
+    R rho, drho, ux, uy, uz;
+    A::mom(ft, rho, drho, ux, uy, uz);
     if (!(rho > R(0))) raise_status(d.status, ST_NONFINITE);
     const R uu = usq<D, R>(ux, uy, uz);
     R omega = R(p.omega);
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
       R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const R dd = ft[i] - feq<D, R>(i, rho, ux, uy, uz, uu);
+        const R dd = ft[i] - A::eq(i, rho, drho, ux, uy, uz, uu);
         const int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
         if (ex) pxx = pxx + dd;
         if (ey) pyy = pyy + dd;
@@ -153,16 +156,15 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const R fe = feq<D, R>(i, rho, ux, uy, uz, uu);
+      const R fe = A::eq(i, rho, drho, ux, uy, uz, uu);
       fout[(int64_t)i * Np + n] = FC::enc(ft[i] - omega * (ft[i] - fe), i);
     }
-    R c = gt[0];
-#pragma unroll
-    for (int i = 1; i < Qg; ++i) c = c + gt[i];
+    R dc;
+    const R c = A::conc(gt, R(p.c0), dc);
     const R og = R(p.omega_g), q = R(p.q);
 #pragma unroll
     for (int i = 0; i < Qg; ++i) {
-      gout[(int64_t)i * Np + n] = (gt[i] - og * (gt[i] - geq<D, R>(i, c, ux, uy, uz))) + R(Lat<D>::wg[i]) * q;
+      gout[(int64_t)i * Np + n] = (gt[i] - og * (gt[i] - A::geqv(i, c, dc, ux, uy, uz))) + R(Lat<D>::wg[i]) * q;
     }
     if (isI) {
       ((R *)d.rho)[n] = rho;
