@@ -66,7 +66,6 @@ def run_one(wl, steps, warmup, log):
     sim.profile(False)
     T1 = sim.read("type")
     bytes1, nf1, _ = sweep_bytes(wl, T1, wl["precision"])
-    tot = sim.totals()
     led = sim.ledgers()
     ncell = int(np.prod(sim.shape))
     wall = t2 - t1
@@ -85,7 +84,6 @@ def run_one(wl, steps, warmup, log):
         n_interface=int(np.count_nonzero(T1 == 1)),
         n_bubbles=led["n_bubbles"],
         status=led["status"],
-        liquid_mass=float(tot["liquid"] + tot["lost_liquid"]),
     )
     # whole-step algorithmic HBM fraction (sweep bytes per step over wall time)
     res["hbm_frac_step"] = bytes_launch / (wall / steps) / 1e9 / HBM_PEAK_GBS

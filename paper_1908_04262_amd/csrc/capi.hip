@@ -119,6 +119,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.rh_key = cv.take<int32_t>((size_t)kp.RH * 4);
   d.rh_head = cv.take<int32_t>((size_t)kp.RH * 4);
   d.contested = cv.take<int32_t>((size_t)kp.ecap * 4);
+  d.rused = cv.take<int32_t>((size_t)kp.ecap * 4);
   d.scratch_d = cv.take<double>(cap * 8);
 }
 

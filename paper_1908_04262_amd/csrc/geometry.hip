@@ -190,34 +190,67 @@ __global__ __launch_bounds__(256) void k_normals(KP p, DA d) {
 }
 
 // Gaussian elimination with partial pivoting (first maximum on ties); fails when a pivot
-// falls below rel times the largest diagonal entry (the points do not determine the fit)
+// falls below rel times the largest diagonal entry (the points do not determine the fit).
+// Fully unrolled: row swaps are selects, so the matrix stays in registers.
 template <class R, int NU>
-__device__ bool solve_ge(R A[6][6], R b[6], R x[6], R rel) {
+__device__ __forceinline__ bool solve_ge(R (&A)[NU][NU], R (&b)[NU], R (&x)[NU], R rel) {
   R scale = R(0);
+#pragma unroll
   for (int c = 0; c < NU; c++)
     if (A[c][c] > scale) scale = A[c][c];
   const R tiny = rel * scale;
+  bool ok = true;
+#pragma unroll
   for (int c = 0; c < NU; c++) {
     int piv = c;
-    for (int r = c + 1; r < NU; r++)
-      if (dabs(A[r][c]) > dabs(A[piv][c])) piv = r;
-    if (!(dabs(A[piv][c]) >= tiny)) return false;
-    if (piv != c) {
-      for (int k = 0; k < NU; k++) { const R t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
-      const R t = b[c]; b[c] = b[piv]; b[piv] = t;
+    R best = dabs(A[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < NU; r++) {
+      const R v = dabs(A[r][c]);
+      if (v > best) { best = v; piv = r; }
     }
+    if (!(best >= tiny)) ok = false;
+#pragma unroll
+    for (int r = c + 1; r < NU; r++) {
+      const bool sw = r == piv;
+#pragma unroll
+      for (int k = 0; k < NU; k++) {
+        const R t = A[c][k];
+        A[c][k] = sw ? A[r][k] : t;
+        A[r][k] = sw ? t : A[r][k];
+      }
+      const R t = b[c];
+      b[c] = sw ? b[r] : t;
+      b[r] = sw ? t : b[r];
+    }
+#pragma unroll
     for (int r = c + 1; r < NU; r++) {
       const R f = A[r][c] / A[c][c];
+#pragma unroll
       for (int k = c; k < NU; k++) A[r][k] = A[r][k] - f * A[c][k];
       b[r] = b[r] - f * b[c];
     }
   }
+#pragma unroll
   for (int r = NU - 1; r >= 0; r--) {
     R acc = b[r];
+#pragma unroll
     for (int k = r + 1; k < NU; k++) acc = acc - A[r][k] * x[k];
     x[r] = acc / A[r][r];
   }
-  return true;
+  return ok;
+}
+
+// add one fit point: normal-matrix entries phi_a phi_b (upper triangle, mirrored: the
+// products are symmetric, so this equals accumulating every entry) and rhs phi_a h
+template <class R, int NU>
+__device__ __forceinline__ void add_point(R (&A)[NU][NU], R (&rhs)[NU], const R (&phi)[NU], R h) {
+#pragma unroll
+  for (int a = 0; a < NU; a++) {
+#pragma unroll
+    for (int b = a; b < NU; b++) A[a][b] = A[a][b] + phi[a] * phi[b];
+    rhs[a] = rhs[a] + phi[a] * h;
+  }
 }
 
 template <int D, int P>
@@ -226,10 +259,11 @@ __global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
   constexpr int NU = D == 3 ? 6 : 3;
   constexpr int RR = D == 3 ? 1 : 2;
   const R rel = sizeof(R) == 8 ? R(1e-9) : R(1e-6);
+  const R *MX = (const R *)d.mx, *MY = (const R *)d.my, *MZ = (const R *)d.mz, *SO = (const R *)d.soff;
   NEWI_LOOP(k, n) {
     const int64_t n = NEWI_CELL(k);
     if ((d.type[n] & TMASK) != TI) continue;
-    const R m0 = ((const R *)d.mx)[n], m1 = ((const R *)d.my)[n], m2 = ((const R *)d.mz)[n];
+    const R m0 = MX[n], m1 = MY[n], m2 = MZ[n];
     R kap = R(0);
     if (m0 != R(0) || m1 != R(0) || m2 != R(0)) {
       int x, y, z;
@@ -253,40 +287,53 @@ __global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
         t1[0] = -m1; t1[1] = m0; t1[2] = R(0);
         t2[0] = t2[1] = t2[2] = R(0);
       }
-      R A[6][6], rhs[6], sol[6];
-      for (int a = 0; a < 6; a++) { rhs[a] = R(0); sol[a] = R(0); for (int b = 0; b < 6; b++) A[a][b] = R(0); }
+      R A[NU][NU], rhs[NU], sol[NU];
+#pragma unroll
+      for (int a = 0; a < NU; a++) {
+        rhs[a] = R(0);
+        sol[a] = R(0);
+#pragma unroll
+        for (int b = 0; b < NU; b++) A[a][b] = R(0);
+      }
       int np = 0;
-      const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-      for (int pass = 0; pass < 2; pass++)
-        for (int dz = zlo; dz <= zhi; dz++)
-          for (int dy = -RR; dy <= RR; dy++)
-            for (int dx = -RR; dx <= RR; dx++) {
-              const bool centre = dx == 0 && dy == 0 && dz == 0;
-              if ((pass == 0) != centre) continue;
-              const int64_t yy = centre ? n : nb_index_or_none(p, x, y, z, dx, dy, dz);
-              if (yy < 0 || (d.type[yy] & TMASK) != TI) continue;
-              const R q0 = ((const R *)d.mx)[yy], q1 = ((const R *)d.my)[yy], q2 = ((const R *)d.mz)[yy];
-              if (q0 == R(0) && q1 == R(0) && q2 == R(0)) continue;
-              const R off = ((const R *)d.soff)[yy];
-              const R px = R(dx) + off * q0, py = R(dy) + off * q1, pz = R(dz) + off * q2;
-              const R u = (px * t1[0] + py * t1[1]) + pz * t1[2];
-              const R v = (px * t2[0] + py * t2[1]) + pz * t2[2];
-              const R h = (px * m0 + py * m1) + pz * m2;
-              R phi[6];
-              if (D == 3) { phi[0] = u * u; phi[1] = v * v; phi[2] = u * v; phi[3] = u; phi[4] = v; phi[5] = R(1); }
-              else { phi[0] = u * u; phi[1] = u; phi[2] = R(1); phi[3] = phi[4] = phi[5] = R(0); }
-              for (int a = 0; a < NU; a++) {
-                for (int b = 0; b < NU; b++) A[a][b] = A[a][b] + phi[a] * phi[b];
-                rhs[a] = rhs[a] + phi[a] * h;
-              }
-              np++;
-            }
+      // the centre point first, then the block in (dz, dy, dx) ascending order
+      for (int j = -1; j < (D == 3 ? 27 : 25); j++) {
+        int dx = 0, dy = 0, dz = 0;
+        if (j >= 0) {
+          if (D == 3) { dx = j % 3 - 1; dy = (j / 3) % 3 - 1; dz = j / 9 - 1; }
+          else { dx = j % 5 - 2; dy = j / 5 - 2; }
+          if (dx == 0 && dy == 0 && dz == 0) continue;
+        }
+        const int64_t yy = j < 0 ? n : nb_index_or_none(p, x, y, z, dx, dy, dz);
+        if (yy < 0 || (d.type[yy] & TMASK) != TI) continue;
+        const R q0 = MX[yy], q1 = MY[yy], q2 = MZ[yy];
+        if (q0 == R(0) && q1 == R(0) && q2 == R(0)) continue;
+        const R off = SO[yy];
+        const R px = R(dx) + off * q0, py = R(dy) + off * q1, pz = R(dz) + off * q2;
+        const R u = (px * t1[0] + py * t1[1]) + pz * t1[2];
+        const R h = (px * m0 + py * m1) + pz * m2;
+        R phi[NU];
+        if constexpr (D == 3) {
+          const R v = (px * t2[0] + py * t2[1]) + pz * t2[2];
+          phi[0] = u * u; phi[1] = v * v; phi[2] = u * v; phi[3] = u; phi[4] = v; phi[5] = R(1);
+        } else {
+          phi[0] = u * u; phi[1] = u; phi[2] = R(1);
+        }
+        add_point<R, NU>(A, rhs, phi, h);
+        np++;
+      }
+#pragma unroll
+      for (int a = 0; a < NU; a++)
+#pragma unroll
+        for (int b = 0; b < a; b++) A[a][b] = A[b][a];
       // 3D: ridge term on the quadratic coefficients; keeps one-sided point sets (next
       // to walls) determined and pulls their undetermined curvature towards zero
-      if (D == 3)
+      if (D == 3) {
+#pragma unroll
         for (int a = 0; a < 3; a++) A[a][a] = A[a][a] + R(1e-2);
+      }
       if (np >= NU && solve_ge<R, NU>(A, rhs, sol, rel)) {
-        if (D == 3) {
+        if constexpr (D == 3) {
           const R cA = sol[0], cB = sol[1], cC = sol[2], cD = sol[3], cE = sol[4];
           const R num = (((R(1) + cE * cE) * (R(2) * cA)) - (((R(2) * cD) * cE) * cC)) + ((R(1) + cD * cD) * (R(2) * cB));
           const R t = (R(1) + cD * cD) + cE * cE;

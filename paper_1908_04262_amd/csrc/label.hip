@@ -200,16 +200,21 @@ __device__ void write_bubble(const KP &p, DA &d, int id, double m, __int128 vk) 
 __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_flux) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int cap = p.cap;
-  __shared__ int s_ncont;
+  __shared__ int s_ncont, s_nroot;
   __shared__ long long s_atm[3];
   int ne = *(volatile int32_t *)(d.cnt + C_ENTRIES);
   if (ne > p.ecap) ne = p.ecap;
+  // ids are never reused, so every id in use is below the id counter
+  int jmax = *(volatile int32_t *)(d.cnt + C_NEXTID);
+  if (jmax > cap) jmax = cap;
   if (tid == 0) {
     s_ncont = 0;
+    s_nroot = 0;
     s_atm[0] = s_atm[1] = s_atm[2] = 0;
   }
+  __syncthreads();
   // phase 0: gas of each old bubble after this step's flux; clear the table
-  for (int j = tid; j < cap; j += nt) {
+  for (int j = tid; j < jmax; j += nt) {
     const int al = d.balive[j];
     d.alive_prev[j] = al;
     double mp = 0.0;
@@ -269,7 +274,11 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
       unsigned s = ((unsigned)root * 2654435761u) & (unsigned)(p.RH - 1);
       for (int probe = 0; probe < p.RH; ++probe) {
         const int32_t old = atomicCAS(&d.rh_key[s], REMPTY, root);
-        if (old == REMPTY || old == root) break;
+        if (old == REMPTY) {
+          d.rused[atomicAdd(&s_nroot, 1)] = (int)s;
+          break;
+        }
+        if (old == root) break;
         s = (s + 1) & (unsigned)(p.RH - 1);
       }
       d.ent_next[e] = atomicExch(&d.rh_head[s], e);
@@ -277,9 +286,10 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
   }
   __syncthreads();
   // phase C: components whose ids are theirs alone
-  for (int s = tid; s < p.RH; s += nt) {
+  const int nroot = s_nroot;
+  for (int u = tid; u < nroot; u += nt) {
+    const int s = d.rused[u];
     const int32_t root = d.rh_key[s];
-    if (root == REMPTY) continue;
     int loc[LOCALMAX];
     int nl = 0;
     bool contested = false;
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
   }
   __syncthreads();
   // phase D: atmosphere shares and collapsed bubbles
-  for (int j = 1 + tid; j < cap; j += nt) {
+  for (int j = 1 + tid; j < jmax; j += nt) {
     if (!d.alive_prev[j]) continue;
     const int lc = d.lab_cnt[j];
     const bool inatm = (lc & ATMBIT) != 0;
@@ -376,8 +386,9 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
     d.cnt[C_CONTESTED] = nc;
   }
   __syncthreads();
-  // clear the root hash; fold this step's ledgers into the running totals
-  for (int s = tid; s < p.RH; s += nt) {
+  // clear the used root-hash slots; fold this step's ledgers into the running totals
+  for (int u = tid; u < nroot; u += nt) {
+    const int s = d.rused[u];
     d.rh_key[s] = REMPTY;
     d.rh_head[s] = -1;
   }

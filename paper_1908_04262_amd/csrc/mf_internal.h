@@ -142,7 +142,8 @@ struct DA {
   int32_t *lab_first;         // smallest non-atmosphere root containing each id [cap]
   int32_t *lab_assigned;      // [cap]
   long long *lab_vtot, *lab_vatm; // [cap][3]
-  int32_t *rh_key, *rh_head;  // root hash [2*ecap]
+  int32_t *rh_key, *rh_head;  // root hash [RH]
+  int32_t *rused;             // used root-hash slots [ecap]
   int32_t *contested;         // [ecap]
   double *scratch_d;          // [cap] spare
 };

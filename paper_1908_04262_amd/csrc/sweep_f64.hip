@@ -1,0 +1,8 @@
+// Lattice sweep, binary64 instance: compiled without floating-point contraction so that
+// every operation rounds as the method's reference arithmetic prescribes.
+#include "sweep_impl.h"
+
+namespace mf {
+template void Ops<2, 0>::sweep(Ctx &, hipStream_t);
+template void Ops<3, 0>::sweep(Ctx &, hipStream_t);
+}  // namespace mf

@@ -12,12 +12,13 @@
 //    (Eq. tau, Eq. carreauTau), ADE collision with source (Eq. diffusion);
 //  - fill / empty classification of interface cells (Sec. 2.1).
 // The kernel also lists the interface cells and the bubble cells of the types it read.
+#pragma once
 #include "lbm_math.h"
 
 namespace mf {
 
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep(KP p, DA d, int cur) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
@@ -71,6 +72,8 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
     if (special) {
       R own[Q], gown[Qg];
       uint8_t tsrc[Q];
+      // the cell's own outgoing populations (bounce-back, mass exchange) and the types
+      // of its sources, all loads issued together
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         own[i] = FC::dec(fin[(int64_t)i * Np + n], i);
@@ -142,7 +145,9 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
       R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const R dd = ft[i] - A::eq(i, rho, drho, ux, uy, uz, uu);
+        // binary64: sum e e (f - f_eq) term by term; offset instances: sum e e (f - w),
+        // the equilibrium part is removed in closed form below
+        const R dd = P == 0 ? ft[i] - A::eq(i, rho, drho, ux, uy, uz, uu) : ft[i];
         const int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
         if (ex) pxx = pxx + dd;
         if (ey) pyy = pyy + dd;
@@ -150,6 +155,19 @@ __global__ __launch_bounds__(256) void k_sweep(KP p, DA d, int cur) {
         if (ex && ey) pxy = pxy + R(ex * ey) * dd;
         if (D == 3 && ex && ez) pxz = pxz + R(ex * ez) * dd;
         if (D == 3 && ey && ez) pyz = pyz + R(ey * ez) * dd;
+      }
+      if constexpr (P != 0) {
+        // second moment of the equilibrium: rho c_s^2 I + rho u u; on offsets the rest
+        // state contributes I/3, so subtract drho/3 on the diagonal
+        const R d3 = drho * R(1.0 / 3.0);
+        pxx = pxx - (d3 + rho * ux * ux);
+        pyy = pyy - (d3 + rho * uy * uy);
+        pxy = pxy - rho * ux * uy;
+        if (D == 3) {
+          pzz = pzz - (d3 + rho * uz * uz);
+          pxz = pxz - rho * ux * uz;
+          pyz = pyz - rho * uy * uz;
+        }
       }
       const R ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + R(2) * ((pxy * pxy + pxz * pxz) + pyz * pyz);
       omega = R(1) / powerlaw_tau<R>(p, rho, sqrt(ss));
@@ -191,8 +209,5 @@ void Ops<D, P>::sweep(Ctx &c, hipStream_t s) {
   const int64_t nb = (int64_t)gx * gy * c.kp.nz;
   hipLaunchKernelGGL((k_sweep<D, P>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
 }
-
-#define MF_INST(D, P) template void Ops<D, P>::sweep(Ctx &, hipStream_t);
-MF_FOR_ALL(MF_INST)
 
 }  // namespace mf
