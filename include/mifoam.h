@@ -191,6 +191,61 @@ int mf_read_bubbles(mf_ctx *ctx, mf_bubble *dst, int32_t capacity, int32_t *n_ou
 /* Ledgers and counters. Synchronises. */
 int mf_totals_get(mf_ctx *ctx, mf_totals *out);
 
+/* ------------------------------------------------------------ learned curvature ---
+ * A small network (125-64-64-1, GELU, bfloat16 weights and activations, binary32
+ * accumulation on the matrix cores) maps the 5x5x5 fill-fraction stencil of an interface
+ * cell, brought to a canonical orientation by the cube symmetry that orders its
+ * central-difference normal as m_x >= m_y >= m_z >= 0, to its mean curvature (the
+ * curvature of Eq. rhob). It is trained on stencils of voxelised spheres and ellipsoids
+ * with exact curvature labels. The plain paraboloid fit remains the fallback. */
+typedef struct mf_mlp mf_mlp; /* opaque trained network (device parameters) */
+
+typedef struct mf_mlp_train_spec {
+  size_t struct_size;  /* = sizeof(mf_mlp_train_spec) */
+  int64_t n_train;     /* training stencils (e.g. 1.9M) */
+  int64_t n_val;       /* validation stencils (e.g. 0.1M), generated after the training ones */
+  int32_t epochs;      /* passes over the training set */
+  int32_t batch;       /* multiple of 64 (e.g. 4096) */
+  double lr;           /* Adam step, cosine-decayed to 0 over the run */
+  double noise;        /* standard deviation of the fill noise on cut cells (0.01) */
+  uint64_t data_seed;  /* stencil generator seed */
+} mf_mlp_train_spec;
+
+/* Number of binary32 parameters in the layout of mf_mlp_get_params: W1 [128][64] (rows
+ * 125..127 zero), b1 [64], W2 [64][64], b2 [64], W3 [64], b3. */
+int mf_mlp_param_count(void);
+
+/* Create a network with weights uniform in +-1/sqrt(fan_in) (SplitMix64 stream of
+ * init_seed) and zero biases; device memory is owned by the network. */
+int mf_mlp_create(uint64_t init_seed, mf_mlp **out);
+int mf_mlp_destroy(mf_mlp *m);
+
+/* Train on the GPU (stream: hipStream_t, NULL = null stream): generate the stencils, then
+ * Adam on the mean squared error of 8 kappa for spec->epochs epochs; *val_rmse receives
+ * the validation root-mean-square curvature error. Synchronises. */
+int mf_mlp_train(mf_mlp *m, const mf_mlp_train_spec *spec, void *stream, double *val_rmse);
+
+/* Copy the binary32 master parameters out / in (host buffers of mf_mlp_param_count floats). */
+int mf_mlp_get_params(const mf_mlp *m, float *dst);
+int mf_mlp_set_params(mf_mlp *m, const float *src);
+
+/* Generate n stencils (sample indices first..first+n-1 of the counter-based generator)
+ * into host buffers: raw stencils [n][125] (dz outer, dx inner) and exact curvature [n]. */
+int mf_mlp_generate(uint64_t data_seed, int64_t first, int64_t n, double noise, float *stencils,
+                    float *kappa, void *stream);
+
+/* Curvature of n raw stencils [n][125] (host) through canonicalisation and the network. */
+int mf_mlp_eval(const mf_mlp *m, const float *stencils, int64_t n, float *kappa, void *stream);
+
+/* Loss and parameter gradient on one batch of raw stencils [B][125] with targets 8 kappa
+ * (host buffers; grad has mf_mlp_param_count floats). For gradient checks. */
+int mf_mlp_grad(const mf_mlp *m, const float *stencils, const float *target8, int32_t B, float *grad,
+                double *loss, void *stream);
+
+/* Use the network for the curvature of ctx (requires curvature = MF_CURV_MLP in the
+ * parameters); the weights are copied, the network may be destroyed afterwards. */
+int mf_attach_mlp(mf_ctx *ctx, const mf_mlp *m);
+
 /* Time of the last mf_step window in milliseconds per launch of the named kernel
  * group, measured with HIP events on the context stream: group 0 = lattice sweep,
  * 1 = whole step. Valid after mf_profile_enable(ctx, 1) and a completed mf_step. */

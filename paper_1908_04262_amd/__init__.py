@@ -3,4 +3,5 @@
 The compute path is the HIP library libmifoam.so (C ABI in include/mifoam.h); this
 package holds its sources (csrc/), its build script and a ctypes binding.
 """
-from .mifoam import EXPORTS, MifoamError, Sim, load_library, make_params  # noqa: F401
+from .mifoam import (  # noqa: F401
+    EXPORTS, CurvatureNet, MifoamError, Sim, generate_stencils, load_library, make_params)

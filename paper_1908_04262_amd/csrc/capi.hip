@@ -12,9 +12,16 @@
 
 using namespace mf;
 
+namespace mf {
+thread_local std::string g_thread_err;
+}
+
+struct mf_mlp;
+int mf_mlp_export_weights(const mf_mlp *m, uint16_t *w_dev, float *b_dev, hipStream_t s);
+
 namespace {
 
-thread_local std::string g_err;
+std::string &g_err = mf::g_thread_err;
 
 struct OpsTable {
   void (*sweep)(Ctx &, hipStream_t);
@@ -132,7 +139,8 @@ int validate(const mf_params *p, std::string &why) {
   if ((double)p->nx * p->ny * nz >= 2147483647.0) { why = "grid exceeds 2^31 cells"; return MF_EINVAL; }
   if (p->precision < 0 || p->precision > 3) { why = "unknown precision"; return MF_EINVAL; }
   if (p->rheology != MF_NEWTONIAN && p->rheology != MF_POWER_LAW) { why = "unknown rheology"; return MF_EINVAL; }
-  if (p->curvature != MF_CURV_PLAIN) { why = "learned curvature is not built into this library"; return MF_EUNSUPPORTED; }
+  if (p->curvature != MF_CURV_PLAIN && p->curvature != MF_CURV_MLP) { why = "unknown curvature mode"; return MF_EINVAL; }
+  if (p->curvature == MF_CURV_MLP && p->dim != 3) { why = "the learned curvature works on 5x5x5 stencils (3D only)"; return MF_EUNSUPPORTED; }
   if (p->max_ids < 2 || p->max_ids > (1 << 24)) { why = "max_ids out of range"; return MF_EINVAL; }
   if (!(p->tau > 0.5) || !(p->D > 0.0) || !(p->RT > 0.0) || !(p->eps >= 0.0)) { why = "tau > 1/2, D > 0, RT > 0, eps >= 0 required"; return MF_EINVAL; }
   if (p->k_pi > 0.0 && !(p->d_max >= 1.0)) { why = "d_max >= 1 required with disjoining pressure"; return MF_EINVAL; }
@@ -319,6 +327,7 @@ int mf_destroy(mf_ctx *c) {
   if (!c) return MF_OK;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->prof_ev.ev) (void)hipEventDestroy(e);
+  if (c->mlp_buf) (void)hipFree(c->mlp_buf);
   if (c->own_ws) (void)hipFree(c->ws);
   delete c;
   return MF_OK;
@@ -363,6 +372,7 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 int mf_step(mf_ctx *c, int32_t nsteps) {
   if (!c) return MF_EINVAL;
   if (nsteps < 0) { c->err = "nsteps < 0"; return MF_EINVAL; }
+  if (c->kp.curvature == MF_CURV_MLP && !c->d.mlp_w) { c->err = "learned curvature selected but no network attached"; return MF_ESTATE; }
   for (int k = 0; k < nsteps; k++) {
     hipEvent_t *ev = nullptr;
     if (c->prof) {
@@ -521,6 +531,21 @@ int mf_totals_get(mf_ctx *c, mf_totals *out) {
   out->n_bubbles = nb;
   out->n_interface = cnt[C_I];
   out->status = st;
+  return MF_OK;
+}
+
+int mf_attach_mlp(mf_ctx *c, const mf_mlp *m) {
+  if (!c || !m) return MF_EINVAL;
+  if (c->kp.curvature != MF_CURV_MLP) { c->err = "the context was created for the plain curvature"; return MF_ESTATE; }
+  if (!c->mlp_buf) {
+    HIPCHK(c, hipMalloc(&c->mlp_buf, 2 * (128 * 64 + 64 * 64 + 64) + 4 * (2 * 64 + 1) + 256));
+  }
+  uint16_t *w = (uint16_t *)c->mlp_buf;
+  float *b = (float *)((char *)c->mlp_buf + ((2 * (128 * 64 + 64 * 64 + 64) + 255) & ~255));
+  const int rc = mf_mlp_export_weights(m, w, b, c->stream);
+  if (rc) { c->err = "copying the network weights failed"; return rc; }
+  c->d.mlp_w = w;
+  c->d.mlp_b = b;
   return MF_OK;
 }
 

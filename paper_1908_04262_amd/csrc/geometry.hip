@@ -263,6 +263,10 @@ __global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
   NEWI_LOOP(k, n) {
     const int64_t n = NEWI_CELL(k);
     if ((d.type[n] & TMASK) != TI) continue;
+    if (d.cflag[n] & CF_MLPOK) {  // the network already gave this cell's curvature
+      d.cflag[n] = 0;
+      continue;
+    }
     const R m0 = MX[n], m1 = MY[n], m2 = MZ[n];
     R kap = R(0);
     if (m0 != R(0) || m1 != R(0) || m2 != R(0)) {
@@ -411,6 +415,7 @@ template <int D, int P>
 void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
   const unsigned nb = list_blocks(c);
   hipLaunchKernelGGL((k_normals<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
   hipLaunchKernelGGL((k_curvature<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_disjoining<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
 }

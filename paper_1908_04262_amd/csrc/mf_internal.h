@@ -16,7 +16,7 @@ constexpr uint8_t TG = 0, TI = 1, TL = 2, TW = 3;
 constexpr uint8_t TMASK = 3, NEARWALL = 4;
 // conversion flag byte (one per cell; zero between steps)
 constexpr uint32_t CF_FILL = 1, CF_EMPTY = 2, CF_NEWI = 4, CF_L2I = 8, CF_ATM = 16,
-                   CF_ATMROOT = 32, CF_VALID = 64;
+                   CF_ATMROOT = 32, CF_VALID = 64, CF_MLPOK = 128;
 constexpr int32_t NOLAB = -1;
 
 // status bits raised by kernels
@@ -146,6 +146,9 @@ struct DA {
   int32_t *rused;             // used root-hash slots [ecap]
   int32_t *contested;         // [ecap]
   double *scratch_d;          // [cap] spare
+  // learned curvature (NULL unless a network is attached)
+  const uint16_t *mlp_w;      // bfloat16 W1 [128][64], W2 [64][64], W3 [64]
+  const float *mlp_b;         // b1 [64], b2 [64], b3
 };
 
 // ------------------------------------------------------------------ fixed point
@@ -290,10 +293,17 @@ struct Ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   double prof_ms[2] = {0, 0};
   int64_t prof_n[2] = {0, 0};
+  void *mlp_buf = nullptr;  // device copy of the attached network's weights
 };
 
 // every (dimension, precision) instance the library is built with
 #define MF_FOR_ALL(M) M(2, 0) M(2, 1) M(2, 2) M(2, 3) M(3, 0) M(3, 1) M(3, 2) M(3, 3)
+
+// message of the last failed call on this thread that has no context
+extern thread_local std::string g_thread_err;
+
+// learned-curvature inference over the new interface cells (3D)
+void launch_mlp_curv(Ctx &c, hipStream_t s);
 
 // initial gas content and pressure of the nucleus ids 1..nn (p0 in device memory)
 void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn);

@@ -1,0 +1,762 @@
+// Learned curvature closure: stencil generator, canonical orientation, bfloat16 MFMA
+// matrix products with binary32 accumulation, training (forward, backward, Adam) and
+// the inference kernel of the time step.
+//
+// Network: 125 fill fractions (5x5x5 block around an interface cell, canonical
+// orientation) -> 64 -> 64 -> 1 with GELU; kappa = out / 8. Inputs and hidden
+// activations are rounded to bfloat16 before each product; weights are rounded from the
+// binary32 master copy. The curvature enters the gas density of Eq. rhob.
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "lbm_math.h"
+
+namespace mf {
+
+constexpr int NF = 125, NPD = 128, NH = 64;
+constexpr int OW1 = 0, OB1 = NPD * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH, OB3 = OW3 + NH;
+constexpr int NPARAM = OB3 + 1;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __host__ __forceinline__ uint16_t bf16_bits(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(((uint32_t)bf16_bits(f)) << 16); }
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.7071067811865476f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.7071067811865476f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
+}
+
+// ---------------------------------------------------------------- stencil generator
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based stream per sample attempt
+struct SplitMix {
+  uint64_t s;
+  __device__ __host__ SplitMix(uint64_t seed, int64_t sample, int attempt) {
+    const uint64_t ctr = (uint64_t)(sample * 16 + attempt + 1);
+    s = seed + ctr * 0xD1B54A32D192ED03ull;
+  }
+  __device__ __host__ uint64_t u64() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  __device__ __host__ double uniform() { return (double)(u64() >> 11) * 0x1p-53; }
+  __device__ double normal() {
+    const double u1 = uniform(), u2 = uniform();
+    return sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+  }
+};
+
+struct Body {
+  double a[3], R[3][3], c[3];
+};
+
+// F < 0 inside the ellipsoid; body coordinates y = R^T (x - c)
+__device__ __forceinline__ double body_F(const Body &b, double x, double y, double z) {
+  const double dx = x - b.c[0], dy = y - b.c[1], dz = z - b.c[2];
+  double f = -1.0;
+  for (int i = 0; i < 3; i++) {
+    const double yi = (dx * b.R[0][i] + dy * b.R[1][i]) + dz * b.R[2][i];
+    const double q = yi / b.a[i];
+    f = f + q * q;
+  }
+  return f;
+}
+
+__device__ double inside_frac(const Body &b, double cx, double cy, double cz) {
+  bool anyin = false, anyout = false;
+  for (int i = 0; i < 27; i++) {
+    const double f = body_F(b, cx + 0.5 * (i % 3 - 1), cy + 0.5 * ((i / 3) % 3 - 1), cz + 0.5 * (i / 9 - 1));
+    if (f < 0) anyin = true;
+    else anyout = true;
+  }
+  if (anyin && !anyout) return 1.0;
+  if (anyout && !anyin) {
+    // all 27 points outside (none exactly on the surface counts as inside)
+    return 0.0;
+  }
+  int cnt = 0;
+  for (int k = 0; k < 10; k++)
+    for (int j = 0; j < 10; j++)
+      for (int i = 0; i < 10; i++)
+        if (body_F(b, cx + (i + 0.5) / 10 - 0.5, cy + (j + 0.5) / 10 - 0.5, cz + (k + 0.5) / 10 - 0.5) < 0) cnt++;
+  return cnt / 1000.0;
+}
+
+// one attempt of sample `sample`; false if rejected (centre cell not cut, |kappa| > 1/2)
+__device__ bool gen_attempt(uint64_t seed, int64_t sample, int attempt, double noise, float *out, float *kappa) {
+  const double L2 = 0.6931471805599453, L40 = 3.6888794541139363;
+  SplitMix st(seed, sample, attempt);
+  Body b;
+  const bool sphere = st.uniform() < 0.5;
+  if (sphere) {
+    const double r = exp(L2 + st.uniform() * (L40 - L2));
+    b.a[0] = b.a[1] = b.a[2] = r;
+  } else {
+    for (int i = 0; i < 3; i++) b.a[i] = exp(L2 + st.uniform() * (L40 - L2));
+  }
+  double q[4];
+  for (int i = 0; i < 4; i++) q[i] = st.normal();
+  const double qn = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+  for (int i = 0; i < 4; i++) q[i] /= qn;
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  b.R[0][0] = 1 - 2 * (y * y + z * z); b.R[0][1] = 2 * (x * y - w * z); b.R[0][2] = 2 * (x * z + w * y);
+  b.R[1][0] = 2 * (x * y + w * z); b.R[1][1] = 1 - 2 * (x * x + z * z); b.R[1][2] = 2 * (y * z - w * x);
+  b.R[2][0] = 2 * (x * z - w * y); b.R[2][1] = 2 * (y * z + w * x); b.R[2][2] = 1 - 2 * (x * x + y * y);
+  double d[3];
+  for (int i = 0; i < 3; i++) d[i] = st.normal();
+  double s2 = 0;
+  for (int i = 0; i < 3; i++) s2 += (d[i] / b.a[i]) * (d[i] / b.a[i]);
+  const double sn = sqrt(s2);
+  double pb[3];
+  for (int i = 0; i < 3; i++) pb[i] = d[i] / sn;
+  double u[3];
+  for (int i = 0; i < 3; i++) u[i] = st.uniform() - 0.5;
+  const bool gas_inside = st.uniform() < 0.5;
+  for (int i = 0; i < 3; i++) b.c[i] = u[i] - ((b.R[i][0] * pb[0] + b.R[i][1] * pb[1]) + b.R[i][2] * pb[2]);
+  float al[NF];
+  for (int j = 0; j < NF; j++) {
+    const double fr = inside_frac(b, (double)(j % 5 - 2), (double)((j / 5) % 5 - 2), (double)(j / 25 - 2));
+    al[j] = (float)(gas_inside ? 1.0 - fr : fr);
+  }
+  if (!(al[62] > 0.0f && al[62] < 1.0f)) return false;
+  // closest surface point to the centre cell's centre (body frame), by bisection on the
+  // Lagrange parameter; then the mean curvature of the ellipsoid there
+  double o[3];
+  for (int i = 0; i < 3; i++) o[i] = -((b.R[0][i] * b.c[0] + b.R[1][i] * b.c[1]) + b.R[2][i] * b.c[2]);
+  double a2[3] = {b.a[0] * b.a[0], b.a[1] * b.a[1], b.a[2] * b.a[2]};
+  double amin2 = fmin(a2[0], fmin(a2[1], a2[2]));
+  auto g = [&](double t) {
+    double s = -1.0;
+    for (int i = 0; i < 3; i++) { const double v = (o[i] * b.a[i]) / (a2[i] + t); s += v * v; }
+    return s;
+  };
+  double lo = -amin2 * (1 - 1e-15);
+  double hi = fmax(1.0, fmax(fabs(o[0]), fmax(fabs(o[1]), fabs(o[2]))) * fmax(b.a[0], fmax(b.a[1], b.a[2])));
+  while (g(hi) > 0) hi *= 2;
+  for (int it = 0; it < 200; it++) {
+    const double mid = 0.5 * (lo + hi);
+    if (g(mid) > 0) lo = mid;
+    else hi = mid;
+  }
+  const double t = 0.5 * (lo + hi);
+  double qc[3];
+  for (int i = 0; i < 3; i++) qc[i] = o[i] * a2[i] / (a2[i] + t);
+  const double num = fabs((qc[0] * qc[0] + qc[1] * qc[1] + qc[2] * qc[2]) - (a2[0] + a2[1] + a2[2]));
+  const double ssum = qc[0] * qc[0] / (a2[0] * a2[0]) + qc[1] * qc[1] / (a2[1] * a2[1]) + qc[2] * qc[2] / (a2[2] * a2[2]);
+  double kap = num / (2.0 * (a2[0] * a2[1] * a2[2]) * (ssum * sqrt(ssum)));
+  if (!gas_inside) kap = -kap;
+  if (fabs(kap) > 0.5) return false;
+  for (int j = 0; j < NF; j++) {
+    if (al[j] > 0.0f && al[j] < 1.0f) {
+      double v = (double)al[j] + noise * st.normal();
+      al[j] = (float)fmin(1.0, fmax(0.0, v));
+    }
+  }
+  for (int j = 0; j < NF; j++) out[j] = al[j];
+  *kappa = (float)kap;
+  return true;
+}
+
+__global__ void k_mlp_generate(uint64_t seed, int64_t first, int64_t n, double noise, float *st, float *kap,
+                               int32_t *status) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    bool ok = false;
+    for (int a = 0; a < 16 && !ok; a++) ok = gen_attempt(seed, first + k, a, noise, st + k * NF, kap + k);
+    if (!ok) {
+      atomicOr(status, 1);
+      for (int j = 0; j < NF; j++) st[k * NF + j] = 0.0f;
+      kap[k] = 0.0f;
+    }
+  }
+}
+
+// canonical orientation: flip the axes whose central difference is negative, then order
+// the axes by |gradient| descending (lower axis first on ties); dst index (e2, e1, e0)
+// takes the source offset d with d[order[a]] = (flip ? -e_a : e_a)
+__device__ __forceinline__ void canon_map(float gx, float gy, float gz, int order[3], int flip[3]) {
+  const float g[3] = {gx, gy, gz};
+  const float ag[3] = {fabsf(gx), fabsf(gy), fabsf(gz)};
+  for (int i = 0; i < 3; i++) flip[i] = g[i] < 0.0f;
+  int o0 = 0, o1 = 1, o2 = 2, t;
+  // stable sort of three keys, descending |g|
+  if (ag[o1] > ag[o0]) { t = o0; o0 = o1; o1 = t; }
+  if (ag[o2] > ag[o1]) { t = o1; o1 = o2; o2 = t; }
+  if (ag[o1] > ag[o0]) { t = o0; o0 = o1; o1 = t; }
+  order[0] = o0;
+  order[1] = o1;
+  order[2] = o2;
+}
+
+// canonical stencils of raw ones, as bfloat16-rounded binary32 rows of 128 (3 zero pads)
+__global__ void k_mlp_canon(const float *raw, int64_t n, float *out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const float *s = raw + k * NF;
+    auto at = [&](int dx, int dy, int dz) { return fminf(1.0f, fmaxf(0.0f, s[(dz + 2) * 25 + (dy + 2) * 5 + (dx + 2)])); };
+    const float gx = 0.5f * (at(1, 0, 0) - at(-1, 0, 0));
+    const float gy = 0.5f * (at(0, 1, 0) - at(0, -1, 0));
+    const float gz = 0.5f * (at(0, 0, 1) - at(0, 0, -1));
+    int order[3], flip[3];
+    canon_map(gx, gy, gz, order, flip);
+    for (int j = 0; j < NPD; j++) {
+      float v = 0.0f;
+      if (j < NF) {
+        const int e[3] = {j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2};
+        int dd[3];
+        for (int a = 0; a < 3; a++) dd[order[a]] = flip[order[a]] ? -e[a] : e[a];
+        v = at(dd[0], dd[1], dd[2]);
+      }
+      out[k * NPD + j] = bf16_round(v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- matrix products
+// C[M][N] (row stride ldc) = op(A)[M][K] op(B)[K][N] on v_mfma_f32_16x16x16_bf16: element
+// A(m,k) at A[m*sam + k*sak], B(k,n) at B[k*sbk + n*sbn], both binary32 in memory and
+// rounded to bfloat16 on load. One wave per 16x16 output tile.
+// EPI 0: C = acc; EPI 1: C = acc + bias[n] and Hout = GELU(C) rounded to bfloat16.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
+                                              int64_t sbn, float *C, int64_t ldc, int M, int N, int K,
+                                              const float *bias, float *Hout) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
+  const int tilesN = N >> 4;
+  const int tm = wave / tilesN, tn = wave % tilesN;
+  if (tm * 16 >= M) return;
+  const int r = lane & 15, kq = (lane >> 4) * 4;
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a, b;
+    for (int j = 0; j < 4; j++) {
+      const int k = k0 + kq + j;
+      a[j] = (short)bf16_bits(A[(int64_t)(tm * 16 + r) * sam + (int64_t)k * sak]);
+      b[j] = (short)bf16_bits(B[(int64_t)k * sbk + (int64_t)(tn * 16 + r) * sbn]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  for (int j = 0; j < 4; j++) {
+    const int row = tm * 16 + kq + j, col = tn * 16 + r;
+    if (EPI == 0) {
+      C[(int64_t)row * ldc + col] = acc[j];
+    } else {
+      const float zz = acc[j] + bias[col];
+      C[(int64_t)row * ldc + col] = zz;
+      Hout[(int64_t)row * ldc + col] = bf16_round(gelu(zz));
+    }
+  }
+}
+
+static void gemm(hipStream_t s, int epi, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
+                 int64_t sbn, float *C, int64_t ldc, int M, int N, int K, const float *bias = nullptr,
+                 float *H = nullptr) {
+  const int tiles = (M / 16) * (N / 16);
+  const unsigned blocks = (unsigned)((tiles + 3) / 4);
+  if (epi == 0)
+    hipLaunchKernelGGL(k_gemm<0>, dim3(blocks), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, H);
+  else
+    hipLaunchKernelGGL(k_gemm<1>, dim3(blocks), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, H);
+}
+
+// output layer: out[b] = sum_j bf16(h2[b][j]) bf16(W3[j]) + b3 (ascending j, binary32)
+__global__ void k_out_layer(const float *H2, const float *theta, int B, float *out) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    float acc = 0.0f;
+    for (int j = 0; j < NH; j++) acc += H2[(int64_t)b * NH + j] * bf16_round(theta[OW3 + j]);
+    out[b] = acc + theta[OB3];
+  }
+}
+
+// loss terms and the output-layer gradient: dout = 2 (out - t) / B; dZ2 = dout W3 GELU'(Z2)
+__global__ void k_out_grad(const float *out, const float *target, const float *theta, const float *Z2, int B,
+                           float *dout, float *dZ2, double *loss) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    const float r = out[b] - target[b];
+    dout[b] = 2.0f * r / (float)B;
+    atomicAdd(loss, (double)r * (double)r / (double)B);
+    for (int j = 0; j < NH; j++)
+      dZ2[(int64_t)b * NH + j] = dout[b] * bf16_round(theta[OW3 + j]) * gelu_grad(Z2[(int64_t)b * NH + j]);
+  }
+}
+
+__global__ void k_mul_gelu_grad(float *D, const float *Z, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    D[i] = D[i] * gelu_grad(Z[i]);
+}
+
+// g[off + j] = sum_b X[b][j] * w[b] (w = NULL: plain column sums), one block per column
+__global__ void k_colsum(const float *X, int ld, int ncol, const float *w, int B, float *g, int off) {
+  __shared__ float sh[256];
+  const int j = blockIdx.x;
+  if (j >= ncol) return;
+  float acc = 0.0f;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) acc += X[(int64_t)b * ld + j] * (w ? w[b] : 1.0f);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[off + j] = sh[0];
+}
+
+__global__ void k_sum_to(const float *x, int B, float *g, int off) {
+  __shared__ float sh[256];
+  float acc = 0.0f;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) acc += x[b];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[off] = sh[0];
+}
+
+// Adam (Kingma & Ba 2015) with bias correction
+__global__ void k_adam(float *theta, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i >= OW1 + NF * NH && i < OB1) continue;  // zero-padded input rows stay zero
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// batch of canonical rows from the training set through a multiplicative permutation
+__global__ void k_gather_batch(const float *Xall, const float *Yall, int64_t ntrain, int64_t first, int64_t mult,
+                               int64_t offset, int B, float *X, float *Y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)B * NPD;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / NPD, j = i % NPD;
+    const int64_t idx = (int64_t)(((unsigned __int128)(first + b) * (unsigned __int128)mult + offset) % ntrain);
+    X[i] = Xall[idx * NPD + j];
+    if (j == 0) Y[b] = 8.0f * Yall[idx];
+  }
+}
+
+// ---------------------------------------------------------------- network object
+struct Net {
+  float *theta = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  float *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *out = nullptr, *dout = nullptr;
+  float *dZ1 = nullptr, *dZ2 = nullptr, *X = nullptr, *Y = nullptr;
+  double *loss = nullptr;
+  int cap = 0;
+  std::string err;
+};
+
+static hipError_t ensure_batch(Net &n, int B) {
+  if (B <= n.cap) return hipSuccess;
+  float **bufs[] = {&n.Z1, &n.H1, &n.Z2, &n.H2, &n.dZ1, &n.dZ2};
+  for (float **b : bufs) {
+    if (*b) (void)hipFree(*b);
+    hipError_t e = hipMalloc(b, sizeof(float) * (size_t)B * NH);
+    if (e) return e;
+  }
+  float **b1s[] = {&n.out, &n.dout, &n.Y};
+  for (float **b : b1s) {
+    if (*b) (void)hipFree(*b);
+    hipError_t e = hipMalloc(b, sizeof(float) * (size_t)B);
+    if (e) return e;
+  }
+  if (n.X) (void)hipFree(n.X);
+  hipError_t e = hipMalloc(&n.X, sizeof(float) * (size_t)B * NPD);
+  if (e) return e;
+  n.cap = B;
+  return hipSuccess;
+}
+
+// forward pass of B canonical rows X (bfloat16-valued binary32 [B][128])
+static void forward(Net &n, hipStream_t s, const float *X, int B) {
+  gemm(s, 1, X, NPD, 1, n.theta + OW1, NH, 1, n.Z1, NH, B, NH, NPD, n.theta + OB1, n.H1);
+  gemm(s, 1, n.H1, NH, 1, n.theta + OW2, NH, 1, n.Z2, NH, B, NH, NH, n.theta + OB2, n.H2);
+  hipLaunchKernelGGL(k_out_layer, dim3((B + 255) / 256), dim3(256), 0, s, n.H2, n.theta, B, n.out);
+}
+
+// loss and gradient of the mean squared error against Y (= 8 kappa), into n.g
+static void backward(Net &n, hipStream_t s, const float *X, const float *Y, int B) {
+  (void)hipMemsetAsync(n.loss, 0, sizeof(double), s);
+  hipLaunchKernelGGL(k_out_grad, dim3((B + 255) / 256), dim3(256), 0, s, n.out, Y, n.theta, n.Z2, B, n.dout, n.dZ2,
+                     n.loss);
+  // W3, b3
+  hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.H2, NH, NH, n.dout, B, n.g, OW3);
+  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(256), 0, s, n.dout, B, n.g, OB3);
+  // W2 = H1^T dZ2, b2
+  gemm(s, 0, n.H1, 1, NH, n.dZ2, NH, 1, n.g + OW2, NH, NH, NH, B);
+  hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.dZ2, NH, NH, (const float *)nullptr, B, n.g, OB2);
+  // dZ1 = (dZ2 W2^T) * GELU'(Z1)
+  gemm(s, 0, n.dZ2, NH, 1, n.theta + OW2, 1, NH, n.dZ1, NH, B, NH, NH);
+  hipLaunchKernelGGL(k_mul_gelu_grad, dim3(256), dim3(256), 0, s, n.dZ1, n.Z1, (int64_t)B * NH);
+  // W1 = X^T dZ1, b1
+  gemm(s, 0, X, 1, NPD, n.dZ1, NH, 1, n.g + OW1, NH, NPD, NH, B);
+  hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.dZ1, NH, NH, (const float *)nullptr, B, n.g, OB1);
+}
+
+// ---------------------------------------------------------------- step inference
+// One work-group takes 64 interface cells at a time: the canonical 5x5x5 stencils go to
+// LDS as bfloat16, the two hidden layers run on the matrix cores (each wave 16 cells x 64
+// units), the output layer on the vector units. A cell whose stencil meets a wall, leaves
+// the domain or meets a gas / interface cell of another bubble, or whose network
+// curvature exceeds the trained range |kappa| <= 1/2, is left to the plain fit.
+template <int P>
+__global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  __shared__ short sA[64][NPD + 4];
+  __shared__ short sH[64][NH + 4];
+  __shared__ int s_cell[64], s_ok[64], s_ord[64][3], s_flip[64][3], s_lab[64];
+  __shared__ float s_ac[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
+  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nNI + nL;
+  const uint16_t *W = d.mlp_w;  // bf16: W1 [128][64], W2 [64][64], W3 [64]
+  const float *bias = d.mlp_b;  // b1 [64], b2 [64], b3
+  for (int64_t t0 = (int64_t)blockIdx.x * 64; t0 < total; t0 += (int64_t)gridDim.x * 64) {
+    if (tid < 64) {
+      const int64_t k = t0 + tid;
+      int cell = -1;
+      if (k < total) {
+        const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
+        if ((d.type[n] & TMASK) == TI) cell = (int)n;
+      }
+      s_cell[tid] = cell;
+      s_ok[tid] = cell >= 0;
+      if (cell >= 0) {
+        int x, y, z;
+        cell_xyz(p, cell, x, y, z);
+        const float ac = fminf(1.0f, fmaxf(0.0f, (float)((const R *)d.alpha)[cell]));
+        auto av = [&](int dx, int dy, int dz) {
+          const int64_t yy = nb_index_or_none(p, x, y, z, dx, dy, dz);
+          if (yy < 0) return ac;
+          const int t = d.type[yy] & TMASK;
+          return t == TG ? 0.0f : (t == TL ? 1.0f : (t == TI ? fminf(1.0f, fmaxf(0.0f, (float)((const R *)d.alpha)[yy])) : ac));
+        };
+        int order[3], flip[3];
+        canon_map(0.5f * (av(1, 0, 0) - av(-1, 0, 0)), 0.5f * (av(0, 1, 0) - av(0, -1, 0)),
+                  0.5f * (av(0, 0, 1) - av(0, 0, -1)), order, flip);
+        for (int a = 0; a < 3; a++) { s_ord[tid][a] = order[a]; s_flip[tid][a] = flip[a]; }
+        s_lab[tid] = d.label[cell];
+        s_ac[tid] = ac;
+      }
+    }
+    __syncthreads();
+    // canonical stencils into LDS
+    for (int idx = tid; idx < 64 * NPD; idx += 256) {
+      const int c = idx / NPD, j = idx % NPD;
+      float v = 0.0f;
+      const int cell = s_cell[c];
+      if (j < NF && cell >= 0) {
+        const int e[3] = {j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2};
+        int dd[3];
+        for (int a = 0; a < 3; a++) dd[s_ord[c][a]] = s_flip[c][s_ord[c][a]] ? -e[a] : e[a];
+        int x, y, z;
+        cell_xyz(p, cell, x, y, z);
+        const int64_t yy = nb_index_or_none(p, x, y, z, dd[0], dd[1], dd[2]);
+        if (yy < 0) {
+          v = s_ac[c];
+          s_ok[c] = 0;
+        } else {
+          const int t = d.type[yy] & TMASK;
+          if (t == TW) { v = s_ac[c]; s_ok[c] = 0; }
+          else if (t == TL) v = 1.0f;
+          else {
+            if (d.label[yy] != s_lab[c]) s_ok[c] = 0;
+            v = t == TG ? 0.0f : fminf(1.0f, fmaxf(0.0f, (float)((const R *)d.alpha)[yy]));
+          }
+        }
+      }
+      sA[c][j] = (short)bf16_bits(v);
+    }
+    __syncthreads();
+    // hidden layers: wave w computes cells 16w..16w+15, all 64 units
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll 1
+    for (int layer = 0; layer < 2; layer++) {
+      const int K = layer == 0 ? NPD : NH;
+      const uint16_t *Wl = layer == 0 ? W : W + NPD * NH;
+      floatx4 acc[4];
+      for (int tn = 0; tn < 4; tn++) acc[tn] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 a;
+        for (int j = 0; j < 4; j++) a[j] = layer == 0 ? sA[wave * 16 + r][k0 + kq + j] : sH[wave * 16 + r][k0 + kq + j];
+        for (int tn = 0; tn < 4; tn++) {
+          bf16x4 b;
+          for (int j = 0; j < 4; j++) b[j] = (short)Wl[(k0 + kq + j) * NH + tn * 16 + r];
+          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tn], 0, 0, 0);
+        }
+      }
+      if (layer == 1) __syncthreads();  // all waves done reading sH of layer 1
+      for (int tn = 0; tn < 4; tn++)
+        for (int j = 0; j < 4; j++) {
+          const int row = wave * 16 + kq + j, col = tn * 16 + r;
+          const float zz = acc[tn][j] + bias[layer * NH + col];
+          sH[row][col] = (short)bf16_bits(gelu(zz));
+        }
+      __syncthreads();
+    }
+    if (tid < 64 && s_cell[tid] >= 0) {
+      float acc = 0.0f;
+      for (int j = 0; j < NH; j++)
+        acc += __uint_as_float(((uint32_t)(uint16_t)sH[tid][j]) << 16) *
+               __uint_as_float(((uint32_t)W[NPD * NH + NH * NH + j]) << 16);
+      const float kap = (acc + bias[2 * NH]) * 0.125f;
+      const int cell = s_cell[tid];
+      if (s_ok[tid] && fabsf(kap) <= 0.5f) {
+        ((R *)d.kappa)[cell] = (R)kap;
+        d.cflag[cell] = (uint8_t)CF_MLPOK;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_mlp_curv(Ctx &c, hipStream_t s) {
+  const unsigned nb = list_blocks(c) < 2048 ? list_blocks(c) : 2048;
+  if (c.kp.dim != 3) return;
+  switch (c.P.precision) {
+    case 0: hipLaunchKernelGGL(k_mlp_curv<0>, dim3(nb), dim3(256), 0, s, c.kp, c.d); break;
+    case 1: hipLaunchKernelGGL(k_mlp_curv<1>, dim3(nb), dim3(256), 0, s, c.kp, c.d); break;
+    case 2: hipLaunchKernelGGL(k_mlp_curv<2>, dim3(nb), dim3(256), 0, s, c.kp, c.d); break;
+    default: hipLaunchKernelGGL(k_mlp_curv<3>, dim3(nb), dim3(256), 0, s, c.kp, c.d); break;
+  }
+}
+
+}  // namespace mf
+
+// ---------------------------------------------------------------- C ABI
+using namespace mf;
+
+struct mf_mlp : Net {};
+
+namespace {
+int fail(const std::string &m, int rc) {
+  mf::g_thread_err = m;
+  return rc;
+}
+#define MLPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess) return fail(std::string(#expr) + ": " + hipGetErrorString(_e), MF_EHIP); \
+  } while (0)
+}  // namespace
+
+extern "C" {
+
+int mf_mlp_param_count(void) { return NPARAM; }
+
+int mf_mlp_create(uint64_t init_seed, mf_mlp **out) {
+  if (!out) return fail("out is NULL", MF_EINVAL);
+  mf_mlp *m = new mf_mlp();
+  std::vector<float> th(NPARAM, 0.0f);
+  SplitMix st(init_seed, 0, 0);
+  const int fan[3] = {NF, NH, NH};
+  const int off[3] = {OW1, OW2, OW3};
+  const int cnt[3] = {NPD * NH, NH * NH, NH};
+  for (int l = 0; l < 3; l++) {
+    const double lim = 1.0 / sqrt((double)fan[l]);
+    for (int i = 0; i < cnt[l]; i++) th[off[l] + i] = (float)((2.0 * st.uniform() - 1.0) * lim);
+  }
+  for (int i = NF * NH; i < NPD * NH; i++) th[OW1 + i] = 0.0f;
+  float **bufs[] = {&m->theta, &m->m, &m->v, &m->g};
+  for (float **b : bufs) MLPCHK(hipMalloc(b, sizeof(float) * NPARAM));
+  MLPCHK(hipMalloc(&m->loss, sizeof(double)));
+  MLPCHK(hipMemcpy(m->theta, th.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice));
+  MLPCHK(hipMemset(m->m, 0, sizeof(float) * NPARAM));
+  MLPCHK(hipMemset(m->v, 0, sizeof(float) * NPARAM));
+  *out = m;
+  return MF_OK;
+}
+
+int mf_mlp_destroy(mf_mlp *m) {
+  if (!m) return MF_OK;
+  float *bufs[] = {m->theta, m->m, m->v, m->g, m->Z1, m->H1, m->Z2, m->H2, m->out, m->dout, m->dZ1, m->dZ2, m->X, m->Y};
+  for (float *b : bufs)
+    if (b) (void)hipFree(b);
+  if (m->loss) (void)hipFree(m->loss);
+  delete m;
+  return MF_OK;
+}
+
+int mf_mlp_get_params(const mf_mlp *m, float *dst) {
+  if (!m || !dst) return fail("NULL argument", MF_EINVAL);
+  MLPCHK(hipMemcpy(dst, m->theta, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+  return MF_OK;
+}
+
+int mf_mlp_set_params(mf_mlp *m, const float *src) {
+  if (!m || !src) return fail("NULL argument", MF_EINVAL);
+  MLPCHK(hipMemcpy(m->theta, src, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
+  return MF_OK;
+}
+
+int mf_mlp_generate(uint64_t seed, int64_t first, int64_t n, double noise, float *stencils, float *kappa, void *stream) {
+  if (n < 0 || (n > 0 && (!stencils || !kappa))) return fail("bad arguments", MF_EINVAL);
+  if (n == 0) return MF_OK;
+  hipStream_t s = (hipStream_t)stream;
+  float *dS = nullptr, *dK = nullptr;
+  int32_t *dst = nullptr, st = 0;
+  MLPCHK(hipMalloc(&dS, sizeof(float) * n * NF));
+  MLPCHK(hipMalloc(&dK, sizeof(float) * n));
+  MLPCHK(hipMalloc(&dst, 4));
+  MLPCHK(hipMemsetAsync(dst, 0, 4, s));
+  hipLaunchKernelGGL(k_mlp_generate, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, seed, first, n, noise, dS, dK,
+                     dst);
+  MLPCHK(hipMemcpyAsync(stencils, dS, sizeof(float) * n * NF, hipMemcpyDeviceToHost, s));
+  MLPCHK(hipMemcpyAsync(kappa, dK, sizeof(float) * n, hipMemcpyDeviceToHost, s));
+  MLPCHK(hipMemcpyAsync(&st, dst, 4, hipMemcpyDeviceToHost, s));
+  MLPCHK(hipStreamSynchronize(s));
+  (void)hipFree(dS);
+  (void)hipFree(dK);
+  (void)hipFree(dst);
+  if (st) return fail("a sample found no valid attempt", MF_ENUMERIC);
+  return MF_OK;
+}
+
+int mf_mlp_eval(const mf_mlp *mc, const float *stencils, int64_t n, float *kappa, void *stream) {
+  mf_mlp *m = const_cast<mf_mlp *>(mc);
+  if (!m || n < 0 || (n > 0 && (!stencils || !kappa))) return fail("bad arguments", MF_EINVAL);
+  if (n == 0) return MF_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t npad = (n + 63) / 64 * 64;
+  MLPCHK(ensure_batch(*m, (int)npad));
+  float *raw = nullptr;
+  MLPCHK(hipMalloc(&raw, sizeof(float) * npad * NF));
+  MLPCHK(hipMemsetAsync(raw, 0, sizeof(float) * npad * NF, s));
+  MLPCHK(hipMemcpyAsync(raw, stencils, sizeof(float) * n * NF, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_mlp_canon, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, raw, npad, m->X);
+  forward(*m, s, m->X, (int)npad);
+  std::vector<float> out(npad);
+  MLPCHK(hipMemcpyAsync(out.data(), m->out, sizeof(float) * npad, hipMemcpyDeviceToHost, s));
+  MLPCHK(hipStreamSynchronize(s));
+  (void)hipFree(raw);
+  for (int64_t i = 0; i < n; i++) kappa[i] = out[i] * 0.125f;
+  return MF_OK;
+}
+
+int mf_mlp_grad(const mf_mlp *mc, const float *stencils, const float *target8, int32_t B, float *grad, double *loss,
+                void *stream) {
+  mf_mlp *m = const_cast<mf_mlp *>(mc);
+  if (!m || B <= 0 || (B % 64) || !stencils || !target8 || !grad) return fail("bad arguments (B % 64 == 0)", MF_EINVAL);
+  hipStream_t s = (hipStream_t)stream;
+  MLPCHK(ensure_batch(*m, B));
+  float *raw = nullptr;
+  MLPCHK(hipMalloc(&raw, sizeof(float) * B * NF));
+  MLPCHK(hipMemcpyAsync(raw, stencils, sizeof(float) * B * NF, hipMemcpyHostToDevice, s));
+  MLPCHK(hipMemcpyAsync(m->Y, target8, sizeof(float) * B, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_mlp_canon, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, raw, (int64_t)B, m->X);
+  forward(*m, s, m->X, B);
+  backward(*m, s, m->X, m->Y, B);
+  MLPCHK(hipMemcpyAsync(grad, m->g, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, s));
+  double l = 0;
+  MLPCHK(hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  MLPCHK(hipStreamSynchronize(s));
+  (void)hipFree(raw);
+  if (loss) *loss = l;
+  return MF_OK;
+}
+
+int mf_mlp_train(mf_mlp *m, const mf_mlp_train_spec *sp, void *stream, double *val_rmse) {
+  if (!m || !sp || sp->struct_size != sizeof(mf_mlp_train_spec)) return fail("bad spec", MF_EINVAL);
+  if (sp->n_train < sp->batch || sp->batch <= 0 || sp->batch % 64 || sp->epochs <= 0 || sp->n_val < 0)
+    return fail("need n_train >= batch, batch % 64 == 0, epochs > 0", MF_EINVAL);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ntot = sp->n_train + sp->n_val;
+  float *raw = nullptr, *Xall = nullptr, *Yall = nullptr;
+  int32_t *dst = nullptr, st = 0;
+  MLPCHK(hipMalloc(&raw, sizeof(float) * ntot * NF));
+  MLPCHK(hipMalloc(&Xall, sizeof(float) * ntot * NPD));
+  MLPCHK(hipMalloc(&Yall, sizeof(float) * ntot));
+  MLPCHK(hipMalloc(&dst, 4));
+  MLPCHK(hipMemsetAsync(dst, 0, 4, s));
+  hipLaunchKernelGGL(k_mlp_generate, dim3((unsigned)((ntot + 127) / 128)), dim3(128), 0, s, sp->data_seed, (int64_t)0,
+                     ntot, sp->noise, raw, Yall, dst);
+  hipLaunchKernelGGL(k_mlp_canon, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, raw, ntot, Xall);
+  MLPCHK(hipFree(raw));
+  MLPCHK(ensure_batch(*m, sp->batch));
+  const int B = sp->batch;
+  const int64_t per_epoch = sp->n_train / B;
+  const int64_t T = per_epoch * sp->epochs;
+  // multiplier of the per-epoch permutation: an odd number coprime to n_train
+  auto coprime = [](int64_t a, int64_t b) {
+    while (b) { int64_t t = a % b; a = b; b = t; }
+    return a == 1;
+  };
+  SplitMix perm(sp->data_seed ^ 0x5DEECE66DULL, 1, 0);
+  int64_t t = 0;
+  for (int ep = 0; ep < sp->epochs; ep++) {
+    int64_t mult = (int64_t)(perm.u64() % (uint64_t)sp->n_train) | 1;
+    while (!coprime(mult, sp->n_train)) mult += 2;
+    const int64_t offset = (int64_t)(perm.u64() % (uint64_t)sp->n_train);
+    for (int64_t it = 0; it < per_epoch; it++, t++) {
+      hipLaunchKernelGGL(k_gather_batch, dim3(512), dim3(256), 0, s, Xall, Yall, sp->n_train, it * B, mult, offset, B,
+                         m->X, m->Y);
+      forward(*m, s, m->X, B);
+      backward(*m, s, m->X, m->Y, B);
+      const double lr = sp->lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (double)t / (double)T));
+      const float c1 = (float)(1.0 - pow(0.9, (double)(t + 1))), c2 = (float)(1.0 - pow(0.999, (double)(t + 1)));
+      hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, m->theta, m->m, m->v, m->g, NPARAM,
+                         (float)lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+    }
+    MLPCHK(hipGetLastError());
+  }
+  // validation error of kappa
+  double se = 0.0;
+  int64_t nv = 0;
+  std::vector<float> out(B), y(B);
+  for (int64_t v0 = sp->n_train; v0 + B <= ntot; v0 += B) {
+    forward(*m, s, Xall + v0 * NPD, B);
+    MLPCHK(hipMemcpyAsync(out.data(), m->out, sizeof(float) * B, hipMemcpyDeviceToHost, s));
+    MLPCHK(hipMemcpyAsync(y.data(), Yall + v0, sizeof(float) * B, hipMemcpyDeviceToHost, s));
+    MLPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < B; i++) {
+      const double e = out[i] * 0.125 - y[i];
+      se += e * e;
+      nv++;
+    }
+  }
+  MLPCHK(hipMemcpyAsync(&st, dst, 4, hipMemcpyDeviceToHost, s));
+  MLPCHK(hipStreamSynchronize(s));
+  (void)hipFree(Xall);
+  (void)hipFree(Yall);
+  (void)hipFree(dst);
+  if (st) return fail("a training sample found no valid attempt", MF_ENUMERIC);
+  if (val_rmse) *val_rmse = nv ? sqrt(se / nv) : 0.0;
+  return MF_OK;
+}
+
+}  // extern "C"
+
+// weights of a network as the bfloat16 / binary32 arrays of a context
+int mf_mlp_export_weights(const mf_mlp *m, uint16_t *w_dev, float *b_dev, hipStream_t s) {
+  std::vector<float> th(NPARAM);
+  if (hipMemcpy(th.data(), m->theta, sizeof(float) * NPARAM, hipMemcpyDeviceToHost)) return MF_EHIP;
+  std::vector<uint16_t> w(NPD * NH + NH * NH + NH);
+  for (int i = 0; i < NPD * NH; i++) w[i] = bf16_bits(th[OW1 + i]);
+  for (int i = 0; i < NH * NH; i++) w[NPD * NH + i] = bf16_bits(th[OW2 + i]);
+  for (int i = 0; i < NH; i++) w[NPD * NH + NH * NH + i] = bf16_bits(th[OW3 + i]);
+  std::vector<float> b(2 * NH + 1);
+  for (int i = 0; i < NH; i++) {
+    b[i] = th[OB1 + i];
+    b[NH + i] = th[OB2 + i];
+  }
+  b[2 * NH] = th[OB3];
+  if (hipMemcpyAsync(w_dev, w.data(), 2 * w.size(), hipMemcpyHostToDevice, s)) return MF_EHIP;
+  if (hipMemcpyAsync(b_dev, b.data(), 4 * b.size(), hipMemcpyHostToDevice, s)) return MF_EHIP;
+  if (hipStreamSynchronize(s)) return MF_EHIP;
+  return MF_OK;
+}

@@ -48,11 +48,19 @@ class MfTotals(C.Structure):
                 ("n_bubbles", C.c_int32), ("n_interface", C.c_int32), ("status", C.c_int32)]
 
 
+class MfMlpTrainSpec(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("n_train", C.c_int64), ("n_val", C.c_int64),
+                ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("noise", C.c_double), ("data_seed", C.c_uint64)]
+
+
 # every symbol include/mifoam.h declares
 EXPORTS = ["mf_abi_version", "mf_last_error", "mf_workspace_bytes", "mf_create", "mf_destroy",
            "mf_nucleate", "mf_step", "mf_sync", "mf_read_field", "mf_write_field",
            "mf_set_bubble", "mf_refresh", "mf_read_bubbles", "mf_totals_get",
-           "mf_profile_enable", "mf_profile_get"]
+           "mf_profile_enable", "mf_profile_get", "mf_mlp_param_count", "mf_mlp_create",
+           "mf_mlp_destroy", "mf_mlp_train", "mf_mlp_get_params", "mf_mlp_set_params",
+           "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_grad", "mf_attach_mlp"]
 
 _LIB = None
 
@@ -64,6 +72,9 @@ def load_library():
         return _LIB
     if not os.path.exists(LIBPATH):
         raise ImportError(f"libmifoam.so is not built ({LIBPATH}); run __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime under the same soname; load it first so that the
+    # library and PyTorch (which supplies device memory and streams) share one runtime
+    import torch  # noqa: F401
     lib = C.CDLL(LIBPATH)
     vp = C.c_void_p
     lib.mf_abi_version.restype = C.c_int
@@ -83,6 +94,16 @@ def load_library():
     lib.mf_totals_get.argtypes = [vp, C.POINTER(MfTotals)]
     lib.mf_profile_enable.argtypes = [vp, C.c_int32]
     lib.mf_profile_get.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.mf_mlp_param_count.restype = C.c_int
+    lib.mf_mlp_create.argtypes = [C.c_uint64, C.POINTER(vp)]
+    lib.mf_mlp_destroy.argtypes = [vp]
+    lib.mf_mlp_train.argtypes = [vp, C.POINTER(MfMlpTrainSpec), vp, C.POINTER(C.c_double)]
+    lib.mf_mlp_get_params.argtypes = [vp, vp]
+    lib.mf_mlp_set_params.argtypes = [vp, vp]
+    lib.mf_mlp_generate.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_double, vp, vp, vp]
+    lib.mf_mlp_eval.argtypes = [vp, vp, C.c_int64, vp, vp]
+    lib.mf_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp]
+    lib.mf_attach_mlp.argtypes = [vp, vp]
     _LIB = lib
     return lib
 
@@ -212,6 +233,9 @@ class Sim:
                     next_id=t.next_id, step=t.step, n_bubbles=t.n_bubbles,
                     n_interface=t.n_interface, status=t.status)
 
+    def attach_mlp(self, net):
+        self._check(self.lib.mf_attach_mlp(self.h, net.h))
+
     def profile(self, on=True):
         self._check(self.lib.mf_profile_enable(self.h, int(on)))
 
@@ -233,3 +257,81 @@ class Sim:
         b = self.bubbles()
         led = self.ledgers()
         return dict(liquid=liquid, dissolved=dissolved, bubble_gas=b["m"].sum(), **led)
+
+
+def _stream_ptr():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_plain(lib, rc):
+    if rc != 0:
+        msg = lib.mf_last_error(None)
+        raise MifoamError(f"{STATUS.get(rc, rc)}: {msg.decode() if msg else ''}")
+
+
+class CurvatureNet:
+    """The learned curvature closure (a libmifoam network object)."""
+
+    def __init__(self, init_seed: int = 7):
+        self.lib = load_library()
+        self.nparam = self.lib.mf_mlp_param_count()
+        h = C.c_void_p()
+        _check_plain(self.lib, self.lib.mf_mlp_create(C.c_uint64(init_seed), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mf_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.empty(self.nparam, np.float32)
+        _check_plain(self.lib, self.lib.mf_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        assert t.size == self.nparam
+        _check_plain(self.lib, self.lib.mf_mlp_set_params(self.h, t.ctypes.data))
+
+    def train(self, n_train, n_val, epochs=8, batch=4096, lr=1e-3, noise=0.01, data_seed=4):
+        spec = MfMlpTrainSpec()
+        spec.struct_size = C.sizeof(MfMlpTrainSpec)
+        spec.n_train, spec.n_val, spec.epochs, spec.batch = n_train, n_val, epochs, batch
+        spec.lr, spec.noise, spec.data_seed = lr, noise, data_seed
+        rmse = C.c_double()
+        _check_plain(self.lib, self.lib.mf_mlp_train(self.h, C.byref(spec), _stream_ptr(), C.byref(rmse)))
+        return rmse.value
+
+    def eval(self, stencils):
+        X = np.ascontiguousarray(stencils, dtype=np.float32).reshape(-1, 125)
+        out = np.empty(X.shape[0], np.float32)
+        _check_plain(self.lib, self.lib.mf_mlp_eval(self.h, X.ctypes.data, X.shape[0], out.ctypes.data,
+                                                    _stream_ptr()))
+        return out
+
+    def grad(self, stencils, target8):
+        X = np.ascontiguousarray(stencils, dtype=np.float32).reshape(-1, 125)
+        t = np.ascontiguousarray(target8, dtype=np.float32)
+        g = np.empty(self.nparam, np.float32)
+        loss = C.c_double()
+        _check_plain(self.lib, self.lib.mf_mlp_grad(self.h, X.ctypes.data, t.ctypes.data, X.shape[0],
+                                                    g.ctypes.data, C.byref(loss), _stream_ptr()))
+        return loss.value, g
+
+
+def generate_stencils(seed, first, n, noise=0.01):
+    """stencils [n,125] and exact curvature [n] from the library's GPU generator"""
+    lib = load_library()
+    X = np.empty((n, 125), np.float32)
+    k = np.empty(n, np.float32)
+    _check_plain(lib, lib.mf_mlp_generate(C.c_uint64(seed), first, n, noise, X.ctypes.data, k.ctypes.data,
+                                          _stream_ptr()))
+    return X, k
