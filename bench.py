@@ -3,12 +3,15 @@
 
 A step is one pass of the whole hot path: lattice sweep, cell conversion, bubble
 labelling and gas bookkeeping, bubble pressures, curvature and disjoining pressure.
-Two runs: populations stored in binary32 ("FP32 plain") and stored as binary16 offsets
-f_i - w_i with binary32 arithmetic ("FP16 store"). ``value`` is the whole-step MLUPS of
-the FP16-store run; the FP32 run and the ratio are reported beside it.
+Two runs: (i) populations stored in binary32 with the plain paraboloid-fit curvature
+("FP32 plain") and (ii) populations stored as binary16 offsets f_i - w_i with binary32
+arithmetic and the learned curvature closure (plain fit as fallback). ``value`` is the
+whole-step MLUPS of run (ii); run (i) and the ratio are reported beside it. The network
+of run (ii) is trained on the GPU by the library before the timed region (2M generated
+stencils by default), and its training time and validation error are reported.
 
 Prints one JSON line. Options: --gpus N (only 1), --steps K, --warmup W,
---workload NAME, --no-cpu-baseline.
+--workload NAME, --no-cpu-baseline, --mlp-train N, --mlp-epochs E.
 """
 import argparse
 import json
@@ -23,21 +26,60 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS & %HBM peak, 384^3 foam; FP16-store+MLP-curvature vs FP32 plain"
 
 
-def sweep_bytes(wl, T, prec):
-    """Algorithmic bytes of one sweep launch: every liquid / interface cell reads and
-    writes each population once (f: Q values, g: Qg values) and reads its type byte;
-    every other cell reads its type byte."""
-    import numpy as np
+BYTES_F = {"fp64": 8, "fp32": 4, "f16s": 2, "bf16s": 2, "f16s_g16": 2}
+BYTES_G = {"fp64": 8, "fp32": 4, "f16s": 4, "bf16s": 4, "f16s_g16": 2}
+
+
+def bytes_per_fluid_cell(wl, prec):
+    """Algorithmic bytes of one fluid-cell update: each population read once and written
+    once (f: Q values, g: Qg values) plus the cell's type byte."""
     Q, Qg = (9, 5) if wl["dim"] == 2 else (19, 7)
-    sf = {"fp64": 8, "fp32": 4, "f16s": 2, "bf16s": 2}[prec]
-    sg = 8 if prec == "fp64" else 4
-    n_fluid = int(np.count_nonzero((T == 1) | (T == 2)))
-    n_other = int(T.size) - n_fluid
-    per_cell = 2 * Q * sf + 2 * Qg * sg + 1
-    return n_fluid * per_cell + n_other, n_fluid, per_cell
+    return 2 * Q * BYTES_F[prec] + 2 * Qg * BYTES_G[prec] + 1
 
 
-def run_one(wl, steps, warmup, log):
+def plain_cells(T, dim):
+    """Liquid cells with no wall among their lattice neighbours: the cells the bulk
+    sweep kernel updates (interface and near-wall cells go to the list kernel)."""
+    import numpy as np
+    W = T == 3
+    nw = np.zeros_like(W)
+    dirs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+            if 0 < abs(a) + abs(b) + abs(c) <= 2]
+    if dim == 2:
+        dirs = [(0, b, c) for (a, b, c) in dirs if a == 0]
+    pad = np.pad(W, 1, constant_values=False)
+    nz, ny, nx = T.shape
+    for (dz, dy, dx) in dirs:
+        nw |= pad[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    return int(np.count_nonzero((T == 2) & ~nw))
+
+
+def sweep_bytes(wl, T, prec):
+    """Algorithmic bytes of one launch of the bulk sweep kernel: every plain liquid cell
+    costs a full update, every other cell its type byte."""
+    per_cell = bytes_per_fluid_cell(wl, prec)
+    n_plain = plain_cells(T, wl["dim"])
+    return n_plain * per_cell + (int(T.size) - n_plain), n_plain, per_cell
+
+
+def train_net(n_train, epochs, log):
+    import torch
+
+    from paper_1908_04262_amd import CurvatureNet
+
+    n_val = max(4096, n_train // 16)
+    net = CurvatureNet(7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rmse = net.train(n_train=n_train, n_val=n_val, epochs=epochs, batch=4096, lr=2e-3, data_seed=4)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"[mlp] trained on {n_train} stencils x {epochs} epochs in {dt:.1f}s, val rmse {rmse:.4f}")
+    return net, dict(n_train=n_train, n_val=n_val, epochs=epochs, seconds=round(dt, 2),
+                     val_rmse_kappa=round(rmse, 5))
+
+
+def run_one(wl, steps, warmup, log, net=None):
     import numpy as np
     import torch
 
@@ -46,6 +88,8 @@ def run_one(wl, steps, warmup, log):
 
     t0 = time.time()
     sim = Sim(wl, device=0)
+    if net is not None:
+        sim.attach_mlp(net)
     c, r, p0 = place_nuclei(wl)
     sim.nucleate(c, r, p0)
     log(f"[{wl['precision']}] created + nucleated {len(r)} nuclei in {time.time() - t0:.1f}s")
@@ -53,7 +97,7 @@ def run_one(wl, steps, warmup, log):
     sim.sync()
     log(f"[{wl['precision']}] warmup {warmup} steps done")
     T0 = sim.read("type")
-    bytes0, nf0, per_cell = sweep_bytes(wl, T0, wl["precision"])
+    bytes0, np0, per_cell = sweep_bytes(wl, T0, wl["precision"])
     sim.profile(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -61,33 +105,40 @@ def run_one(wl, steps, warmup, log):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     sim.sync()
-    sweep_ms, nsw = sim.profile_get(0)
+    bulk_ms, nsw = sim.profile_get(0)
     step_ms, nst = sim.profile_get(1)
+    spec_ms, _ = sim.profile_get(2)
     sim.profile(False)
     T1 = sim.read("type")
-    bytes1, nf1, _ = sweep_bytes(wl, T1, wl["precision"])
+    bytes1, np1, _ = sweep_bytes(wl, T1, wl["precision"])
     led = sim.ledgers()
     ncell = int(np.prod(sim.shape))
     wall = t2 - t1
-    sweep_avg_s = sweep_ms / 1e3 / max(nsw, 1)
+    bulk_avg_s = bulk_ms / 1e3 / max(nsw, 1)
     bytes_launch = 0.5 * (bytes0 + bytes1)
+    n_fluid = int(np.count_nonzero((T1 == 1) | (T1 == 2)))
     res = dict(
         precision=wl["precision"],
+        curvature=wl["curvature"],
         mlups=ncell * steps / wall / 1e6,
         ms_per_step=wall * 1e3 / steps,
-        sweep_ms=sweep_avg_s * 1e3,
+        bulk_sweep_ms=bulk_avg_s * 1e3,
+        special_sweep_ms=spec_ms / max(nsw, 1),
         step_event_ms=step_ms / max(nst, 1),
-        sweep_bytes=bytes_launch,
-        sweep_gbs=bytes_launch / sweep_avg_s / 1e9,
+        bulk_sweep_bytes=bytes_launch,
+        bulk_sweep_gbs=bytes_launch / bulk_avg_s / 1e9,
         bytes_per_fluid_cell=per_cell,
-        n_fluid=0.5 * (nf0 + nf1),
+        n_plain=0.5 * (np0 + np1),
+        n_fluid=n_fluid,
         n_interface=int(np.count_nonzero(T1 == 1)),
         n_bubbles=led["n_bubbles"],
         status=led["status"],
     )
-    # whole-step algorithmic HBM fraction (sweep bytes per step over wall time)
-    res["hbm_frac_step"] = bytes_launch / (wall / steps) / 1e9 / HBM_PEAK_GBS
-    log(f"[{wl['precision']}] {json.dumps(res)}")
+    # whole-step algorithmic HBM fraction: full-update bytes of every fluid cell per step
+    # over the wall time of a step
+    step_bytes = n_fluid * per_cell + (ncell - n_fluid)
+    res["hbm_frac_step"] = step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS
+    log(f"[{wl['precision']}/{wl['curvature']}] {json.dumps(res)}")
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -131,11 +182,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3_foam_384")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mlp-train", type=int, default=1966080)
+    ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the sweep would shard).", file=sys.stderr)
+              "(the sweep shards by z-slabs; that path is not built).", file=sys.stderr)
         sys.exit(2)
 
     def log(msg):
@@ -145,9 +198,19 @@ def main():
     from synth import workload
 
     wl = workload(a.workload)
-    r32 = run_one(dict(wl, precision="fp32"), a.steps, a.warmup, log)
-    r16 = run_one(dict(wl, precision="f16s"), a.steps, a.warmup, log)
+    r32 = run_one(dict(wl, precision="fp32", curvature="plain"), a.steps, a.warmup, log)
+    net, train_info = train_net(a.mlp_train, a.mlp_epochs, log)
+    r16 = run_one(dict(wl, precision="f16s_g16", curvature="mlp"), a.steps, a.warmup, log, net=net)
+    r16f = run_one(dict(wl, precision="f16s", curvature="mlp"), a.steps, a.warmup, log, net=net)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
+
+    def brief(r):
+        return {"mlups": round(r["mlups"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                "hbm_frac_step": round(r["hbm_frac_step"], 4),
+                "bulk_sweep_gbs": round(r["bulk_sweep_gbs"], 1),
+                "bulk_sweep_ms": round(r["bulk_sweep_ms"], 4),
+                "special_sweep_ms": round(r["special_sweep_ms"], 4)}
+
     out = {
         "metric": METRIC,
         "value": round(r16["mlups"], 2),
@@ -164,24 +227,26 @@ def main():
         "config": {
             "workload": f"{wl['name']}: {wl['nx']}x{wl['ny']}x{wl['nz']} D3Q19+D3Q7 power-law "
                         f"foam, {wl['nuclei']['n']} bubbles r~U[2,4], seed {wl['seed']}",
-            "storage": "f16 offsets f-w (value); fp32 run reported as fp32_plain",
-            "curvature": "plain paraboloid fit",
+            "storage": "f and g as binary16 offsets, binary32 arithmetic (value); "
+                       "binary32 (fp32_plain)",
+            "curvature": "learned 125-64-64-1 MLP with plain-fit fallback (value); "
+                         "plain fit (fp32_plain)",
         },
+        "mlp_training": train_info,
         "hbm_frac_step": round(r16["hbm_frac_step"], 4),
-        "fp32_plain": {"mlups": round(r32["mlups"], 2), "ms_per_step": round(r32["ms_per_step"], 4),
-                       "hbm_frac_step": round(r32["hbm_frac_step"], 4),
-                       "sweep_gbs": round(r32["sweep_gbs"], 1)},
+        "fp32_plain": brief(r32),
+        "f16_f_only_mlp": brief(r16f),
         "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep<3,2> (f16 offsets)",
-            "achieved": round(r16["sweep_gbs"], 1),
+            "kernel": "k_sweep_vec<3,4,4> (bulk sweep, binary16 f and g)",
+            "achieved": round(r16["bulk_sweep_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(r16["sweep_gbs"] / HBM_PEAK_GBS, 4),
+            "frac": round(r16["bulk_sweep_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "bytes_per_launch": r16["sweep_bytes"],
-            "avg_launch_ms": round(r16["sweep_ms"], 4),
+            "bytes_per_launch": r16["bulk_sweep_bytes"],
+            "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
         },
         "cpu_baseline": cpu,
     }

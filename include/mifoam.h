@@ -20,7 +20,7 @@
  *   - dissolved gas on D2Q5 / D3Q7 with a Henry's-law interface condition and per-bubble
  *     gas flux (Sec. 3.1-3.2, Eqs. diffusion, diffusionconst, gascurrent, henryslaw,
  *     reconstructdiffusion);
- *   - bubble tracking by flood fill with merge / split bookkeeping (Sec. 3.6).
+ *   - bubble tracking by flood fill with merge / split bookkeeping (Sec. 3.5).
  *
  * Lattice units throughout. Cell index n = x + nx*(y + ny*z); grids include the wall
  * layer of every closed axis. Device work is enqueued on the stream given to
@@ -55,7 +55,10 @@ enum mf_precision {
   MF_FP64 = 0,     /* f, g and all cell fields in binary64 */
   MF_FP32 = 1,     /* f, g and cell fields in binary32; bubble table in binary64 */
   MF_F16S = 2,     /* f stored as binary16 offsets f_i - w_i, arithmetic in binary32 */
-  MF_BF16S = 3     /* f stored as bfloat16 offsets f_i - w_i, arithmetic in binary32 */
+  MF_BF16S = 3,    /* f stored as bfloat16 offsets f_i - w_i, arithmetic in binary32 */
+  MF_F16S_G16 = 4  /* f as in MF_F16S; g stored as binary16 scaled offsets
+                      (g_i - w_i c0) / c0 (c0 = initial concentration, or k_H p_atm
+                      when c0 = 0), arithmetic in binary32 */
 };
 
 enum mf_rheology { MF_NEWTONIAN = 0, MF_POWER_LAW = 1 };
@@ -151,7 +154,7 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
 /* Destroy; frees only memory the library allocated. NULL is accepted. */
 int mf_destroy(mf_ctx *ctx);
 
-/* Nucleation (Sec. 3.5): n spheres (disks in 2D) with centres [n][3] (z ignored in
+/* Nucleation (Sec. 3.4): n spheres (disks in 2D) with centres [n][3] (z ignored in
  * 2D), radii [n] and initial pressures p0 [n] (host arrays). Each is voxelised with 8
  * sample points per axis and cell; nucleus k gets id k+1; overlapping nuclei merge to
  * the smaller id. Gas mass = p0 V / RT (Eq. idealgas). Valid once, before mf_step
@@ -174,7 +177,8 @@ int mf_sync(mf_ctx *ctx);
 int mf_read_field(mf_ctx *ctx, int32_t field, void *dst, size_t dst_bytes, int32_t dst_on_device);
 
 /* Overwrite a field from host memory (hand-built test states); same layout as
- * mf_read_field. Allowed before the first mf_step. Call mf_refresh afterwards. */
+ * mf_read_field. Allowed before the first mf_step. Call mf_refresh afterwards. A type
+ * field must keep walls on the outer layer of every closed axis (MF_EINVAL otherwise). */
 int mf_write_field(mf_ctx *ctx, int32_t field, const void *src, size_t src_bytes);
 
 /* Set one bubble-table entry (hand-built test states). */
@@ -246,9 +250,12 @@ int mf_mlp_grad(const mf_mlp *m, const float *stencils, const float *target8, in
  * parameters); the weights are copied, the network may be destroyed afterwards. */
 int mf_attach_mlp(mf_ctx *ctx, const mf_mlp *m);
 
-/* Time of the last mf_step window in milliseconds per launch of the named kernel
- * group, measured with HIP events on the context stream: group 0 = lattice sweep,
- * 1 = whole step. Valid after mf_profile_enable(ctx, 1) and a completed mf_step. */
+/* Time spent in a kernel group over the steps since mf_profile_enable(ctx, 1), in
+ * milliseconds (total) with the number of steps timed, measured with HIP events on the
+ * context stream: group 0 = the bulk lattice sweep (the whole sweep on domains that
+ * use the per-cell kernel), 1 = whole step, 2 = the interface / near-wall sweep kernel
+ * (zero time on domains that use the per-cell kernel). At most 4096 steps are timed
+ * per enable; a further mf_step returns MF_ESTATE until the next enable. */
 int mf_profile_enable(mf_ctx *ctx, int32_t on);
 int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launches);
 

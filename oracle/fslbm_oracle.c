@@ -13,8 +13,8 @@
  * or fusion. Build with -O2 -ffp-contract=off -fno-fast-math so that every + - * / sqrt
  * is one correctly rounded IEEE binary64 operation.
  *
- * Step order (the readings of the paper that fix what the paper leaves open are
- * listed in DESIGN.md, "Readings"):
+ * Step order (where the paper leaves a choice open, the comment of the pass states
+ * the reading taken):
  *   S1  stream f (Eq. streaming), bounce-back at walls (Sec. 2), gas-side
  *       reconstruction at interface cells (Eq. reconstruct) with the gas density
  *       of Eq. rhob / rhobplusdisjoining;
@@ -24,7 +24,7 @@
  *   S4  moments (Sec. 2), BGK collision (Eqs. collision, equilibrium) with tau from
  *       Eq. tau or the power-law limit of Eq. carreauTau; ADE collision (Eq. diffusion);
  *   S5-S7 cell-type conversion and excess-mass redistribution (Sec. 2.1, last paragraph);
- *   S8  bubble labelling by flood fill with merge/split bookkeeping (Sec. 3.6);
+ *   S8  bubble labelling by flood fill with merge/split bookkeeping (Sec. 3.5);
  *   S9  ideal-gas bubble pressure (Eq. idealgas);
  *   S10 interface curvature (normal + paraboloid fit, PLIC points);
  *   S11 disjoining pressure by ray traversal (Sec. 3.3, Appendix A, Algorithm 1).
@@ -635,7 +635,7 @@ static int cmp_entry(const void *a, const void *b) {
 /* S8 + S9. Connected components of the gas and interface cells under the lattice
  * neighbourhood, visited in ascending cell order so that each component's root is its
  * smallest cell index. Bubble gas is carried to the new components in proportion to
- * the volume each old bubble leaves in them (Sec. 3.6); components that touch the
+ * the volume each old bubble leaves in them (Sec. 3.5); components that touch the
  * headspace join the atmosphere (id 0, fixed pressure). Pinned against
  * scipy.ndimage.label and hand-worked merge / split cases. */
 static int relabel(OS *s, int apply_flux) {
@@ -879,7 +879,7 @@ void or_destroy(void *h) {
 
 const char *or_error(void *h) { return ((OS *)h)->errmsg; }
 
-/* S0. Nucleation (Sec. 3.5): each sphere (3D) or disk (2D) is voxelised with 8 sample
+/* S0. Nucleation (Sec. 3.4): each sphere (3D) or disk (2D) is voxelised with 8 sample
  * points per axis per cell; fully covered cells become gas, partly covered cells
  * interface cells with alpha = 1 - covered fraction. Liquid cells that then touch gas
  * become interface cells with alpha = 1. The initial gas mass is p0 V / RT (Eq.

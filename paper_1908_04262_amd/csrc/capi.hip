@@ -24,7 +24,7 @@ namespace {
 std::string &g_err = mf::g_thread_err;
 
 struct OpsTable {
-  void (*sweep)(Ctx &, hipStream_t);
+  void (*sweep)(Ctx &, hipStream_t, hipEvent_t);
   void (*convert)(Ctx &, hipStream_t);
   void (*label)(Ctx &, hipStream_t, int);
   void (*geometry)(Ctx &, hipStream_t);
@@ -48,19 +48,21 @@ OpsTable ops_for(int dim, int prec) {
       case 0: return make_ops<2, 0>();
       case 1: return make_ops<2, 1>();
       case 2: return make_ops<2, 2>();
-      default: return make_ops<2, 3>();
+      case 3: return make_ops<2, 3>();
+      default: return make_ops<2, 4>();
     }
   }
   switch (prec) {
     case 0: return make_ops<3, 0>();
     case 1: return make_ops<3, 1>();
     case 2: return make_ops<3, 2>();
-    default: return make_ops<3, 3>();
+    case 3: return make_ops<3, 3>();
+    default: return make_ops<3, 4>();
   }
 }
 
 size_t sf_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
-size_t sg_bytes(int prec) { return prec == 0 ? 8 : 4; }
+size_t sg_bytes(int prec) { return prec == 0 ? 8 : (prec == 4 ? 2 : 4); }
 size_t r_bytes(int prec) { return prec == 0 ? 8 : 4; }
 int next_pow2(int v) {
   int p = 1;
@@ -97,6 +99,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.blist = cv.take<int32_t>(Np * 4);
   d.nilist = cv.take<int32_t>(Np * 4);
   d.l2ilist = cv.take<int32_t>(Np * 4);
+  d.wmask = cv.take<uint32_t>(Np * 4);
   d.cnt = cv.take<int32_t>(C_NCOUNT * 4);
   d.status = cv.take<int32_t>(4);
   const size_t cap = (size_t)kp.cap;
@@ -137,7 +140,7 @@ int validate(const mf_params *p, std::string &why) {
   const int nz = p->dim == 2 ? 1 : p->nz;
   if (p->nx < 3 || p->ny < 3 || nz < 1 || (p->dim == 3 && nz < 3)) { why = "grid too small"; return MF_EINVAL; }
   if ((double)p->nx * p->ny * nz >= 2147483647.0) { why = "grid exceeds 2^31 cells"; return MF_EINVAL; }
-  if (p->precision < 0 || p->precision > 3) { why = "unknown precision"; return MF_EINVAL; }
+  if (p->precision < 0 || p->precision > 4) { why = "unknown precision"; return MF_EINVAL; }
   if (p->rheology != MF_NEWTONIAN && p->rheology != MF_POWER_LAW) { why = "unknown rheology"; return MF_EINVAL; }
   if (p->curvature != MF_CURV_PLAIN && p->curvature != MF_CURV_MLP) { why = "unknown curvature mode"; return MF_EINVAL; }
   if (p->curvature == MF_CURV_MLP && p->dim != 3) { why = "the learned curvature works on 5x5x5 stencils (3D only)"; return MF_EUNSUPPORTED; }
@@ -186,6 +189,12 @@ KP make_kp(const mf_params &P) {
   k.pl_gdot_ref = P.pl_gdot_ref;
   k.tau_min = P.tau_min;
   k.tau_max = P.tau_max;
+  double gs = k.c0 > 0.0 ? k.c0 : P.kH * P.p_atm;
+  if (!(gs > 0.0)) gs = 1.0;
+  k.gsc = (float)gs;
+  k.ginv = (float)(1.0 / gs);
+  k.pl_l2nu3 = P.pl_nu_ref > 0.0 ? (float)log2(3.0 * P.pl_nu_ref) : 0.0f;
+  k.pl_kg = P.pl_gdot_ref > 0.0 ? (float)(2.1213203435596424 / P.pl_gdot_ref) : 0.0f;
   return k;
 }
 
@@ -224,7 +233,8 @@ void reset_counters(Ctx *c) { hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3
 
 // per-step event pairs when profiling
 struct Prof {
-  std::vector<hipEvent_t> ev;  // 4 per step: step start, sweep start, sweep end, step end
+  std::vector<hipEvent_t> ev;  // 5 per step: step start, sweep start, bulk sweep end,
+                               // interface sweep end, step end
   size_t used = 0;
 };
 
@@ -376,23 +386,24 @@ int mf_step(mf_ctx *c, int32_t nsteps) {
   for (int k = 0; k < nsteps; k++) {
     hipEvent_t *ev = nullptr;
     if (c->prof) {
-      if (c->prof_ev.used + 4 > c->prof_ev.ev.size()) {
+      if (c->prof_ev.used + 5 > c->prof_ev.ev.size()) {
         c->err = "profiling event pool exhausted; call mf_profile_get";
         return MF_ESTATE;
       }
       ev = &c->prof_ev.ev[c->prof_ev.used];
-      c->prof_ev.used += 4;
+      c->prof_ev.used += 5;
       (void)hipEventRecord(ev[0], c->stream);
     }
     reset_counters(c);
+    c->ops.build_lists(*c, c->stream);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    c->ops.sweep(*c, c->stream);
-    if (ev) (void)hipEventRecord(ev[2], c->stream);
+    c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr);
+    if (ev) (void)hipEventRecord(ev[3], c->stream);
     c->cur ^= 1;
     c->ops.convert(*c, c->stream);
     c->ops.label(*c, c->stream, 1);
     c->ops.geometry(*c, c->stream);
-    if (ev) (void)hipEventRecord(ev[3], c->stream);
+    if (ev) (void)hipEventRecord(ev[4], c->stream);
     c->step++;
   }
   c->stepped = c->stepped || nsteps > 0;
@@ -442,6 +453,21 @@ int mf_write_field(mf_ctx *c, int32_t field, const void *src, size_t src_bytes) 
   const size_t need = field_bytes(c, field);
   if (!need || field == MF_FIELD_CONC) { c->err = "field cannot be written"; return MF_EINVAL; }
   if (src_bytes < need) { c->err = "source too small"; return MF_EINVAL; }
+  if (field == MF_FIELD_TYPE) {
+    // the outer layer of every closed axis is a wall layer (the sweep relies on it)
+    const uint8_t *t = (const uint8_t *)src;
+    const int nx = c->kp.nx, ny = c->kp.ny, nz = c->kp.nz;
+    for (int z = 0; z < nz; z++)
+      for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) {
+          const bool face = (!c->kp.per[0] && (x == 0 || x == nx - 1)) || (!c->kp.per[1] && (y == 0 || y == ny - 1)) ||
+                            (c->kp.dim == 3 && !c->kp.per[2] && (z == 0 || z == nz - 1));
+          if (face && (t[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)] & 3) != MF_WALL) {
+            c->err = "cells on the outer layer of a closed axis must be walls";
+            return MF_EINVAL;
+          }
+        }
+  }
   void *stage = nullptr;
   HIPCHK(c, hipMalloc(&stage, need));
   hipError_t e = hipMemcpyAsync(stage, src, need, hipMemcpyHostToDevice, c->stream);
@@ -553,7 +579,7 @@ int mf_profile_enable(mf_ctx *c, int32_t on) {
   if (!c) return MF_EINVAL;
   c->prof = on != 0;
   if (c->prof && c->prof_ev.ev.empty()) {
-    c->prof_ev.ev.resize(4 * 4096);
+    c->prof_ev.ev.resize(5 * 4096);
     for (auto &e : c->prof_ev.ev) HIPCHK(c, hipEventCreate(&e));
   }
   c->prof_ev.used = 0;
@@ -562,14 +588,15 @@ int mf_profile_enable(mf_ctx *c, int32_t on) {
 
 int mf_profile_get(mf_ctx *c, int32_t group, double *ms_total, int64_t *launches) {
   if (!c || !ms_total || !launches) return MF_EINVAL;
-  if (group != 0 && group != 1) { c->err = "group must be 0 (sweep) or 1 (step)"; return MF_EINVAL; }
+  if (group < 0 || group > 2) { c->err = "group must be 0 (bulk sweep), 1 (step) or 2 (interface sweep)"; return MF_EINVAL; }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double tot = 0.0;
   int64_t nl = 0;
-  for (size_t k = 0; k + 4 <= c->prof_ev.used; k += 4) {
+  static const int from[3] = {1, 0, 2}, to[3] = {2, 4, 3};
+  for (size_t k = 0; k + 5 <= c->prof_ev.used; k += 5) {
     float ms = 0.0f;
-    hipEvent_t a = group == 0 ? c->prof_ev.ev[k + 1] : c->prof_ev.ev[k];
-    hipEvent_t b = group == 0 ? c->prof_ev.ev[k + 2] : c->prof_ev.ev[k + 3];
+    hipEvent_t a = c->prof_ev.ev[k + from[group]];
+    hipEvent_t b = c->prof_ev.ev[k + to[group]];
     HIPCHK(c, hipEventElapsedTime(&ms, a, b));
     tot += ms;
     nl++;

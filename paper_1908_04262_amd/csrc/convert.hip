@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
         lab = d.label[n];
         R gv[L::Qg], dc;
 #pragma unroll
-        for (int i = 0; i < L::Qg; ++i) gv[i] = g[(int64_t)i * p.Np + n];
+        for (int i = 0; i < L::Qg; ++i) gv[i] = GCodec<P>::dec(g[(int64_t)i * p.Np + n], p);
         sg = Arith<D, P>::conc(gv, R(p.c0), dc);
       }
     } else if (k < total) {
@@ -194,8 +194,10 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
       R gv[L::Qg], dcz;
 #pragma unroll
       for (int i = 0; i < L::Qg; ++i) {
-        gv[i] = Arith<D, P>::geqv(i, cH, cH - R(p.c0), ubx, uby, ubz);
-        g[(int64_t)i * p.Np + n] = gv[i];
+        // the bubble gives up exactly the gas that is stored
+        const SG st = GCodec<P>::enc(Arith<D, P>::geqv(i, cH, cH - R(p.c0), ubx, uby, ubz), p);
+        g[(int64_t)i * p.Np + n] = st;
+        gv[i] = GCodec<P>::dec(st, p);
       }
       sg = Arith<D, P>::conc(gv, R(p.c0), dcz);
       ((R *)d.rho)[n] = rb;

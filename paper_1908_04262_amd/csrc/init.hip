@@ -1,4 +1,4 @@
-// Initial state, nucleation (Sec. 3.5), list rebuilds and field transfer.
+// Initial state, nucleation (Sec. 3.4), list rebuilds and field transfer.
 #include "lbm_math.h"
 
 namespace mf {
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_init_box(KP p, DA d, int gas_from) {
         f[(int64_t)i * p.Np + n] = FCodec<P, D>::enc((t == TW || P != 0) ? R(0) : R(L::w[i]), i);
 #pragma unroll
       for (int i = 0; i < L::Qg; ++i)
-        g[(int64_t)i * p.Np + n] = (t == TW || P != 0) ? R(0) : R(L::wg[i] * p.c0);
+        g[(int64_t)i * p.Np + n] = GCodec<P>::enc((t == TW || P != 0) ? R(0) : R(L::wg[i] * p.c0), p);
     }
     const R one = t == TL ? R(1) : R(0);
     ((R *)d.alpha)[n] = one;
@@ -50,22 +50,24 @@ __global__ __launch_bounds__(256) void k_init_box(KP p, DA d, int gas_from) {
   }
 }
 
-// static flag: the cell touches a wall through a lattice direction
+// static flags: the cell touches a wall through a lattice direction (type bit), and the
+// directions i whose source x - e_i is a wall (bit mask)
 template <int D>
 __global__ __launch_bounds__(256) void k_nearwall(KP p, DA d) {
   using L = Lat<D>;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x) {
     const uint8_t t = d.type[n] & TMASK;
-    bool nw = false;
+    uint32_t wm = 0;
     if (t != TW) {
       int x, y, z;
       cell_xyz(p, n, x, y, z);
       for (int i = 1; i < L::Q; ++i) {
-        const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-        if ((d.type[yy] & TMASK) == TW) nw = true;
+        const int64_t s = nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
+        if ((d.type[s] & TMASK) == TW) wm |= 1u << i;
       }
     }
-    d.type[n] = t | (nw ? NEARWALL : 0);
+    d.wmask[n] = wm;
+    d.type[n] = t | (wm ? NEARWALL : 0);
   }
 }
 
@@ -181,15 +183,73 @@ __global__ __launch_bounds__(256) void k_nuc_fix2(KP p, DA d) {
 
 // interface and bubble lists of the current types (the sweep builds them every step;
 // this full pass serves initial and hand-written states)
+// Interface list (type I) and bubble list (gas or interface with a non-zero bubble id),
+// each in cell order within a chunk of LIST_CHUNK cells per block: a first pass counts,
+// one atomic per block and list reserves the block's range, a second pass writes.
+constexpr int LIST_CHUNK = 16384;
+
+__device__ __forceinline__ void list_preds(const KP &p, const DA &d, int64_t n, bool &pi, bool &pb) {
+  pi = pb = false;
+  if (n >= p.N) return;
+  const int t = d.type[n] & TMASK;
+  pi = t == TI;
+  pb = (t == TG || t == TI) && d.label[n] != 0;
+}
+
 __global__ __launch_bounds__(256) void k_build_lists(KP p, DA d) {
-  for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x; n0 < p.N; n0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t n = n0 + threadIdx.x;
-    const bool in = n < p.N;
-    const int t = in ? d.type[n] & TMASK : TW;
-    const bool gi = in && (t == TG || t == TI);
-    const int32_t lab = gi ? d.label[n] : NOLAB;
-    wave_append(d.ilist, d.cnt + C_I, in && t == TI, (int32_t)n);
-    wave_append(d.blist, d.cnt + C_B, gi && lab != 0, (int32_t)n);
+  __shared__ int s_w[2][4];
+  __shared__ int s_base[2];
+  const int64_t c0 = (int64_t)blockIdx.x * LIST_CHUNK;
+  const int64_t c1 = c0 + LIST_CHUNK < p.N ? c0 + LIST_CHUNK : p.N;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  int ci = 0, cb = 0;
+  for (int64_t n = c0 + threadIdx.x; n < c1; n += 256) {
+    bool pi, pb;
+    list_preds(p, d, n, pi, pb);
+    ci += pi;
+    cb += pb;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    ci += __shfl_xor(ci, o);
+    cb += __shfl_xor(cb, o);
+  }
+  if (lane == 0) {
+    s_w[0][w] = ci;
+    s_w[1][w] = cb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int ti = s_w[0][0] + s_w[0][1] + s_w[0][2] + s_w[0][3];
+    const int tb = s_w[1][0] + s_w[1][1] + s_w[1][2] + s_w[1][3];
+    s_base[0] = ti ? atomicAdd(d.cnt + C_I, ti) : 0;
+    s_base[1] = tb ? atomicAdd(d.cnt + C_B, tb) : 0;
+  }
+  __syncthreads();
+  int oi = s_base[0], ob = s_base[1];
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int64_t n0 = c0; n0 < c1; n0 += 256) {
+    bool pi, pb;
+    list_preds(p, d, n0 + threadIdx.x, pi, pb);
+    const unsigned long long bi = __ballot(pi), bb = __ballot(pb);
+    __syncthreads();  // the previous iteration has read s_w
+    if (lane == 0) {
+      s_w[0][w] = __popcll(bi);
+      s_w[1][w] = __popcll(bb);
+    }
+    __syncthreads();
+    int pre_i = 0, pre_b = 0, all_i = 0, all_b = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (k < w) {
+        pre_i += s_w[0][k];
+        pre_b += s_w[1][k];
+      }
+      all_i += s_w[0][k];
+      all_b += s_w[1][k];
+    }
+    if (pi) d.ilist[oi + pre_i + __popcll(bi & lt)] = (int32_t)(n0 + threadIdx.x);
+    if (pb) d.blist[ob + pre_b + __popcll(bb & lt)] = (int32_t)(n0 + threadIdx.x);
+    oi += all_i;
+    ob += all_b;
   }
 }
 
@@ -228,7 +288,7 @@ __global__ __launch_bounds__(256) void k_read(KP p, DA d, int cur, int field, do
         double c = 0.0;
         if (t == TL || t == TI) {
           R gv[L::Qg], dc;
-          for (int i = 0; i < L::Qg; ++i) gv[i] = g[(int64_t)i * p.Np + n];
+          for (int i = 0; i < L::Qg; ++i) gv[i] = GCodec<P>::dec(g[(int64_t)i * p.Np + n], p);
           c = (double)Arith<D, P>::conc(gv, R(p.c0), dc);
           if (P != 0) c = p.c0 + (double)dc;
         }
@@ -242,7 +302,7 @@ __global__ __launch_bounds__(256) void k_read(KP p, DA d, int cur, int field, do
         break;
       case MF_FIELD_G:
         for (int i = 0; i < L::Qg; ++i)
-          out[(int64_t)i * p.N + n] = (double)g[(int64_t)i * p.Np + n] + (P != 0 ? L::wg[i] * p.c0 : 0.0);
+          out[(int64_t)i * p.N + n] = (double)GCodec<P>::dec(g[(int64_t)i * p.Np + n], p) + (P != 0 ? L::wg[i] * p.c0 : 0.0);
         break;
     }
   }
@@ -273,7 +333,7 @@ __global__ __launch_bounds__(256) void k_write(KP p, DA d, int cur, int field, c
         break;
       case MF_FIELD_G:
         for (int i = 0; i < L::Qg; ++i)
-          g[(int64_t)i * p.Np + n] = (SG)(in[(int64_t)i * p.N + n] - (P != 0 ? L::wg[i] * p.c0 : 0.0));
+          g[(int64_t)i * p.Np + n] = GCodec<P>::enc((R)(in[(int64_t)i * p.N + n] - (P != 0 ? L::wg[i] * p.c0 : 0.0)), p);
         break;
     }
   }
@@ -317,7 +377,8 @@ void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn) {
 
 template <int D, int P>
 void Ops<D, P>::build_lists(Ctx &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_lists, dim3(grid_blocks(c)), dim3(256), 0, s, c.kp, c.d);
+  const int64_t nb = (c.kp.N + LIST_CHUNK - 1) / LIST_CHUNK;
+  hipLaunchKernelGGL(k_build_lists, dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d);
 }
 
 template <int D, int P>
@@ -328,8 +389,9 @@ void Ops<D, P>::read_field(Ctx &c, hipStream_t s, int field, double *dst_dev) {
 template <int D, int P>
 void Ops<D, P>::write_field(Ctx &c, hipStream_t s, int field, const double *src_dev) {
   hipLaunchKernelGGL((k_write<D, P>), dim3(grid_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur, field, src_dev);
-  if (field == MF_FIELD_TYPE)
+  if (field == MF_FIELD_TYPE) {
     hipLaunchKernelGGL((k_nearwall<D>), dim3(grid_blocks(c)), dim3(256), 0, s, c.kp, c.d);
+  }
 }
 
 #define MF_INST(D, P)                                                                  \

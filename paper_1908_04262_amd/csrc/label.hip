@@ -1,4 +1,4 @@
-// Bubble tracking (Sec. 3.6): every step the gas and interface cells are grouped into
+// Bubble tracking (Sec. 3.5): every step the gas and interface cells are grouped into
 // connected components under the lattice neighbourhood (flood fill, here a lock-free
 // union-find whose roots are the smallest cell index of each component), and each
 // bubble's gas is carried over merges and splits in proportion to the volume it leaves

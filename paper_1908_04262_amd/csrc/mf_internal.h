@@ -57,12 +57,14 @@ template <> struct Lat<3> {
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 // ------------------------------------------------------------------ precision
-// P = 0 binary64 throughout; 1 binary32; 2 binary16 offsets f - w; 3 bfloat16 offsets.
+// P = 0 binary64 throughout; 1 binary32; 2 binary16 offsets f - w; 3 bfloat16 offsets;
+// 4 binary16 offsets for f and binary16 scaled offsets (g - w c0) / s_g for g.
 template <int P> struct Prec;
 template <> struct Prec<0> { using R = double; using SF = double; using SG = double; };
 template <> struct Prec<1> { using R = float; using SF = float; using SG = float; };
 template <> struct Prec<2> { using R = float; using SF = _Float16; using SG = float; };
 template <> struct Prec<3> { using R = float; using SF = uint16_t; using SG = float; };
+template <> struct Prec<4> { using R = float; using SF = _Float16; using SG = _Float16; };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
@@ -82,12 +84,12 @@ template <int P, int D> struct FCodec {
   static constexpr bool SHIFT = P != 0;
   static __device__ __forceinline__ R dec(SF s, int) {
     if constexpr (P == 0 || P == 1) return s;
-    else if constexpr (P == 2) return (float)s;
+    else if constexpr (P == 2 || P == 4) return (float)s;
     else return bf16_to_f32(s);
   }
   static __device__ __forceinline__ SF enc(R v, int) {
     if constexpr (P == 0 || P == 1) return v;
-    else if constexpr (P == 2) return (_Float16)v;
+    else if constexpr (P == 2 || P == 4) return (_Float16)v;
     else return f32_to_bf16(v);
   }
   // full population value in binary64 (field transfer)
@@ -98,6 +100,23 @@ template <int P, int D> struct FCodec {
   static __device__ __forceinline__ SF from_full(double v, int i) {
     if constexpr (P == 0) return v;
     else return enc((R)(v - Lat<D>::w[i]), i);
+  }
+};
+
+// Dissolved-gas codec: instances 1-3 store the binary32 offsets g_i - w_i c0 as they
+// are; instance 4 stores them divided by s_g (the initial concentration) in binary16,
+// so that the relative precision of the stored offsets does not depend on the level
+// of dissolved gas.
+template <int P> struct GCodec {
+  using R = typename Prec<P>::R;
+  using SG = typename Prec<P>::SG;
+  template <class K> static __device__ __forceinline__ R dec(SG s, const K &p) {
+    if constexpr (P == 4) return (float)s * p.gsc;
+    else return s;
+  }
+  template <class K> static __device__ __forceinline__ SG enc(R v, const K &p) {
+    if constexpr (P == 4) return (_Float16)(v * p.ginv);
+    else return (SG)v;
   }
 };
 
@@ -114,6 +133,9 @@ struct KP {
   double omega, omega_g;
   double sigma, kH, RT, k_pi, d_max, p_atm, q, eps, c0;
   double pl_n, pl_nu_ref, pl_gdot_ref, tau_min, tau_max;
+  float gsc, ginv;  // dissolved-gas storage scale s_g and 1/s_g (instance 4)
+  float pl_l2nu3;   // log2(3 nu_ref) (power law, binary32 instances)
+  float pl_kg;      // (3 / sqrt 2) / gdot_ref: shear rate = pl_kg |Pi_neq| / (rho tau) gdot_ref
 };
 
 struct DA {
@@ -122,6 +144,7 @@ struct DA {
   void *M, *alpha, *rho, *ux, *uy, *uz, *kappa, *Pi, *exc, *mx, *my, *mz, *soff;
   int32_t *label, *parent;
   int32_t *ilist, *blist, *nilist, *l2ilist;
+  uint32_t *wmask;            // static: bit i set when the source x - e_i of the cell is a wall
   int32_t *cnt;
   int32_t *status;
   // bubble table
@@ -177,18 +200,6 @@ __device__ __host__ __forceinline__ double fx_to_double(__int128 v) { return (do
 
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-// append value for every lane with pred set; called by the whole wave
-__device__ __forceinline__ void wave_append(int32_t *list, int32_t *counter, bool pred, int32_t value) {
-  unsigned long long m = __ballot(pred);
-  if (m == 0) return;
-  int lane = lane_id();
-  int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
-  base = __shfl(base, leader);
-  if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
-}
 
 // add a fixed-point value to acc[key*3 .. +2] for every lane with pred; lanes that share
 // a key are summed inside the wave first. Called by the whole wave.
@@ -265,7 +276,9 @@ __device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y,
 // every kernel family is a template over (D, P); the dispatcher picks one instance
 struct Ctx;
 template <int D, int P> struct Ops {
-  static void sweep(Ctx &c, hipStream_t s);
+  // the lattice sweep; with mid != NULL, the event is recorded between the bulk kernel
+  // and the interface / near-wall kernel
+  static void sweep(Ctx &c, hipStream_t s, hipEvent_t mid);
   static void convert(Ctx &c, hipStream_t s);
   static void label(Ctx &c, hipStream_t s, int apply_flux);
   static void geometry(Ctx &c, hipStream_t s);
@@ -297,7 +310,7 @@ struct Ctx {
 };
 
 // every (dimension, precision) instance the library is built with
-#define MF_FOR_ALL(M) M(2, 0) M(2, 1) M(2, 2) M(2, 3) M(3, 0) M(3, 1) M(3, 2) M(3, 3)
+#define MF_FOR_ALL(M) M(2, 0) M(2, 1) M(2, 2) M(2, 3) M(2, 4) M(3, 0) M(3, 1) M(3, 2) M(3, 3) M(3, 4)
 
 // message of the last failed call on this thread that has no context
 extern thread_local std::string g_thread_err;

@@ -1,0 +1,14 @@
+// Lattice sweep, 16-bit-storage instances (binary16 / bfloat16 population offsets,
+// binary32 arithmetic): multiply-adds may contract into fused operations (these
+// instances are held to tolerances, not to bit equality).
+#pragma clang fp contract(fast)
+#include "sweep_impl.h"
+
+namespace mf {
+template void Ops<2, 2>::sweep(Ctx &, hipStream_t, hipEvent_t);
+template void Ops<2, 3>::sweep(Ctx &, hipStream_t, hipEvent_t);
+template void Ops<2, 4>::sweep(Ctx &, hipStream_t, hipEvent_t);
+template void Ops<3, 2>::sweep(Ctx &, hipStream_t, hipEvent_t);
+template void Ops<3, 3>::sweep(Ctx &, hipStream_t, hipEvent_t);
+template void Ops<3, 4>::sweep(Ctx &, hipStream_t, hipEvent_t);
+}  // namespace mf

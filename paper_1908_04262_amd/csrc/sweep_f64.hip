@@ -3,6 +3,6 @@
 #include "sweep_impl.h"
 
 namespace mf {
-template void Ops<2, 0>::sweep(Ctx &, hipStream_t);
-template void Ops<3, 0>::sweep(Ctx &, hipStream_t);
+template void Ops<2, 0>::sweep(Ctx &, hipStream_t, hipEvent_t);
+template void Ops<3, 0>::sweep(Ctx &, hipStream_t, hipEvent_t);
 }  // namespace mf

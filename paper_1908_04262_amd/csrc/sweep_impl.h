@@ -1,5 +1,5 @@
-// Lattice sweep: one thread per cell, pull streaming from the SoA buffer of the
-// previous step into the other buffer.
+// Lattice sweep: pull streaming from the SoA buffer of the previous step into the
+// other buffer.
 //
 //  - streaming with bounce-back at walls (Sec. 2, Eqs. collisionstep, streamingstep);
 //  - at interface cells, populations arriving from gas are rebuilt at the gas density
@@ -11,44 +11,212 @@
 //  - moments, BGK collision (Eqs. collision, equilibrium) with Newtonian or power-law tau
 //    (Eq. tau, Eq. carreauTau), ADE collision with source (Eq. diffusion);
 //  - fill / empty classification of interface cells (Sec. 2.1).
-// The kernel also lists the interface cells and the bubble cells of the types it read.
+//
+// Two launch forms compute the same update:
+//  * per cell (k_sweep): one thread per cell over the whole grid. Used for binary64,
+//    for periodic axes and for rows whose length is not a multiple of the vector width;
+//  * split (k_sweep_vec + k_sweep_special): the bulk kernel gives each thread VW
+//    consecutive cells, so that every population plane is read and written with
+//    aligned 8- or 16-byte accesses per lane (the one-cell shift of directions with an
+//    x component is done across lanes); it updates every liquid cell, taking
+//    bounce-back at walls from a static per-cell mask of wall directions. Interface
+//    cells take the per-cell path in a second kernel over the interface list, so the
+//    bulk kernel carries no divergent interface work.
+// The interface and bubble lists of the step are built before the sweep.
 #pragma once
+#include <utility>
+
 #include "lbm_math.h"
 
 namespace mf {
 
+// Power-law relaxation time in binary32 (the same root as powerlaw_tau): Newton's
+// method on u = log2(tau - 1/2), whose iterates are those on ln(tau - 1/2) scaled by
+// 1/ln 2, with the hardware base-2 exponential and logarithm.
+__device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float pn) {
+  const float n = (float)p.pl_n;
+  float tau;
+  if (!(pn > 0.0f)) {
+    tau = n < 1.0f ? (float)p.tau_max : (n > 1.0f ? (float)p.tau_min : 0.5f + 3.0f * (float)p.pl_nu_ref);
+  } else {
+    const float l3 = p.pl_l2nu3;
+    const float la = l3 + (n - 1.0f) * __builtin_amdgcn_logf((p.pl_kg * pn) * rinv);
+    const float m = 1.0f - n;
+    float u = l3;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const float e = __builtin_amdgcn_exp2f(u);
+      const float r = __builtin_amdgcn_rcpf(e + 0.5f);
+      const float F = (u - m * __builtin_amdgcn_logf(e + 0.5f)) - la;
+      const float dF = 1.0f - (m * e) * r;
+      u = u - F * __builtin_amdgcn_rcpf(dF);
+    }
+    tau = 0.5f + __builtin_amdgcn_exp2f(u);
+  }
+  tau = tau < (float)p.tau_min ? (float)p.tau_min : tau;
+  tau = tau > (float)p.tau_max ? (float)p.tau_max : tau;
+  return tau;
+}
+
+// BGK collision of one cell on offsets in binary32 (instances 1-4): one reciprocal of
+// the density, equilibria built in pairs of opposite directions (even part
+// w (drho + rho (4.5 (e.u)^2 - 1.5 u.u)), odd part 3 w rho e.u).
+template <int D>
+__device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft, float *gt, float &rho, float &ux,
+                                            float &uy, float &uz) {
+  using L = Lat<D>;
+  constexpr int Q = L::Q, Qg = L::Qg;
+  float s, jx, jy, jz;
+  sums<D, float>(ft, s, jx, jy, jz);
+  const float drho = s;
+  rho = 1.0f + s;
+  if (!(rho > 0.0f)) raise_status(d.status, ST_NONFINITE);
+  const float ir = __builtin_amdgcn_rcpf(rho);
+  ux = jx * ir;
+  uy = jy * ir;
+  uz = D == 3 ? jz * ir : 0.0f;
+  const float uu = usq<D, float>(ux, uy, uz);
+  float omega = (float)p.omega;
+  if (p.rheology == MF_POWER_LAW) {
+    // non-equilibrium momentum flux: sum e e (f - w) minus the equilibrium part
+    // rho c_s^2 I + rho u u taken relative to the rest state (I/3)
+    float pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float dd = ft[i];
+      const int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
+      if (ex) pxx = pxx + dd;
+      if (ey) pyy = pyy + dd;
+      if (D == 3 && ez) pzz = pzz + dd;
+      if (ex && ey) pxy = pxy + float(ex * ey) * dd;
+      if (D == 3 && ex && ez) pxz = pxz + float(ex * ez) * dd;
+      if (D == 3 && ey && ez) pyz = pyz + float(ey * ez) * dd;
+    }
+    const float d3 = drho * (1.0f / 3.0f);
+    pxx = pxx - (d3 + rho * ux * ux);
+    pyy = pyy - (d3 + rho * uy * uy);
+    pxy = pxy - rho * ux * uy;
+    if (D == 3) {
+      pzz = pzz - (d3 + rho * uz * uz);
+      pxz = pxz - rho * ux * uz;
+      pyz = pyz - rho * uy * uz;
+    }
+    const float ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + 2.0f * ((pxy * pxy + pxz * pxz) + pyz * pyz);
+    omega = __builtin_amdgcn_rcpf(powerlaw_tau_f32(p, ir, __builtin_amdgcn_sqrtf(ss)));
+  }
+  const float c15 = 1.5f * uu;
+  {
+    const float w0 = (float)L::w[0];
+    ft[0] = ft[0] - omega * (ft[0] - (w0 * drho - (w0 * rho) * c15));
+  }
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const float eu = edot<D, float>(i, ux, uy, uz);
+    const float w = (float)L::w[i];
+    const float wr = w * rho;
+    const float ev = w * drho + wr * ((4.5f * eu) * eu - c15);
+    const float od = wr * (3.0f * eu);
+    ft[i] = ft[i] - omega * (ft[i] - (ev + od));
+    ft[i + 1] = ft[i + 1] - omega * (ft[i + 1] - (ev - od));
+  }
+  float dc = gt[0];
+#pragma unroll
+  for (int i = 1; i < Qg; ++i) dc = dc + gt[i];
+  const float c = (float)p.c0 + dc;
+  const float og = (float)p.omega_g, q = (float)p.q;
+  {
+    const float wg = (float)L::wg[0];
+    gt[0] = (gt[0] - og * (gt[0] - wg * dc)) + wg * q;
+  }
+#pragma unroll
+  for (int i = 1; i < Qg; i += 2) {
+    const float eu = edot<D, float>(i, ux, uy, uz);
+    const float wg = (float)L::wg[i];
+    const float ev = wg * dc;
+    const float od = (wg * c) * ((float)L::kg * eu);
+    gt[i] = (gt[i] - og * (gt[i] - (ev + od))) + wg * q;
+    gt[i + 1] = (gt[i + 1] - og * (gt[i + 1] - (ev - od))) + wg * q;
+  }
+}
+
+// BGK collision of one cell in the register convention of instance P (fluid and ADE
+// lattices); ft and gt are replaced by their post-collision values.
 template <int D, int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep(KP p, DA d, int cur) {
+__device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename Prec<P>::R *ft,
+                                             typename Prec<P>::R *gt, typename Prec<P>::R &rho,
+                                             typename Prec<P>::R &ux, typename Prec<P>::R &uy,
+                                             typename Prec<P>::R &uz) {
+  if constexpr (P != 0) {
+    collide_f32<D>(p, d, ft, gt, rho, ux, uy, uz);
+    return;
+  }
+  using L = Lat<D>;
+  using R = typename Prec<P>::R;
+  using A = Arith<D, P>;
+  constexpr int Q = L::Q, Qg = L::Qg;
+  R drho;
+  A::mom(ft, rho, drho, ux, uy, uz);
+  if (!(rho > R(0))) raise_status(d.status, ST_NONFINITE);
+  const R uu = usq<D, R>(ux, uy, uz);
+  R omega = R(p.omega);
+  if (p.rheology == MF_POWER_LAW) {
+    R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      // binary64: sum e e (f - f_eq) term by term; offset instances: sum e e (f - w),
+      // the equilibrium part is removed in closed form below
+      const R dd = P == 0 ? ft[i] - A::eq(i, rho, drho, ux, uy, uz, uu) : ft[i];
+      const int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
+      if (ex) pxx = pxx + dd;
+      if (ey) pyy = pyy + dd;
+      if (D == 3 && ez) pzz = pzz + dd;
+      if (ex && ey) pxy = pxy + R(ex * ey) * dd;
+      if (D == 3 && ex && ez) pxz = pxz + R(ex * ez) * dd;
+      if (D == 3 && ey && ez) pyz = pyz + R(ey * ez) * dd;
+    }
+    if constexpr (P != 0) {
+      // second moment of the equilibrium: rho c_s^2 I + rho u u; on offsets the rest
+      // state contributes I/3, so subtract drho/3 on the diagonal
+      const R d3 = drho * R(1.0 / 3.0);
+      pxx = pxx - (d3 + rho * ux * ux);
+      pyy = pyy - (d3 + rho * uy * uy);
+      pxy = pxy - rho * ux * uy;
+      if (D == 3) {
+        pzz = pzz - (d3 + rho * uz * uz);
+        pxz = pxz - rho * ux * uz;
+        pyz = pyz - rho * uy * uz;
+      }
+    }
+    const R ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + R(2) * ((pxy * pxy + pxz * pxz) + pyz * pyz);
+    omega = R(1) / powerlaw_tau<R>(p, rho, sqrt(ss));
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R fe = A::eq(i, rho, drho, ux, uy, uz, uu);
+    ft[i] = ft[i] - omega * (ft[i] - fe);
+  }
+  R dc;
+  const R c = A::conc(gt, R(p.c0), dc);
+  const R og = R(p.omega_g), q = R(p.q);
+#pragma unroll
+  for (int i = 0; i < Qg; ++i) gt[i] = (gt[i] - og * (gt[i] - A::geqv(i, c, dc, ux, uy, uz))) + R(Lat<D>::wg[i]) * q;
+}
+
+// The whole update of one cell (x, y, z) = n with type byte tb and bubble id lab; lanes
+// with fluid == false only take part in the wave-level gas-ledger sum. Called by the
+// whole wave.
+template <int D, int P>
+__device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool fluid, int x, int y, int z, int64_t n,
+                                           uint8_t tb, int32_t lab) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
   using SG = typename Prec<P>::SG;
   using FC = FCodec<P, D>;
+  using GC = GCodec<P>;
   using A = Arith<D, P>;
   constexpr int Q = L::Q, Qg = L::Qg;
-
-  // tile of 64 x 4 cells; consecutive tiles of one z-range go to the same XCD
-  const int gx = (p.nx + 63) >> 6, gy = (p.ny + 3) >> 2;
-  const int64_t nb = (int64_t)gx * gy * p.nz;
-  int64_t b = blockIdx.x;
-  const int64_t per = nb >> 3;
-  if (b < (per << 3)) b = (b & 7) * per + (b >> 3);
-  const int bx = (int)(b % gx);
-  const int64_t rr = b / gx;
-  const int by = (int)(rr % gy);
-  const int z = (int)(rr / gy);
-  const int x = (bx << 6) + (threadIdx.x & 63);
-  const int y = (by << 2) + (threadIdx.x >> 6);
-  const bool in = x < p.nx && y < p.ny && z < p.nz;
-  const int64_t n = in ? (int64_t)x + (int64_t)p.nx * ((int64_t)y + (int64_t)p.ny * z) : 0;
-  const uint8_t tb = in ? d.type[n] : TW;
   const int t = tb & TMASK;
-  const bool gi = in && (t == TG || t == TI);
-  const int32_t lab = gi ? d.label[n] : NOLAB;
-  wave_append(d.ilist, d.cnt + C_I, in && t == TI, (int32_t)n);
-  wave_append(d.blist, d.cnt + C_B, gi && lab != 0, (int32_t)n);
-
-  const bool fluid = in && (t == TL || t == TI);
   const bool isI = fluid && t == TI;
   bool hasgas = false;
   R phic = R(0);
@@ -64,7 +232,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (int i = 0; i < Q; ++i) {
       const int64_t s = nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
       ft[i] = FC::dec(fin[(int64_t)i * Np + s], i);
-      if (i < Qg) gt[i] = gin[(int64_t)i * Np + s];
+      if (i < Qg) gt[i] = GC::dec(gin[(int64_t)i * Np + s], p);
     }
     R Ms = R(0);
     const bool special = isI || (tb & NEARWALL);
@@ -77,7 +245,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         own[i] = FC::dec(fin[(int64_t)i * Np + n], i);
-        if (i < Qg) gown[i] = gin[(int64_t)i * Np + n];
+        if (i < Qg) gown[i] = GC::dec(gin[(int64_t)i * Np + n], p);
         const int64_t s = nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
         tsrc[i] = d.type[s] & TMASK;
       }
@@ -135,55 +303,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         Ms = ((const R *)d.M)[n] + dm;
       }
     }
-    // moments and collision
-    R rho, drho, ux, uy, uz;
-    A::mom(ft, rho, drho, ux, uy, uz);
-    if (!(rho > R(0))) raise_status(d.status, ST_NONFINITE);
-    const R uu = usq<D, R>(ux, uy, uz);
-    R omega = R(p.omega);
-    if (p.rheology == MF_POWER_LAW) {
-      R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+    R rho, ux, uy, uz;
+    collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        // binary64: sum e e (f - f_eq) term by term; offset instances: sum e e (f - w),
-        // the equilibrium part is removed in closed form below
-        const R dd = P == 0 ? ft[i] - A::eq(i, rho, drho, ux, uy, uz, uu) : ft[i];
-        const int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
-        if (ex) pxx = pxx + dd;
-        if (ey) pyy = pyy + dd;
-        if (D == 3 && ez) pzz = pzz + dd;
-        if (ex && ey) pxy = pxy + R(ex * ey) * dd;
-        if (D == 3 && ex && ez) pxz = pxz + R(ex * ez) * dd;
-        if (D == 3 && ey && ez) pyz = pyz + R(ey * ez) * dd;
-      }
-      if constexpr (P != 0) {
-        // second moment of the equilibrium: rho c_s^2 I + rho u u; on offsets the rest
-        // state contributes I/3, so subtract drho/3 on the diagonal
-        const R d3 = drho * R(1.0 / 3.0);
-        pxx = pxx - (d3 + rho * ux * ux);
-        pyy = pyy - (d3 + rho * uy * uy);
-        pxy = pxy - rho * ux * uy;
-        if (D == 3) {
-          pzz = pzz - (d3 + rho * uz * uz);
-          pxz = pxz - rho * ux * uz;
-          pyz = pyz - rho * uy * uz;
-        }
-      }
-      const R ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + R(2) * ((pxy * pxy + pxz * pxz) + pyz * pyz);
-      omega = R(1) / powerlaw_tau<R>(p, rho, sqrt(ss));
-    }
+    for (int i = 0; i < Q; ++i) fout[(int64_t)i * Np + n] = FC::enc(ft[i], i);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R fe = A::eq(i, rho, drho, ux, uy, uz, uu);
-      fout[(int64_t)i * Np + n] = FC::enc(ft[i] - omega * (ft[i] - fe), i);
-    }
-    R dc;
-    const R c = A::conc(gt, R(p.c0), dc);
-    const R og = R(p.omega_g), q = R(p.q);
-#pragma unroll
-    for (int i = 0; i < Qg; ++i) {
-      gout[(int64_t)i * Np + n] = (gt[i] - og * (gt[i] - A::geqv(i, c, dc, ux, uy, uz))) + R(Lat<D>::wg[i]) * q;
-    }
+    for (int i = 0; i < Qg; ++i) gout[(int64_t)i * Np + n] = GC::enc(gt[i], p);
     if (isI) {
       ((R *)d.rho)[n] = rho;
       ((R *)d.ux)[n] = ux;
@@ -203,11 +328,262 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   wave_fx_add(d.phi, hasgas && lab >= 0 && lab < p.cap, lab, fx3((double)phic));
 }
 
+// block index remapped so that consecutive tiles go to the same XCD (of 8): the
+// hardware deals blocks round-robin over the XCDs, each with its own L2
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t per = nb >> 3;
+  return b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
+}
+
+// ------------------------------------------------------------------ per-cell form
 template <int D, int P>
-void Ops<D, P>::sweep(Ctx &c, hipStream_t s) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep(KP p, DA d, int cur) {
+  // tile of 64 x 4 cells
+  const int gx = (p.nx + 63) >> 6, gy = (p.ny + 3) >> 2;
+  const int64_t nb = (int64_t)gx * gy * p.nz;
+  const int64_t b = xcd_block(blockIdx.x, nb);
+  const int bx = (int)(b % gx);
+  const int64_t rr = b / gx;
+  const int by = (int)(rr % gy);
+  const int z = (int)(rr / gy);
+  const int x = (bx << 6) + (threadIdx.x & 63);
+  const int y = (by << 2) + (threadIdx.x >> 6);
+  const bool in = x < p.nx && y < p.ny && z < p.nz;
+  const int64_t n = in ? (int64_t)x + (int64_t)p.nx * ((int64_t)y + (int64_t)p.ny * z) : 0;
+  const uint8_t tb = in ? d.type[n] : TW;
+  const int t = tb & TMASK;
+  const int32_t lab = in && t == TI ? d.label[n] : NOLAB;
+  sweep_cell<D, P>(p, d, cur, in && (t == TL || t == TI), x, y, z, n, tb, lab);
+}
+
+// ------------------------------------------------------------------ split form
+// interface cells (this step's interface list)
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
+  LIST_LOOP(k, d.cnt + C_I) {
+    int64_t n = 0;
+    uint8_t tb = TW;
+    bool fluid = false;
+    int32_t lab = NOLAB;
+    int x = 0, y = 0, z = 0;
+    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
+      n = d.ilist[k];
+      tb = d.type[n];
+      fluid = true;
+      lab = d.label[n];
+      cell_xyz(p, n, x, y, z);
+    }
+    sweep_cell<D, P>(p, d, cur, fluid, x, y, z, n, tb, lab);
+  }
+}
+
+template <class T> __device__ __forceinline__ uint32_t lane_bits(T v) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, v);
+  else return (uint32_t)__builtin_bit_cast(uint16_t, v);
+}
+template <class T> __device__ __forceinline__ T from_lane_bits(uint32_t u) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, u);
+  else return __builtin_bit_cast(T, (uint16_t)u);
+}
+
+// One aligned VW-wide load of plane `plane` for the cell group of this lane, shifted by
+// the x component ex of the direction: element j of the result is the value at
+// n0 + j - ex - off. The element that crosses into the neighbouring lane's group comes
+// from that lane; a lane whose neighbour has no valid group (or the first / last lane
+// of the wave) loads it itself, with the index clamped into the plane (such a value
+// only ever feeds a wall cell).
+template <class T, int VW> using Vec = T __attribute__((ext_vector_type(VW)));
+
+template <class T, int VW, int EX>
+__device__ __forceinline__ Vec<T, VW> load_shifted(const T *plane, int64_t base, int64_t off, int64_t N, bool selfprev,
+                                                   bool selfnext) {
+  using VT = Vec<T, VW>;
+  const int64_t s0 = base - off;
+  const VT a = *(const VT *)(plane + s0);
+  if constexpr (EX == 0) {
+    return a;
+  } else if constexpr (EX == 1) {
+    uint32_t pv = __shfl_up(lane_bits(a[VW - 1]), 1);
+    if (selfprev) {
+      const int64_t k = s0 - 1 < 0 ? 0 : s0 - 1;
+      pv = lane_bits(plane[k]);
+    }
+    VT r;
+    r[0] = from_lane_bits<T>(pv);
+#pragma unroll
+    for (int j = 1; j < VW; ++j) r[j] = a[j - 1];
+    return r;
+  } else {
+    uint32_t nv = __shfl_down(lane_bits(a[0]), 1);
+    if (selfnext) {
+      const int64_t k = s0 + VW > N - 1 ? N - 1 : s0 + VW;
+      nv = lane_bits(plane[k]);
+    }
+    VT r;
+#pragma unroll
+    for (int j = 0; j < VW - 1; ++j) r[j] = a[j + 1];
+    r[VW - 1] = from_lane_bits<T>(nv);
+    return r;
+  }
+}
+
+template <int D, int I> struct DirOff {
+  static __device__ __forceinline__ int64_t get(const KP &p) {
+    return (int64_t)Lat<D>::ey[I] * p.nx + (D == 3 ? (int64_t)Lat<D>::ez[I] * ((int64_t)p.nx * p.ny) : 0);
+  }
+};
+
+template <int D, int P, int VW, int I>
+__device__ __forceinline__ void load_dir(const KP &p, const typename Prec<P>::SF *fin, const typename Prec<P>::SG *gin,
+                                         int64_t base, bool sp, bool sn, Vec<typename Prec<P>::SF, VW> (&fv)[Lat<D>::Q],
+                                         Vec<typename Prec<P>::SG, VW> (&gv)[Lat<D>::Qg]) {
+  constexpr int EX = Lat<D>::ex[I];
+  const int64_t off = DirOff<D, I>::get(p);
+  fv[I] = load_shifted<typename Prec<P>::SF, VW, EX>(fin + (int64_t)I * p.Np, base, off, p.N, sp, sn);
+  if constexpr (I < Lat<D>::Qg)
+    gv[I] = load_shifted<typename Prec<P>::SG, VW, EX>(gin + (int64_t)I * p.Np, base, off, p.N, sp, sn);
+}
+
+template <int D, int P, int VW, int... Is>
+__device__ __forceinline__ void load_all(const KP &p, const typename Prec<P>::SF *fin, const typename Prec<P>::SG *gin,
+                                         int64_t base, bool sp, bool sn, Vec<typename Prec<P>::SF, VW> (&fv)[Lat<D>::Q],
+                                         Vec<typename Prec<P>::SG, VW> (&gv)[Lat<D>::Qg], std::integer_sequence<int, Is...>) {
+  (load_dir<D, P, VW, Is>(p, fin, gin, base, sp, sn, fv, gv), ...);
+}
+
+// Bulk kernel: VW consecutive cells n0 .. n0+VW-1 per thread (the grid is linear in the
+// cell index). Requires closed axes (no periodic wrap) and nx % VW == 0, so that every
+// group starts on a VW boundary and the pulls of a fluid cell are plain index offsets.
+template <int D, int P, int VW>
+__global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
+  using L = Lat<D>;
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  using SG = typename Prec<P>::SG;
+  using FC = FCodec<P, D>;
+  using GC = GCodec<P>;
+  constexpr int Q = L::Q, Qg = L::Qg;
+  using VF = Vec<SF, VW>;
+  using VG = Vec<SG, VW>;
+  using VB = Vec<uint8_t, VW>;
+
+  const int64_t N = p.N;
+  // plain block order: every XCD streams through neighbouring parts of the grid
+  const int64_t n0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VW;
+  const int lane = lane_id();
+
+  // cell types of the group
+  VB tv;
+  if (n0 < N) tv = *(const VB *)(d.type + n0);
+  else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) tv[e] = TW;
+  }
+  bool plain[VW];
+  bool anyplain = false, allplain = true, anywall = false;
+#pragma unroll
+  for (int e = 0; e < VW; ++e) {
+    const uint8_t tb = tv[e];
+    plain[e] = (tb & TMASK) == TL;
+    anyplain = anyplain || plain[e];
+    allplain = allplain && plain[e];
+    anywall = anywall || (plain[e] && (tb & NEARWALL));
+  }
+  if (__ballot(anyplain) == 0) return;  // wave-uniform
+
+  // aligned loads stay inside [0, N) for groups whose start lies in [lo, hi]; every group
+  // holding a liquid cell does (liquid cells are never on the outer layer of a closed
+  // axis, which is all walls). Other lanes load from lo: their values are never stored.
+  const int64_t offA = (int64_t)p.nx * (D == 3 ? (int64_t)p.ny + 1 : 1);
+  const int64_t lo = offA, hi = N - offA - VW;
+  const bool safe = n0 >= lo && n0 <= hi;
+  const int64_t base = safe ? n0 : lo;
+  const bool selfprev = lane == 0 || !(n0 - VW >= lo && n0 - VW <= hi);
+  const bool selfnext = lane == 63 || !(n0 + VW >= lo && n0 + VW <= hi);
+
+  VF fv[Q];
+  VG gv[Qg];
+  load_all<D, P, VW>(p, (const SF *)d.f[cur], (const SG *)d.g[cur], base, selfprev, selfnext, fv, gv,
+                     std::make_integer_sequence<int, Q>{});
+
+  const SF *fin = (const SF *)d.f[cur];
+  const SG *gin = (const SG *)d.g[cur];
+#pragma unroll
+  for (int e = 0; e < VW; ++e) {
+    if (plain[e]) {
+      R ft[Q], gt[Qg];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) ft[i] = FC::dec(fv[i][e], i);
+#pragma unroll
+      for (int i = 0; i < Qg; ++i) gt[i] = GC::dec(gv[i][e], p);
+      if (anywall && (tv[e] & NEARWALL)) {
+        // bounce-back: a population whose source is a wall is the cell's own outgoing
+        // population of the opposite direction
+        const int64_t n = n0 + e;
+        const uint32_t wm = d.wmask[n];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          if (wm & (1u << i)) {
+            ft[i] = FC::dec(fin[(int64_t)opp(i) * p.Np + n], i);
+            if (i < Qg) gt[i] = GC::dec(gin[(int64_t)opp(i) * p.Np + n], p);
+          }
+        }
+      }
+      R rho, ux, uy, uz;
+      collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) fv[i][e] = FC::enc(ft[i], i);
+#pragma unroll
+      for (int i = 0; i < Qg; ++i) gv[i][e] = GC::enc(gt[i], p);
+    }
+  }
+
+  SF *fout = (SF *)d.f[cur ^ 1];
+  SG *gout = (SG *)d.g[cur ^ 1];
+  if (allplain) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) *(VF *)(fout + (int64_t)i * p.Np + n0) = fv[i];
+#pragma unroll
+    for (int i = 0; i < Qg; ++i) *(VG *)(gout + (int64_t)i * p.Np + n0) = gv[i];
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      if (!plain[e]) continue;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) fout[(int64_t)i * p.Np + n0 + e] = fv[i][e];
+#pragma unroll
+      for (int i = 0; i < Qg; ++i) gout[(int64_t)i * p.Np + n0 + e] = gv[i][e];
+    }
+  }
+}
+
+// cells per thread of the bulk kernel: 8-byte population accesses per lane
+template <int P> constexpr int vec_width() { return P == 1 ? 2 : 4; }
+
+template <int D, int P>
+bool use_split(const Ctx &c) {
+  constexpr int VW = vec_width<P>();
+  if (P == 0) return false;
+  if (c.kp.per[0] || c.kp.per[1] || c.kp.per[2]) return false;
+  return c.kp.nx % VW == 0 && c.kp.nx >= 2 * VW && c.kp.ny >= 3 && (D == 2 || c.kp.nz >= 3);
+}
+
+template <int D, int P>
+void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t mid) {
+  if constexpr (P != 0) {
+    if (use_split<D, P>(c)) {
+      constexpr int VW = vec_width<P>();
+      const int64_t nb = (c.kp.N + 256 * VW - 1) / (256 * VW);
+      hipLaunchKernelGGL((k_sweep_vec<D, P, VW>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
+      if (mid) (void)hipEventRecord(mid, s);
+      hipLaunchKernelGGL((k_sweep_special<D, P>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
+      return;
+    }
+  }
   const int gx = (c.kp.nx + 63) / 64, gy = (c.kp.ny + 3) / 4;
   const int64_t nb = (int64_t)gx * gy * c.kp.nz;
   hipLaunchKernelGGL((k_sweep<D, P>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
+  if (mid) (void)hipEventRecord(mid, s);
 }
 
 }  // namespace mf

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmifoam.so")
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "f16s": 2, "bf16s": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "f16s": 2, "bf16s": 3, "f16s_g16": 4}
 FIELDS = dict(type=0, label=1, rho=2, ux=3, uy=4, uz=5, alpha=6, mass=7, conc=8,
               kappa=9, pi=10, f=11, g=12)
 STATUS = {0: "MF_OK", -1: "MF_EINVAL", -2: "MF_ENOMEM", -3: "MF_EHIP", -4: "MF_ECAPACITY",

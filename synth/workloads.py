@@ -4,8 +4,8 @@ Every run in this repository starts from a parameter dictionary returned by
 ``workload(name)`` or ``small_case(name)`` and from the nucleus list returned by
 ``place_nuclei``.  The physical constants that the benchmark configurations leave
 open are filled from the parameter sets printed in the paper's figure captions
-(Sec. 4.3-4.5: k_H = 5e-3, RT = 50, k_Pi = 5e-3) and from the sources listed in
-the design doc.  Randomness: SplitMix64 (Steele, Lea and Flood, 2014) as the integer
+(Sec. 4.3-4.5: k_H = 5e-3, RT = 50, k_Pi = 5e-3); the remaining gaps (liquid level,
+diffusivity, supersaturation, power-law reference viscosity) are fixed below.  Randomness: SplitMix64 (Steele, Lea and Flood, 2014) as the integer
 stream and U(0,1) = (u >> 11) * 2**-53.
 
 Nucleus placement is dart throwing: per attempt draw r ~ U[r_min, r_max], then the

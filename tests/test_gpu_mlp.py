@@ -127,11 +127,19 @@ def _stencil_from_state(T, alpha, lab, x, y, z):
     return out, ok
 
 
-def test_in_step_inference_matches_reference():
-    from paper_1908_04262_amd import CurvatureNet, Sim
-    _say("in-step inference")
+@pytest.fixture(scope="module")
+def trained_net():
+    from paper_1908_04262_amd import CurvatureNet
+    _say("training a network for the in-step tests")
     net = CurvatureNet(7)
-    net.train(n_train=32768, n_val=2048, epochs=1, batch=2048, lr=2e-3, data_seed=4)
+    net.train(n_train=65536, n_val=4096, epochs=2, batch=2048, lr=2e-3, data_seed=4)
+    return net
+
+
+def test_in_step_inference_matches_reference(trained_net):
+    from paper_1908_04262_amd import Sim
+    _say("in-step inference")
+    net = trained_net
     th = net.params().astype(np.float64)
     wl = small_case("c2_small", precision="fp32", curvature="mlp", nx=64)
     sim = Sim(wl)
@@ -158,3 +166,39 @@ def test_in_step_inference_matches_reference():
         _say("mismatch", (x, y, z), "gpu", kg[b], "ref", ko[b], "label", lab[z, y, x],
              "alpha", al[z, y, x], "n", len(bad), "of", use.sum())
     assert np.abs(kg[use] - ko[use]).max() <= 2e-3
+
+
+def _liquid(s):
+    t = s.totals()
+    return t["liquid"] + t["lost_liquid"]
+
+
+@pytest.mark.parametrize("prec", ["f16s", "bf16s"])
+def test_16bit_storage_with_learned_curvature(trained_net, prec):
+    """16-bit offsets + learned curvature against the FP64 oracle with plain curvature:
+    liquid mass within 1e-6 relative, bubble volumes within 1% while no topology change
+    has happened (after one, trajectories may legitimately part)."""
+    from paper_1908_04262_amd import Sim
+    wl = small_case("c2_small", precision=prec, curvature="mlp")
+    wl64 = small_case("c2_small", precision="fp64")
+    _say(f"{prec} + mlp c2_small vs fp64 oracle")
+    gpu = Sim(wl)
+    gpu.attach_mlp(trained_net)
+    orc = Oracle(wl64)
+    c, r, p0 = place_nuclei(wl)
+    gpu.nucleate(c, r, p0)
+    orc.nucleate(c, r, p0)
+    m0 = _liquid(gpu)
+    compared = 0
+    for k in range(4):
+        gpu.step(10)
+        orc.step(10)
+        bg, bo = gpu.bubbles(), orc.bubbles()
+        if list(bg["id"]) == list(bo["id"]) and orc.ledgers()["next_id"] == len(r) + 1:
+            dv = np.abs(bg["V"] - bo["V"]) / bo["V"]
+            _say(f"  step {10 * (k + 1)}: max volume deviation {dv.max():.2e}")
+            assert dv.max() < 0.01, dv.max()
+            compared += 1
+        dm = abs(_liquid(gpu) - m0) / m0
+        assert dm < 1e-6, dm
+    assert compared >= 1

@@ -2,7 +2,7 @@
 
 P13 hand-worked cell conversions with excess-mass redistribution (Sec. 2.1, last
 paragraph); P14 bubble labelling against scipy.ndimage.label and hand-worked merge /
-split gas bookkeeping (Sec. 3.6); P5-P7 the conservation ledgers and the ideal-gas law
+split gas bookkeeping (Sec. 3.5); P5-P7 the conservation ledgers and the ideal-gas law
 (Eq. idealgas); P8 the Laplace jump of a static bubble through the gas density of
 Eq. rhob; P12 dissolution of a bubble in gas-free liquid (Sec. 4.3).
 """

@@ -5,7 +5,7 @@ inclusion-exclusion volume of a cut unit cube in exact rational arithmetic;
 P15 the ray traversal of Appendix A (Algorithm 1, generalised to 3D) against exact
 rational ray/grid crossing parameters, and the disjoining pressure of two flat films of
 known gap (Sec. 3.3, Eq. for Pi); P9 curvature of voxelised circles and spheres;
-nucleation volume (Sec. 3.5).
+nucleation volume (Sec. 3.4).
 """
 import itertools
 import math
