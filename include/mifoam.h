@@ -252,9 +252,9 @@ int mf_attach_mlp(mf_ctx *ctx, const mf_mlp *m);
 
 /* Time spent in a kernel group over the steps since mf_profile_enable(ctx, 1), in
  * milliseconds (total) with the number of steps timed, measured with HIP events on the
- * context stream: group 0 = the bulk lattice sweep (the whole sweep on domains that
- * use the per-cell kernel), 1 = whole step, 2 = the interface / near-wall sweep kernel
- * (zero time on domains that use the per-cell kernel). At most 4096 steps are timed
+ * context stream: group 0 = the bulk lattice sweep kernel (the whole sweep on domains
+ * that use the per-cell kernel), 1 = whole step, 2 = the interface-cell sweep kernel
+ * (zero on domains that use the per-cell kernel). At most 4096 steps are timed
  * per enable; a further mf_step returns MF_ESTATE until the next enable. */
 int mf_profile_enable(mf_ctx *ctx, int32_t on);
 int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launches);

@@ -100,6 +100,8 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.nilist = cv.take<int32_t>(Np * 4);
   d.l2ilist = cv.take<int32_t>(Np * 4);
   d.wmask = cv.take<uint32_t>(Np * 4);
+  d.lcnt = cv.take<int32_t>((size_t)2 * list_blocks_of(kp) * 4);
+  d.sword = P.curvature == MF_CURV_MLP ? cv.take<uint32_t>(Np * 4) : nullptr;
   d.cnt = cv.take<int32_t>(C_NCOUNT * 4);
   d.status = cv.take<int32_t>(4);
   const size_t cap = (size_t)kp.cap;
@@ -144,6 +146,7 @@ int validate(const mf_params *p, std::string &why) {
   if (p->rheology != MF_NEWTONIAN && p->rheology != MF_POWER_LAW) { why = "unknown rheology"; return MF_EINVAL; }
   if (p->curvature != MF_CURV_PLAIN && p->curvature != MF_CURV_MLP) { why = "unknown curvature mode"; return MF_EINVAL; }
   if (p->curvature == MF_CURV_MLP && p->dim != 3) { why = "the learned curvature works on 5x5x5 stencils (3D only)"; return MF_EUNSUPPORTED; }
+  if (p->curvature == MF_CURV_MLP && p->max_ids > 65534) { why = "the learned curvature supports at most 65534 bubble ids"; return MF_EINVAL; }
   if (p->max_ids < 2 || p->max_ids > (1 << 24)) { why = "max_ids out of range"; return MF_EINVAL; }
   if (!(p->tau > 0.5) || !(p->D > 0.0) || !(p->RT > 0.0) || !(p->eps >= 0.0)) { why = "tau > 1/2, D > 0, RT > 0, eps >= 0 required"; return MF_EINVAL; }
   if (p->k_pi > 0.0 && !(p->d_max >= 1.0)) { why = "d_max >= 1 required with disjoining pressure"; return MF_EINVAL; }
@@ -345,6 +348,7 @@ int mf_destroy(mf_ctx *c) {
 
 int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii, const double *p0) {
   if (!c) return MF_EINVAL;
+  c->sword_dirty = true;
   if (c->nucleated || c->stepped) { c->err = "mf_nucleate is valid once, before mf_step"; return MF_ESTATE; }
   if (n < 0 || (n > 0 && (!centers || !radii || !p0))) { c->err = "bad nucleus arrays"; return MF_EINVAL; }
   if (n + 1 > c->kp.cap) { c->err = "more nuclei than the bubble table holds"; return MF_ECAPACITY; }
@@ -449,6 +453,7 @@ int mf_read_field(mf_ctx *c, int32_t field, void *dst, size_t dst_bytes, int32_t
 
 int mf_write_field(mf_ctx *c, int32_t field, const void *src, size_t src_bytes) {
   if (!c || !src) return MF_EINVAL;
+  c->sword_dirty = true;
   if (c->stepped) { c->err = "mf_write_field is valid before the first mf_step"; return MF_ESTATE; }
   const size_t need = field_bytes(c, field);
   if (!need || field == MF_FIELD_CONC) { c->err = "field cannot be written"; return MF_EINVAL; }
@@ -502,6 +507,7 @@ int mf_set_bubble(mf_ctx *c, int32_t id, double gas_mass, double volume, double 
 
 int mf_refresh(mf_ctx *c, int32_t relabel) {
   if (!c) return MF_EINVAL;
+  c->sword_dirty = true;
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
   if (relabel) c->ops.label(*c, c->stream, 0);
@@ -563,15 +569,22 @@ int mf_totals_get(mf_ctx *c, mf_totals *out) {
 int mf_attach_mlp(mf_ctx *c, const mf_mlp *m) {
   if (!c || !m) return MF_EINVAL;
   if (c->kp.curvature != MF_CURV_MLP) { c->err = "the context was created for the plain curvature"; return MF_ESTATE; }
+  // weights (bfloat16), biases (binary32) and the canonical-slot table, 256-byte aligned
+  const size_t wbytes = (2 * (128 * 64 + 64 * 64 + 64) + 255) & ~(size_t)255;
+  const size_t bbytes = (4 * (2 * 64 + 1) + 255) & ~(size_t)255;
+  const size_t tbytes = 48 * 128;
   if (!c->mlp_buf) {
-    HIPCHK(c, hipMalloc(&c->mlp_buf, 2 * (128 * 64 + 64 * 64 + 64) + 4 * (2 * 64 + 1) + 256));
+    HIPCHK(c, hipMalloc(&c->mlp_buf, wbytes + bbytes + tbytes));
+    build_canon_table((uint8_t *)c->mlp_buf + wbytes + bbytes, c->stream);
+    HIPCHK(c, hipGetLastError());
   }
   uint16_t *w = (uint16_t *)c->mlp_buf;
-  float *b = (float *)((char *)c->mlp_buf + ((2 * (128 * 64 + 64 * 64 + 64) + 255) & ~255));
+  float *b = (float *)((char *)c->mlp_buf + wbytes);
   const int rc = mf_mlp_export_weights(m, w, b, c->stream);
   if (rc) { c->err = "copying the network weights failed"; return rc; }
   c->d.mlp_w = w;
   c->d.mlp_b = b;
+  c->d.mlp_canon = (const uint8_t *)c->mlp_buf + wbytes + bbytes;
   return MF_OK;
 }
 

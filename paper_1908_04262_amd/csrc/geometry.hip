@@ -411,9 +411,46 @@ __global__ __launch_bounds__(256) void k_disjoining(KP p, DA d) {
   }
 }
 
+// stencil words (learned curvature): over the whole grid after a state change made
+// outside the time step, else over the cells whose type, fill fraction or bubble id can
+// have changed in this step (this step's interface list, the new interface cells and the
+// relabelled bubble cells)
+template <int P>
+__global__ __launch_bounds__(256) void k_sword_all(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x)
+    d.sword[n] = stencil_word<R>(d.type[n], ((const R *)d.alpha)[n], d.label[n]);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_sword_lists(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  const int nI = *(volatile int32_t *)(d.cnt + C_I), nB = *(volatile int32_t *)(d.cnt + C_B);
+  const int nNI = *(volatile int32_t *)(d.cnt + C_NI), nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nB + nNI + nL;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = k;
+    int32_t n;
+    if (q < nI) n = d.ilist[q];
+    else if ((q -= nI) < nB) n = d.blist[q];
+    else if ((q -= nB) < nNI) n = d.nilist[q];
+    else n = d.l2ilist[q - nNI];
+    d.sword[n] = stencil_word<R>(d.type[n], ((const R *)d.alpha)[n], d.label[n]);
+  }
+}
+
 template <int D, int P>
 void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
   const unsigned nb = list_blocks(c);
+  if (c.d.sword) {
+    if (c.sword_dirty) {
+      const int64_t g = (c.kp.N + 255) / 256;
+      hipLaunchKernelGGL((k_sword_all<P>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, c.kp, c.d);
+      c.sword_dirty = false;
+    } else {
+      hipLaunchKernelGGL((k_sword_lists<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+    }
+  }
   hipLaunchKernelGGL((k_normals<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
   hipLaunchKernelGGL((k_curvature<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);

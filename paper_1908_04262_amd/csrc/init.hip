@@ -184,74 +184,156 @@ __global__ __launch_bounds__(256) void k_nuc_fix2(KP p, DA d) {
 // interface and bubble lists of the current types (the sweep builds them every step;
 // this full pass serves initial and hand-written states)
 // Interface list (type I) and bubble list (gas or interface with a non-zero bubble id),
-// each in cell order within a chunk of LIST_CHUNK cells per block: a first pass counts,
-// one atomic per block and list reserves the block's range, a second pass writes.
-constexpr int LIST_CHUNK = 16384;
+// in cell order, without atomics: each thread classifies 64 consecutive cells (16-byte
+// type loads; labels only where there is gas or interface); a count pass writes the
+// per-block totals, one work-group scans them, and a write pass places every entry at
+// its block's offset plus its rank inside the block.
+constexpr int LIST_CPT = 64;
+constexpr int LIST_CHUNK = 256 * LIST_CPT;
 
-__device__ __forceinline__ void list_preds(const KP &p, const DA &d, int64_t n, bool &pi, bool &pb) {
-  pi = pb = false;
-  if (n >= p.N) return;
-  const int t = d.type[n] & TMASK;
-  pi = t == TI;
-  pb = (t == TG || t == TI) && d.label[n] != 0;
-}
-
-__global__ __launch_bounds__(256) void k_build_lists(KP p, DA d) {
-  __shared__ int s_w[2][4];
-  __shared__ int s_base[2];
-  const int64_t c0 = (int64_t)blockIdx.x * LIST_CHUNK;
-  const int64_t c1 = c0 + LIST_CHUNK < p.N ? c0 + LIST_CHUNK : p.N;
-  const int lane = lane_id(), w = threadIdx.x >> 6;
-  int ci = 0, cb = 0;
-  for (int64_t n = c0 + threadIdx.x; n < c1; n += 256) {
-    bool pi, pb;
-    list_preds(p, d, n, pi, pb);
-    ci += pi;
-    cb += pb;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    ci += __shfl_xor(ci, o);
-    cb += __shfl_xor(cb, o);
-  }
-  if (lane == 0) {
-    s_w[0][w] = ci;
-    s_w[1][w] = cb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int ti = s_w[0][0] + s_w[0][1] + s_w[0][2] + s_w[0][3];
-    const int tb = s_w[1][0] + s_w[1][1] + s_w[1][2] + s_w[1][3];
-    s_base[0] = ti ? atomicAdd(d.cnt + C_I, ti) : 0;
-    s_base[1] = tb ? atomicAdd(d.cnt + C_B, tb) : 0;
-  }
-  __syncthreads();
-  int oi = s_base[0], ob = s_base[1];
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int64_t n0 = c0; n0 < c1; n0 += 256) {
-    bool pi, pb;
-    list_preds(p, d, n0 + threadIdx.x, pi, pb);
-    const unsigned long long bi = __ballot(pi), bb = __ballot(pb);
-    __syncthreads();  // the previous iteration has read s_w
-    if (lane == 0) {
-      s_w[0][w] = __popcll(bi);
-      s_w[1][w] = __popcll(bb);
+__device__ __forceinline__ void list_masks(const KP &p, const DA &d, int64_t c0, unsigned long long &mi,
+                                           unsigned long long &mb) {
+  mi = mb = 0;
+#pragma unroll
+  for (int g = 0; g < LIST_CPT / 16; ++g) {
+    const int64_t n = c0 + g * 16;
+    if (n >= p.N) break;
+    uint8_t t[16];
+    if (n + 16 <= p.N) {
+      const uint4 v = *(const uint4 *)(d.type + n);
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) t[k] = (uint8_t)(wv[k >> 2] >> (8 * (k & 3)));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) t[k] = n + k < p.N ? d.type[n + k] : TW;
     }
-    __syncthreads();
-    int pre_i = 0, pre_b = 0, all_i = 0, all_b = 0;
-    for (int k = 0; k < 4; ++k) {
-      if (k < w) {
-        pre_i += s_w[0][k];
-        pre_b += s_w[1][k];
+    uint32_t gi = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int tt = t[k] & TMASK;
+      if (tt == TI) mi |= 1ull << (g * 16 + k);
+      if (tt == TG || tt == TI) gi |= 1u << k;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((gi >> (4 * q)) & 15u)) continue;
+      int32_t lb[4];
+      if (n + 4 * q + 4 <= p.N) {
+        const int4 v = *(const int4 *)(d.label + n + 4 * q);
+        lb[0] = v.x; lb[1] = v.y; lb[2] = v.z; lb[3] = v.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lb[k] = n + 4 * q + k < p.N ? d.label[n + 4 * q + k] : 0;
       }
-      all_i += s_w[0][k];
-      all_b += s_w[1][k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (((gi >> (4 * q + k)) & 1u) && lb[k] != 0) mb |= 1ull << (g * 16 + 4 * q + k);
     }
-    if (pi) d.ilist[oi + pre_i + __popcll(bi & lt)] = (int32_t)(n0 + threadIdx.x);
-    if (pb) d.blist[ob + pre_b + __popcll(bb & lt)] = (int32_t)(n0 + threadIdx.x);
-    oi += all_i;
-    ob += all_b;
   }
 }
+
+// block-wide inclusive scan of two counts (256 threads); returns the block totals
+__device__ __forceinline__ void block_scan2(int &si, int &sb, int &ti, int &tb) {
+  __shared__ int s_w[2][4];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int a = __shfl_up(si, o), b = __shfl_up(sb, o);
+    if (lane >= o) { si += a; sb += b; }
+  }
+  if (lane == 63) {
+    s_w[0][w] = si;
+    s_w[1][w] = sb;
+  }
+  __syncthreads();
+  ti = tb = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (k < w) {
+      si += s_w[0][k];
+      sb += s_w[1][k];
+    }
+    ti += s_w[0][k];
+    tb += s_w[1][k];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_list_count(KP p, DA d) {
+  const int64_t c0 = (int64_t)blockIdx.x * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
+  unsigned long long mi, mb;
+  list_masks(p, d, c0, mi, mb);
+  int si = __popcll(mi), sb = __popcll(mb), ti, tb;
+  block_scan2(si, sb, ti, tb);
+  if (threadIdx.x == 0) {
+    d.lcnt[2 * blockIdx.x] = ti;
+    d.lcnt[2 * blockIdx.x + 1] = tb;
+  }
+}
+
+// exclusive scan of the per-block counts (in place) and the list lengths
+__global__ __launch_bounds__(1024) void k_list_scan(DA d, int nb) {
+  __shared__ int s_w[2][16];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  int si = 0, sb = 0;
+  for (int k = 0; k < per && b0 + k < nb; ++k) {
+    si += d.lcnt[2 * (b0 + k)];
+    sb += d.lcnt[2 * (b0 + k) + 1];
+  }
+  const int ci = si, cb = sb;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int a = __shfl_up(si, o), b = __shfl_up(sb, o);
+    if (lane >= o) { si += a; sb += b; }
+  }
+  if (lane == 63) {
+    s_w[0][w] = si;
+    s_w[1][w] = sb;
+  }
+  __syncthreads();
+  int oi = si - ci, ob = sb - cb, ti = 0, tb = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < w) {
+      oi += s_w[0][k];
+      ob += s_w[1][k];
+    }
+    ti += s_w[0][k];
+    tb += s_w[1][k];
+  }
+  for (int k = 0; k < per && b0 + k < nb; ++k) {
+    const int a = d.lcnt[2 * (b0 + k)], b = d.lcnt[2 * (b0 + k) + 1];
+    d.lcnt[2 * (b0 + k)] = oi;
+    d.lcnt[2 * (b0 + k) + 1] = ob;
+    oi += a;
+    ob += b;
+  }
+  if (threadIdx.x == 0) {
+    d.cnt[C_I] = ti;
+    d.cnt[C_B] = tb;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_list_write(KP p, DA d) {
+  const int64_t c0 = (int64_t)blockIdx.x * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
+  unsigned long long mi, mb;
+  list_masks(p, d, c0, mi, mb);
+  const int ci = __popcll(mi), cb = __popcll(mb);
+  int si = ci, sb = cb, ti, tb;
+  block_scan2(si, sb, ti, tb);
+  int oi = d.lcnt[2 * blockIdx.x] + si - ci, ob = d.lcnt[2 * blockIdx.x + 1] + sb - cb;
+  while (mi) {
+    const int b = __ffsll((long long)mi) - 1;
+    mi &= mi - 1;
+    d.ilist[oi++] = (int32_t)(c0 + b);
+  }
+  while (mb) {
+    const int b = __ffsll((long long)mb) - 1;
+    mb &= mb - 1;
+    d.blist[ob++] = (int32_t)(c0 + b);
+  }
+}
+
+int list_blocks_of(const KP &kp) { return (int)((kp.N + LIST_CHUNK - 1) / LIST_CHUNK); }
 
 // initial gas content m = p0 V / RT and pressure of every nucleus id
 __global__ void k_init_mass(KP p, DA d, const double *p0, int nn) {
@@ -377,8 +459,10 @@ void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn) {
 
 template <int D, int P>
 void Ops<D, P>::build_lists(Ctx &c, hipStream_t s) {
-  const int64_t nb = (c.kp.N + LIST_CHUNK - 1) / LIST_CHUNK;
-  hipLaunchKernelGGL(k_build_lists, dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d);
+  const int nb = list_blocks_of(c.kp);
+  hipLaunchKernelGGL(k_list_count, dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, c.d, nb);
+  hipLaunchKernelGGL(k_list_write, dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d);
 }
 
 template <int D, int P>

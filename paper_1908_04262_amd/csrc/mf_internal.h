@@ -144,6 +144,7 @@ struct DA {
   void *M, *alpha, *rho, *ux, *uy, *uz, *kappa, *Pi, *exc, *mx, *my, *mz, *soff;
   int32_t *label, *parent;
   int32_t *ilist, *blist, *nilist, *l2ilist;
+  int32_t *lcnt;              // per-block counts / offsets of the list builder [2][blocks]
   uint32_t *wmask;            // static: bit i set when the source x - e_i of the cell is a wall
   int32_t *cnt;
   int32_t *status;
@@ -172,6 +173,8 @@ struct DA {
   // learned curvature (NULL unless a network is attached)
   const uint16_t *mlp_w;      // bfloat16 W1 [128][64], W2 [64][64], W3 [64]
   const float *mlp_b;         // b1 [64], b2 [64], b3
+  const uint8_t *mlp_canon;   // canonical slot of each stencil element [48 symmetries][128]
+  uint32_t *sword;            // stencil word of every cell (learned curvature only; see stencil_word)
 };
 
 // ------------------------------------------------------------------ fixed point
@@ -200,6 +203,12 @@ __device__ __host__ __forceinline__ double fx_to_double(__int128 v) { return (do
 
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// order LDS accesses of the lanes of one wave (no other wave involved)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 // add a fixed-point value to acc[key*3 .. +2] for every lane with pred; lanes that share
 // a key are summed inside the wave first. Called by the whole wave.
@@ -300,12 +309,10 @@ struct Ctx {
   size_t ws_bytes = 0;
   bool nucleated = false;
   bool stepped = false;
+  bool sword_dirty = true;  // stencil words to be rebuilt over the whole grid
   int64_t step = 0;
   std::string err;
   bool prof = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  double prof_ms[2] = {0, 0};
-  int64_t prof_n[2] = {0, 0};
   void *mlp_buf = nullptr;  // device copy of the attached network's weights
 };
 
@@ -315,8 +322,27 @@ struct Ctx {
 // message of the last failed call on this thread that has no context
 extern thread_local std::string g_thread_err;
 
+// work-groups of the list builder (one per chunk of cells)
+int list_blocks_of(const KP &kp);
+
+// Stencil word of a cell, read by the learned curvature's 5x5x5 gather in one load:
+// bits 0-15 the bfloat16 (nearest even) of the fill fraction a stencil reads there (1 for
+// liquid, 0 for gas, the clamped alpha for interface), bits 16-31 a code: 0 for liquid,
+// bubble id + 1 for gas and interface, 0xFFFF for a wall.
+template <class R>
+__device__ __forceinline__ uint32_t stencil_word(uint8_t tb, R alpha, int32_t lab) {
+  const int t = tb & TMASK;
+  if (t == TW) return 0xFFFF0000u;
+  if (t == TL) return (uint32_t)f32_to_bf16(1.0f);
+  const float v = t == TG ? 0.0f : fminf(1.0f, fmaxf(0.0f, (float)alpha));
+  return ((uint32_t)((lab + 1) & 0xFFFF) << 16) | (uint32_t)f32_to_bf16(v);
+}
+
 // learned-curvature inference over the new interface cells (3D)
 void launch_mlp_curv(Ctx &c, hipStream_t s);
+
+// table of canonical stencil slots for the 48 cube symmetries (48 x 128 bytes)
+void build_canon_table(uint8_t *lut, hipStream_t s);
 
 // initial gas content and pressure of the nucleus ids 1..nn (p0 in device memory)
 void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn);

@@ -406,127 +406,273 @@ static void backward(Net &n, hipStream_t s, const float *X, const float *Y, int 
 }
 
 // ---------------------------------------------------------------- step inference
-// One work-group takes 64 interface cells at a time: the canonical 5x5x5 stencils go to
-// LDS as bfloat16, the two hidden layers run on the matrix cores (each wave 16 cells x 64
-// units), the output layer on the vector units. A cell whose stencil meets a wall, leaves
-// the domain or meets a gas / interface cell of another bubble, or whose network
-// curvature exceeds the trained range |kappa| <= 1/2, is left to the plain fit.
+// Each wave takes 16 interface cells at a time, independently of the other waves of
+// its work-group: it gathers the 5x5x5 stencils in natural order (contiguous along x)
+// and writes each value to its canonical position in the wave's LDS rows as bfloat16,
+// runs the two hidden layers on the matrix cores (16 cells x 64 units, weights held
+// transposed in LDS so that each B fragment is one 8-byte read), and the output layer
+// as a 16-lane shuffle reduction. A cell whose stencil meets a wall, leaves the domain
+// or meets a gas / interface cell of another bubble, or whose network curvature exceeds
+// the trained range |kappa| <= 1/2, is left to the plain fit.
+struct MlpWaveLds {
+  // canonical stencils of 16 cells; the first hidden layer overwrites them once the
+  // wave's layer-1 products have read them
+  union {
+    short a[16][NPD + 4];
+    short h[16][NH + 4];
+  };
+  // the 64 cells of the wave's tile
+  int cell[64], x[64], y[64], z[64], lab[64], code[64];
+  float ac[64];
+};
+
+// bfloat16 bits of a binary32 value, round to nearest even (hardware conversion)
+__device__ __forceinline__ short bf16_hw(float f) { return __builtin_bit_cast(short, (__bf16)f); }
+
+// GELU for inference: erf from the rational approximation of Abramowitz & Stegun (1964),
+// formula 7.1.26 (absolute error below 1.5e-7, far under the bfloat16 rounding that
+// follows every activation), with the hardware base-2 exponential and reciprocal
+__device__ __forceinline__ float gelu_fast(float z) {
+  const float x = fabsf(z) * 0.7071067811865476f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  const float y = 1.0f - poly * t * __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);
+  return 0.5f * z * (1.0f + (z < 0.0f ? -y : y));
+}
+
+// index of a cube symmetry: 6 axis orders times 8 flip patterns
+__device__ __forceinline__ int sym_index(const int order[3], const int flip[3]) {
+  const int perm = order[0] == 0 ? (order[1] == 1 ? 0 : 1) : (order[0] == 1 ? (order[1] == 0 ? 2 : 3) : (order[1] == 0 ? 4 : 5));
+  return perm * 8 + flip[0] + 2 * flip[1] + 4 * flip[2];
+}
+
+// canonical slot of each natural stencil element for each of the 48 symmetries: the
+// canonical axis a reads source axis order[a], negated when that axis is flipped
+__global__ void k_canon_table(uint8_t *lut) {
+  static constexpr int ord[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 48 * NPD; i += gridDim.x * blockDim.x) {
+    const int k = i / NPD, j = i % NPD;
+    uint8_t v = 0;
+    if (j < NF) {
+      const int flip[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+      const int dsrc[3] = {j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2};
+      int e[3];
+      for (int a = 0; a < 3; ++a) {
+        const int o = ord[k >> 3][a];
+        e[a] = flip[o] ? -dsrc[o] : dsrc[o];
+      }
+      v = (uint8_t)((e[0] + 2) + 5 * (e[1] + 2) + 25 * (e[2] + 2));
+    }
+    lut[i] = v;
+  }
+}
+
+void build_canon_table(uint8_t *lut, hipStream_t s) {
+  hipLaunchKernelGGL(k_canon_table, dim3(24), dim3(256), 0, s, lut);
+}
+
+// fill fraction a stencil reads at a cell of type t (walls read the centre value)
+template <class R>
+__device__ __forceinline__ float stencil_value(int t, R alpha, float centre) {
+  return t == TG ? 0.0f : (t == TL ? 1.0f : (t == TI ? fminf(1.0f, fmaxf(0.0f, (float)alpha)) : centre));
+}
+
+template <class T> __device__ __forceinline__ T uniform(T v) {
+  return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
   using R = typename Prec<P>::R;
-  __shared__ short sA[64][NPD + 4];
-  __shared__ short sH[64][NH + 4];
-  __shared__ int s_cell[64], s_ok[64], s_ord[64][3], s_flip[64][3], s_lab[64];
-  __shared__ float s_ac[64];
+  __shared__ short sW1[NH][NPD + 4];  // W1 transposed: [unit][input]
+  __shared__ short sW2[NH][NH + 4];   // W2 transposed: [unit][input]
+  __shared__ float sB1[NH], sB2[NH], sW3[NH];
+  __shared__ MlpWaveLds sw[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint16_t *W = d.mlp_w;  // bf16: W1 [128][64], W2 [64][64], W3 [64]
+  const float *bias = d.mlp_b;  // b1 [64], b2 [64], b3
+  const uint8_t *lut = d.mlp_canon;
+  for (int i = tid; i < NPD * NH; i += 256) sW1[i % NH][i / NH] = (short)W[i];
+  for (int i = tid; i < NH * NH; i += 256) sW2[i % NH][i / NH] = (short)W[NPD * NH + i];
+  if (tid < NH) {
+    sB1[tid] = bias[tid];
+    sB2[tid] = bias[NH + tid];
+    sW3[tid] = __uint_as_float(((uint32_t)W[NPD * NH + NH * NH + tid]) << 16);
+  }
+  __syncthreads();
+  const float b3 = bias[2 * NH];
+  MlpWaveLds &M = sw[wave];
+  const R *alpha = (const R *)d.alpha;
+
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
   const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
   const int64_t total = (int64_t)nI + nNI + nL;
-  const uint16_t *W = d.mlp_w;  // bf16: W1 [128][64], W2 [64][64], W3 [64]
-  const float *bias = d.mlp_b;  // b1 [64], b2 [64], b3
-  for (int64_t t0 = (int64_t)blockIdx.x * 64; t0 < total; t0 += (int64_t)gridDim.x * 64) {
-    if (tid < 64) {
-      const int64_t k = t0 + tid;
+  const int64_t nxy = (int64_t)p.nx * p.ny;
+  const bool periodic = p.per[0] || p.per[1] || p.per[2];
+  const int r = lane & 15, kq = (lane >> 4) * 4;
+  // the lane's two stencil elements j = lane and lane + 64 as index offsets
+  const int64_t off0 = (int64_t)(lane % 5 - 2) + (int64_t)p.nx * ((lane / 5) % 5 - 2) + nxy * (lane / 25 - 2);
+  const int j1 = lane + 64;
+  const int64_t off1 = (int64_t)(j1 % 5 - 2) + (int64_t)p.nx * ((j1 / 5) % 5 - 2) + nxy * (j1 / 25 - 2);
+  for (int64_t t0 = ((int64_t)blockIdx.x * 4 + wave) * 64; t0 < total; t0 += (int64_t)gridDim.x * 4 * 64) {
+    // set-up, one cell per lane: the cell and its six axis neighbours are loaded
+    // together once the list entry is known
+    {
+      const int64_t k = t0 + lane;
       int cell = -1;
-      if (k < total) {
-        const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-        if ((d.type[n] & TMASK) == TI) cell = (int)n;
-      }
-      s_cell[tid] = cell;
-      s_ok[tid] = cell >= 0;
+      if (k < total) cell = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
+      int cx = 0, cy = 0, cz = 0, code = 0, lab = 0;
+      float ac = 0.0f;
       if (cell >= 0) {
-        int x, y, z;
-        cell_xyz(p, cell, x, y, z);
-        const float ac = fminf(1.0f, fmaxf(0.0f, (float)((const R *)d.alpha)[cell]));
-        auto av = [&](int dx, int dy, int dz) {
-          const int64_t yy = nb_index_or_none(p, x, y, z, dx, dy, dz);
-          if (yy < 0) return ac;
-          const int t = d.type[yy] & TMASK;
-          return t == TG ? 0.0f : (t == TL ? 1.0f : (t == TI ? fminf(1.0f, fmaxf(0.0f, (float)((const R *)d.alpha)[yy])) : ac));
-        };
-        int order[3], flip[3];
-        canon_map(0.5f * (av(1, 0, 0) - av(-1, 0, 0)), 0.5f * (av(0, 1, 0) - av(0, -1, 0)),
-                  0.5f * (av(0, 0, 1) - av(0, 0, -1)), order, flip);
-        for (int a = 0; a < 3; a++) { s_ord[tid][a] = order[a]; s_flip[tid][a] = flip[a]; }
-        s_lab[tid] = d.label[cell];
-        s_ac[tid] = ac;
-      }
-    }
-    __syncthreads();
-    // canonical stencils into LDS
-    for (int idx = tid; idx < 64 * NPD; idx += 256) {
-      const int c = idx / NPD, j = idx % NPD;
-      float v = 0.0f;
-      const int cell = s_cell[c];
-      if (j < NF && cell >= 0) {
-        const int e[3] = {j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2};
-        int dd[3];
-        for (int a = 0; a < 3; a++) dd[s_ord[c][a]] = s_flip[c][s_ord[c][a]] ? -e[a] : e[a];
-        int x, y, z;
-        cell_xyz(p, cell, x, y, z);
-        const int64_t yy = nb_index_or_none(p, x, y, z, dd[0], dd[1], dd[2]);
-        if (yy < 0) {
-          v = s_ac[c];
-          s_ok[c] = 0;
+        cell_xyz(p, cell, cx, cy, cz);
+        int64_t nb6[6];
+        int tn6[6];
+        R al6[6];
+        const int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nb6[q] = nb_index_or_none(p, cx, cy, cz, off[q][0], off[q][1], off[q][2]);
+        const int tc = d.type[cell] & TMASK;
+        const R al = alpha[cell];
+        lab = d.label[cell];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          tn6[q] = nb6[q] >= 0 ? d.type[nb6[q]] & TMASK : TW;
+          al6[q] = nb6[q] >= 0 ? alpha[nb6[q]] : R(0);
+        }
+        if (tc != TI) {
+          cell = -1;
         } else {
-          const int t = d.type[yy] & TMASK;
-          if (t == TW) { v = s_ac[c]; s_ok[c] = 0; }
-          else if (t == TL) v = 1.0f;
-          else {
-            if (d.label[yy] != s_lab[c]) s_ok[c] = 0;
-            v = t == TG ? 0.0f : fminf(1.0f, fmaxf(0.0f, (float)((const R *)d.alpha)[yy]));
-          }
+          ac = fminf(1.0f, fmaxf(0.0f, (float)al));
+          float v6[6];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) v6[q] = stencil_value<R>(tn6[q], al6[q], ac);
+          int order[3], flip[3];
+          canon_map(0.5f * (v6[0] - v6[1]), 0.5f * (v6[2] - v6[3]), 0.5f * (v6[4] - v6[5]), order, flip);
+          code = sym_index(order, flip);
+          // on a closed axis, a cell within two cells of the wall layer has a wall in
+          // its stencil: left to the plain fit without a gather
+          const int cxyz[3] = {cx, cy, cz}, dims[3] = {p.nx, p.ny, p.nz};
+          for (int a = 0; a < 3; ++a)
+            if (!p.per[a] && (cxyz[a] < 3 || cxyz[a] > dims[a] - 4)) code |= 64;
         }
       }
-      sA[c][j] = (short)bf16_bits(v);
+      M.cell[lane] = cell;
+      M.x[lane] = cx;
+      M.y[lane] = cy;
+      M.z[lane] = cz;
+      M.lab[lane] = lab;
+      M.code[lane] = code;
+      M.ac[lane] = ac;
     }
-    __syncthreads();
-    // hidden layers: wave w computes cells 16w..16w+15, all 64 units
-    const int r = lane & 15, kq = (lane >> 4) * 4;
+    wave_lds_sync();
+    for (int sb = 0; sb < 64; sb += 16) {
+      if (t0 + sb >= total) break;  // wave-uniform
+      // gather: slot m of a lane is element j = lane + 64 (m & 1) of cell sb + (m >> 1),
+      // at the lane's fixed offset from the cell, one stencil word per element; the loads
+      // of sixteen slots are issued before any is used
+      unsigned badm = 0;
 #pragma unroll 1
-    for (int layer = 0; layer < 2; layer++) {
-      const int K = layer == 0 ? NPD : NH;
-      const uint16_t *Wl = layer == 0 ? W : W + NPD * NH;
+      for (int m0 = 0; m0 < 32; m0 += 16) {
+        uint32_t wd[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int m = m0 + u, c = sb + (m >> 1), h = m & 1;
+          const int cc = uniform(M.cell[c]);
+          const int cd = uniform(M.code[c]);
+          int64_t yy = -1;
+          if (cc >= 0 && !(cd & 64) && (h == 0 || lane < NF - 64)) {
+            if (periodic) {
+              const int j = lane + 64 * h;
+              yy = nb_index_or_none(p, M.x[c], M.y[c], M.z[c], j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2);
+            } else {
+              yy = (int64_t)cc + (h ? off1 : off0);
+            }
+          }
+          wd[u] = yy >= 0 ? d.sword[yy] : 0xFFFF0000u;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int m = m0 + u, c = sb + (m >> 1), h = m & 1, j = lane + 64 * h;
+          const int cc = uniform(M.cell[c]);
+          if (cc < 0 || j >= NF) {
+            M.a[m >> 1][j] = 0;
+            continue;
+          }
+          const uint32_t code = wd[u] >> 16;
+          // a wall (or the outside of a closed axis), or gas / interface of another bubble
+          if (code == 0xFFFFu || (code != 0u && code != (uint32_t)(uniform(M.lab[c]) + 1))) badm |= 1u << (m >> 1);
+          const short bits = code == 0xFFFFu ? bf16_hw(uniform(M.ac[c])) : (short)(wd[u] & 0xFFFFu);
+          M.a[m >> 1][lut[(uniform(M.code[c]) & 63) * NPD + j]] = bits;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) badm |= __shfl_xor(badm, o);
+      wave_lds_sync();
+      // first hidden layer
       floatx4 acc[4];
       for (int tn = 0; tn < 4; tn++) acc[tn] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-      for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x4 a;
-        for (int j = 0; j < 4; j++) a[j] = layer == 0 ? sA[wave * 16 + r][k0 + kq + j] : sH[wave * 16 + r][k0 + kq + j];
+#pragma unroll
+      for (int k0 = 0; k0 < NPD; k0 += 16) {
+        const bf16x4 a = *(const bf16x4 *)&M.a[r][k0 + kq];
+#pragma unroll
         for (int tn = 0; tn < 4; tn++) {
-          bf16x4 b;
-          for (int j = 0; j < 4; j++) b[j] = (short)Wl[(k0 + kq + j) * NH + tn * 16 + r];
+          const bf16x4 b = *(const bf16x4 *)&sW1[tn * 16 + r][k0 + kq];
           acc[tn] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tn], 0, 0, 0);
         }
       }
-      if (layer == 1) __syncthreads();  // all waves done reading sH of layer 1
+      wave_lds_sync();  // every lane has read its stencil rows before they are overwritten
+#pragma unroll
       for (int tn = 0; tn < 4; tn++)
-        for (int j = 0; j < 4; j++) {
-          const int row = wave * 16 + kq + j, col = tn * 16 + r;
-          const float zz = acc[tn][j] + bias[layer * NH + col];
-          sH[row][col] = (short)bf16_bits(gelu(zz));
+#pragma unroll
+        for (int j = 0; j < 4; j++) M.h[kq + j][tn * 16 + r] = bf16_hw(gelu_fast(acc[tn][j] + sB1[tn * 16 + r]));
+      wave_lds_sync();
+      // second hidden layer
+      for (int tn = 0; tn < 4; tn++) acc[tn] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k0 = 0; k0 < NH; k0 += 16) {
+        const bf16x4 a = *(const bf16x4 *)&M.h[r][k0 + kq];
+#pragma unroll
+        for (int tn = 0; tn < 4; tn++) {
+          const bf16x4 b = *(const bf16x4 *)&sW2[tn * 16 + r][k0 + kq];
+          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tn], 0, 0, 0);
         }
-      __syncthreads();
-    }
-    if (tid < 64 && s_cell[tid] >= 0) {
-      float acc = 0.0f;
-      for (int j = 0; j < NH; j++)
-        acc += __uint_as_float(((uint32_t)(uint16_t)sH[tid][j]) << 16) *
-               __uint_as_float(((uint32_t)W[NPD * NH + NH * NH + j]) << 16);
-      const float kap = (acc + bias[2 * NH]) * 0.125f;
-      const int cell = s_cell[tid];
-      if (s_ok[tid] && fabsf(kap) <= 0.5f) {
-        ((R *)d.kappa)[cell] = (R)kap;
-        d.cflag[cell] = (uint8_t)CF_MLPOK;
       }
+      // output layer: lane (r, kq) holds units tn*16 + r of cells kq .. kq+3
+      float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int tn = 0; tn < 4; tn++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const float hv =
+              __uint_as_float(((uint32_t)(uint16_t)bf16_hw(gelu_fast(acc[tn][j] + sB2[tn * 16 + r]))) << 16);
+          part[j] += hv * sW3[tn * 16 + r];
+        }
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        for (int o = 8; o > 0; o >>= 1) part[j] += __shfl_xor(part[j], o);
+      if (r == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int c = kq + j;
+          const int cc = M.cell[sb + c];
+          const float kap = (part[j] + b3) * 0.125f;
+          if (cc >= 0 && !((badm >> c) & 1) && !(M.code[sb + c] & 64) && fabsf(kap) <= 0.5f) {
+            ((R *)d.kappa)[cc] = (R)kap;
+            d.cflag[cc] = (uint8_t)CF_MLPOK;
+          }
+        }
+      }
+      wave_lds_sync();
     }
-    __syncthreads();
   }
 }
 
 void launch_mlp_curv(Ctx &c, hipStream_t s) {
-  const unsigned nb = list_blocks(c) < 2048 ? list_blocks(c) : 2048;
+  // persistent work-groups (each stages the weights once); about four per CU
+  const unsigned nb = list_blocks(c) < 1024 ? list_blocks(c) : 1024;
   if (c.kp.dim != 3) return;
   switch (c.P.precision) {
     case 0: hipLaunchKernelGGL(k_mlp_curv<0>, dim3(nb), dim3(256), 0, s, c.kp, c.d); break;

@@ -21,7 +21,8 @@
 //    x component is done across lanes); it updates every liquid cell, taking
 //    bounce-back at walls from a static per-cell mask of wall directions. Interface
 //    cells take the per-cell path in a second kernel over the interface list, so the
-//    bulk kernel carries no divergent interface work.
+//    bulk kernel carries no divergent interface work (doing the interface cells in the
+//    bulk kernel, in the same wave or on their own lanes, measured slower).
 // The interface and bubble lists of the step are built before the sweep.
 #pragma once
 #include <utility>
@@ -202,6 +203,111 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
   for (int i = 0; i < Qg; ++i) gt[i] = (gt[i] - og * (gt[i] - A::geqv(i, c, dc, ux, uy, uz))) + R(Lat<D>::wg[i]) * q;
 }
 
+// The part of the update of an interface cell or a cell next to a wall that needs the
+// cell's own populations and the types of its sources: bounce-back, gas-side rebuild at
+// the bubble pressure (fluid and dissolved gas, with the gas ledger), and for interface
+// cells the mass exchange. ft / gt hold the pulled populations on entry. src(i) is the
+// index of the source x - e_i, dst(i) that of the neighbour x + e_i.
+template <int D, int P, class Src, class Dst>
+__device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64_t n, bool isI, int32_t lab,
+                                              Src src, Dst dst, typename Prec<P>::R *ft, typename Prec<P>::R *gt,
+                                              typename Prec<P>::R &Ms, bool &hasG, bool &hasF,
+                                              typename Prec<P>::R &phic, bool &hasgas) {
+  using L = Lat<D>;
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  using SG = typename Prec<P>::SG;
+  using FC = FCodec<P, D>;
+  using GC = GCodec<P>;
+  using A = Arith<D, P>;
+  constexpr int Q = L::Q, Qg = L::Qg;
+  const SF *fin = (const SF *)d.f[cur];
+  const SG *gin = (const SG *)d.g[cur];
+  const int64_t Np = p.Np;
+  R own[Q], gown[Qg];
+  uint8_t tsrc[Q];
+  // the cell's own outgoing populations and the types of its sources, all loads issued
+  // together
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    own[i] = FC::dec(fin[(int64_t)i * Np + n], i);
+    if (i < Qg) gown[i] = GC::dec(gin[(int64_t)i * Np + n], p);
+    tsrc[i] = d.type[src(i)] & TMASK;
+  }
+  R rg = R(1), uox = R(0), uoy = R(0), uoz = R(0), uou = R(0), cH = R(0), dcH = R(0);
+  if (isI) {
+    double pb = p.p_atm;
+    if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
+    else raise_status(d.status, ST_BADLABEL);
+    const R kap = ((const R *)d.kappa)[n], pi = ((const R *)d.Pi)[n];
+    rg = R(3) * ((R(pb) - R(2) * R(p.sigma) * kap) - pi);
+    cH = R(p.kH) * R(pb);
+    dcH = cH - R(p.c0);
+    uox = ((const R *)d.ux)[n];
+    uoy = ((const R *)d.uy)[n];
+    uoz = D == 3 ? ((const R *)d.uz)[n] : R(0);
+    uou = usq<D, R>(uox, uoy, uoz);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (i > 0 && tsrc[i] == TG) hasG = true;
+    if (i > 0 && (tsrc[i] == TL || tsrc[i] == TI)) hasF = true;
+    if (tsrc[i] == TW) {
+      ft[i] = own[opp(i)];
+    } else if (tsrc[i] == TG) {
+      if (!isI) raise_status(d.status, ST_INVARIANT);
+      ft[i] = (A::eq(i, rg, rg - R(1), uox, uoy, uoz, uou) + A::eq(opp(i), rg, rg - R(1), uox, uoy, uoz, uou)) -
+              own[opp(i)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Qg; ++i) {
+    if (tsrc[i] == TW) {
+      gt[i] = gown[opp(i)];
+    } else if (tsrc[i] == TG) {
+      gt[i] = (A::geqv(i, cH, dcH, uox, uoy, uoz) + A::geqv(opp(i), cH, dcH, uox, uoy, uoz)) - gown[opp(i)];
+      phic = phic + (gown[opp(i)] - gt[i]);
+      hasgas = true;
+    }
+  }
+  if (isI) {
+    // interface mass exchange with liquid and interface neighbours y = x + e_i
+    const R ax = ((const R *)d.alpha)[n];
+    R dm = R(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int tn = tsrc[opp(i)];
+      if (tn == TL) {
+        dm = dm + (ft[opp(i)] - own[i]);
+      } else if (tn == TI) {
+        const R ay = ((const R *)d.alpha)[dst(i)];
+        dm = dm + (R(0.5) * (ax + ay)) * (ft[opp(i)] - own[i]);
+      }
+    }
+    Ms = ((const R *)d.M)[n] + dm;
+  }
+}
+
+// what an interface cell stores besides its populations: density, velocity, mass and
+// its fill / empty class (Sec. 2.1)
+template <int D, class R>
+__device__ __forceinline__ void store_interface(const KP &p, DA &d, int64_t n, R rho, R ux, R uy, R uz, R Ms,
+                                                bool hasG, bool hasF) {
+  ((R *)d.rho)[n] = rho;
+  ((R *)d.ux)[n] = ux;
+  ((R *)d.uy)[n] = uy;
+  if (D == 3) ((R *)d.uz)[n] = uz;
+  ((R *)d.M)[n] = Ms;
+  uint8_t cl = 0;
+  if (Ms > (R(1) + R(p.eps)) * rho) cl = CF_FILL;
+  else if (Ms < (-R(p.eps)) * rho) cl = CF_EMPTY;
+  else if (p.cleanup) {
+    if (!hasG) cl = CF_FILL;
+    else if (!hasF) cl = CF_EMPTY;
+  }
+  d.cflag[n] = cl;
+}
+
 // The whole update of one cell (x, y, z) = n with type byte tb and bubble id lab; lanes
 // with fluid == false only take part in the wave-level gas-ledger sum. Called by the
 // whole wave.
@@ -214,7 +320,6 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
   using SG = typename Prec<P>::SG;
   using FC = FCodec<P, D>;
   using GC = GCodec<P>;
-  using A = Arith<D, P>;
   constexpr int Q = L::Q, Qg = L::Qg;
   const int t = tb & TMASK;
   const bool isI = fluid && t == TI;
@@ -235,73 +340,11 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
       if (i < Qg) gt[i] = GC::dec(gin[(int64_t)i * Np + s], p);
     }
     R Ms = R(0);
-    const bool special = isI || (tb & NEARWALL);
     bool hasG = false, hasF = false;
-    if (special) {
-      R own[Q], gown[Qg];
-      uint8_t tsrc[Q];
-      // the cell's own outgoing populations (bounce-back, mass exchange) and the types
-      // of its sources, all loads issued together
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        own[i] = FC::dec(fin[(int64_t)i * Np + n], i);
-        if (i < Qg) gown[i] = GC::dec(gin[(int64_t)i * Np + n], p);
-        const int64_t s = nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
-        tsrc[i] = d.type[s] & TMASK;
-      }
-      R rg = R(1), uox = R(0), uoy = R(0), uoz = R(0), uou = R(0), cH = R(0), dcH = R(0);
-      if (isI) {
-        double pb = p.p_atm;
-        if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
-        else raise_status(d.status, ST_BADLABEL);
-        const R kap = ((const R *)d.kappa)[n], pi = ((const R *)d.Pi)[n];
-        rg = R(3) * ((R(pb) - R(2) * R(p.sigma) * kap) - pi);
-        cH = R(p.kH) * R(pb);
-        dcH = cH - R(p.c0);
-        uox = ((const R *)d.ux)[n];
-        uoy = ((const R *)d.uy)[n];
-        uoz = D == 3 ? ((const R *)d.uz)[n] : R(0);
-        uou = usq<D, R>(uox, uoy, uoz);
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        if (i > 0 && tsrc[i] == TG) hasG = true;
-        if (i > 0 && (tsrc[i] == TL || tsrc[i] == TI)) hasF = true;
-        if (tsrc[i] == TW) {
-          ft[i] = own[opp(i)];
-        } else if (tsrc[i] == TG) {
-          if (!isI) raise_status(d.status, ST_INVARIANT);
-          ft[i] = (A::eq(i, rg, rg - R(1), uox, uoy, uoz, uou) + A::eq(opp(i), rg, rg - R(1), uox, uoy, uoz, uou)) -
-                  own[opp(i)];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < Qg; ++i) {
-        if (tsrc[i] == TW) {
-          gt[i] = gown[opp(i)];
-        } else if (tsrc[i] == TG) {
-          gt[i] = (A::geqv(i, cH, dcH, uox, uoy, uoz) + A::geqv(opp(i), cH, dcH, uox, uoy, uoz)) - gown[opp(i)];
-          phic = phic + (gown[opp(i)] - gt[i]);
-          hasgas = true;
-        }
-      }
-      if (isI) {
-        // interface mass exchange with liquid and interface neighbours y = x + e_i
-        const R ax = ((const R *)d.alpha)[n];
-        R dm = R(0);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const int tn = tsrc[opp(i)];
-          if (tn == TL) {
-            dm = dm + (ft[opp(i)] - own[i]);
-          } else if (tn == TI) {
-            const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-            const R ay = ((const R *)d.alpha)[yy];
-            dm = dm + (R(0.5) * (ax + ay)) * (ft[opp(i)] - own[i]);
-          }
-        }
-        Ms = ((const R *)d.M)[n] + dm;
-      }
+    if (isI || (tb & NEARWALL)) {
+      auto src = [&](int i) { return nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]); };
+      auto dst = [&](int i) { return nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]); };
+      special_terms<D, P>(p, d, cur, n, isI, lab, src, dst, ft, gt, Ms, hasG, hasF, phic, hasgas);
     }
     R rho, ux, uy, uz;
     collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
@@ -309,21 +352,7 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
     for (int i = 0; i < Q; ++i) fout[(int64_t)i * Np + n] = FC::enc(ft[i], i);
 #pragma unroll
     for (int i = 0; i < Qg; ++i) gout[(int64_t)i * Np + n] = GC::enc(gt[i], p);
-    if (isI) {
-      ((R *)d.rho)[n] = rho;
-      ((R *)d.ux)[n] = ux;
-      ((R *)d.uy)[n] = uy;
-      if (D == 3) ((R *)d.uz)[n] = uz;
-      ((R *)d.M)[n] = Ms;
-      uint8_t cl = 0;
-      if (Ms > (R(1) + R(p.eps)) * rho) cl = CF_FILL;
-      else if (Ms < (-R(p.eps)) * rho) cl = CF_EMPTY;
-      else if (p.cleanup) {
-        if (!hasG) cl = CF_FILL;
-        else if (!hasF) cl = CF_EMPTY;
-      }
-      d.cflag[n] = cl;
-    }
+    if (isI) store_interface<D, R>(p, d, n, rho, ux, uy, uz, Ms, hasG, hasF);
   }
   wave_fx_add(d.phi, hasgas && lab >= 0 && lab < p.cap, lab, fx3((double)phic));
 }
@@ -357,7 +386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 // ------------------------------------------------------------------ split form
-// interface cells (this step's interface list)
+// interface cells (this step's interface list) through the per-cell update
 template <int D, int P>
 __global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
   LIST_LOOP(k, d.cnt + C_I) {
@@ -479,21 +508,20 @@ __global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
 #pragma unroll
     for (int e = 0; e < VW; ++e) tv[e] = TW;
   }
-  bool plain[VW];
-  bool anyplain = false, allplain = true, anywall = false;
+  bool liquid[VW];
+  bool anyliquid = false, anywall = false;
 #pragma unroll
   for (int e = 0; e < VW; ++e) {
     const uint8_t tb = tv[e];
-    plain[e] = (tb & TMASK) == TL;
-    anyplain = anyplain || plain[e];
-    allplain = allplain && plain[e];
-    anywall = anywall || (plain[e] && (tb & NEARWALL));
+    liquid[e] = (tb & TMASK) == TL;
+    anyliquid = anyliquid || liquid[e];
+    anywall = anywall || (liquid[e] && (tb & NEARWALL));
   }
-  if (__ballot(anyplain) == 0) return;  // wave-uniform
+  if (__ballot(anyliquid) == 0) return;  // wave-uniform
 
   // aligned loads stay inside [0, N) for groups whose start lies in [lo, hi]; every group
-  // holding a liquid cell does (liquid cells are never on the outer layer of a closed
-  // axis, which is all walls). Other lanes load from lo: their values are never stored.
+  // holding a fluid cell does (fluid cells are never on the outer layer of a closed axis,
+  // which is all walls). Other lanes load from lo: their values are never stored.
   const int64_t offA = (int64_t)p.nx * (D == 3 ? (int64_t)p.ny + 1 : 1);
   const int64_t lo = offA, hi = N - offA - VW;
   const bool safe = n0 >= lo && n0 <= hi;
@@ -510,16 +538,16 @@ __global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
   const SG *gin = (const SG *)d.g[cur];
 #pragma unroll
   for (int e = 0; e < VW; ++e) {
-    if (plain[e]) {
+    if (liquid[e]) {
       R ft[Q], gt[Qg];
 #pragma unroll
       for (int i = 0; i < Q; ++i) ft[i] = FC::dec(fv[i][e], i);
 #pragma unroll
       for (int i = 0; i < Qg; ++i) gt[i] = GC::dec(gv[i][e], p);
+      const int64_t n = n0 + e;
       if (anywall && (tv[e] & NEARWALL)) {
         // bounce-back: a population whose source is a wall is the cell's own outgoing
         // population of the opposite direction
-        const int64_t n = n0 + e;
         const uint32_t wm = d.wmask[n];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -538,22 +566,18 @@ __global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
     }
   }
 
+  // Whole-group stores for every lane holding a liquid cell. The other cells of the group
+  // receive values that nothing reads: populations of wall and gas cells are never used
+  // (bounce-back and the gas-side rebuild take the receiving cell's own values, and a
+  // gas cell that turns interface is initialised afresh), and interface cells are
+  // rewritten by the interface kernel that follows.
   SF *fout = (SF *)d.f[cur ^ 1];
   SG *gout = (SG *)d.g[cur ^ 1];
-  if (allplain) {
+  if (anyliquid) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) *(VF *)(fout + (int64_t)i * p.Np + n0) = fv[i];
 #pragma unroll
     for (int i = 0; i < Qg; ++i) *(VG *)(gout + (int64_t)i * p.Np + n0) = gv[i];
-  } else {
-#pragma unroll
-    for (int e = 0; e < VW; ++e) {
-      if (!plain[e]) continue;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) fout[(int64_t)i * p.Np + n0 + e] = fv[i][e];
-#pragma unroll
-      for (int i = 0; i < Qg; ++i) gout[(int64_t)i * p.Np + n0 + e] = gv[i][e];
-    }
   }
 }
 
@@ -561,7 +585,7 @@ __global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
 template <int P> constexpr int vec_width() { return P == 1 ? 2 : 4; }
 
 template <int D, int P>
-bool use_split(const Ctx &c) {
+bool use_vector(const Ctx &c) {
   constexpr int VW = vec_width<P>();
   if (P == 0) return false;
   if (c.kp.per[0] || c.kp.per[1] || c.kp.per[2]) return false;
@@ -571,7 +595,7 @@ bool use_split(const Ctx &c) {
 template <int D, int P>
 void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t mid) {
   if constexpr (P != 0) {
-    if (use_split<D, P>(c)) {
+    if (use_vector<D, P>(c)) {
       constexpr int VW = vec_width<P>();
       const int64_t nb = (c.kp.N + 256 * VW - 1) / (256 * VW);
       hipLaunchKernelGGL((k_sweep_vec<D, P, VW>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
