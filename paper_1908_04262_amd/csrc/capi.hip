@@ -128,6 +128,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.lab_assigned = cv.take<int32_t>(cap * 4);
   d.lab_vtot = cv.take<long long>(cap * 24);
   d.lab_vatm = cv.take<long long>(cap * 24);
+  d.vacc = cv.take<long long>(cap * 24);
   d.rh_key = cv.take<int32_t>((size_t)kp.RH * 4);
   d.rh_head = cv.take<int32_t>((size_t)kp.RH * 4);
   d.contested = cv.take<int32_t>((size_t)kp.ecap * 4);

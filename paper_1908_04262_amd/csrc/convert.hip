@@ -279,6 +279,181 @@ __global__ __launch_bounds__(256) void k_clear_conv_flags(DA d) {
   }
 }
 
+// Whether this step's conversions can have changed the connected components of the gas
+// and interface cells. Only cells that fill (leave the set) and liquid cells that turn
+// interface (join it) change the set.
+//  - A joining cell whose gas / interface neighbours all carry its own id merges nothing.
+//  - A leaving cell of the atmosphere (next to a gas / interface cell with id 0) changes
+//    nothing: every piece of the atmosphere keeps id 0, and no bubble touches it.
+//  - Another leaving cell x: let K be the leaving cells connected to x inside its 3^d block
+//    (none of them with a leaving lattice neighbour outside that block, else the test
+//    fails), and R the remaining gas / interface lattice neighbours of K. If R is not
+//    empty and connected inside the 5^d window around x without the leaving cells, every
+//    path through K has a detour, so nothing splits or disappears.
+// When any cell fails, the flag is set and the full labelling runs; otherwise ids, merges
+// and splits stay as they were.
+struct Bits128 {
+  uint64_t w[2];
+  __device__ bool get(int q) const { return (w[q >> 6] >> (q & 63)) & 1ull; }
+  __device__ void set(int q) { w[q >> 6] |= 1ull << (q & 63); }
+};
+
+__device__ __forceinline__ Bits128 shift128(Bits128 v, int s) {
+  Bits128 o;
+  if (s > 0) {
+    o.w[0] = v.w[0] << s;
+    o.w[1] = (v.w[1] << s) | (v.w[0] >> (64 - s));
+  } else if (s < 0) {
+    const int t = -s;
+    o.w[0] = (v.w[0] >> t) | (v.w[1] << (64 - t));
+    o.w[1] = v.w[1] >> t;
+  } else {
+    o = v;
+  }
+  return o;
+}
+
+// One step of lattice dilation of a window mask, computed by the whole wave: lane i < Q-1
+// moves the set along direction i+1 (positions whose step leaves the window are dropped
+// by the lane's mask `valid`), and the lanes' results are OR-ed together.
+__device__ __forceinline__ Bits128 dilate(Bits128 v, Bits128 valid, int shift, bool active) {
+  Bits128 m = {{v.w[0] & valid.w[0], v.w[1] & valid.w[1]}};
+  Bits128 o = active ? shift128(m, shift) : Bits128{{0, 0}};
+  for (int off = 32; off > 0; off >>= 1) {
+    o.w[0] |= __shfl_xor(o.w[0], off);
+    o.w[1] |= __shfl_xor(o.w[1], off);
+  }
+  o.w[0] |= v.w[0];
+  o.w[1] |= v.w[1];
+  return o;
+}
+
+// flood of `seed` inside `allowed` (wave-uniform loop)
+__device__ __forceinline__ Bits128 flood(Bits128 seed, Bits128 allowed, Bits128 valid, int shift, bool active) {
+  Bits128 r = seed;
+  for (int it = 0; it < 16; ++it) {
+    Bits128 n = dilate(r, valid, shift, active);
+    n.w[0] &= allowed.w[0];
+    n.w[1] &= allowed.w[1];
+    n.w[0] |= seed.w[0];
+    n.w[1] |= seed.w[1];
+    if (n.w[0] == r.w[0] && n.w[1] == r.w[1]) break;
+    r = n;
+  }
+  return r;
+}
+
+// The window test of one leaving cell, by the whole wave, from the masks of gas /
+// interface cells (g) and leaving cells (f) of its 5^d window (position dx + 5 dy +
+// 25 dz, offsets -2..2); true when the cell may split or remove a component. K: the
+// leaving cells connected to the centre inside its 3^d block; R: the gas / interface
+// lattice neighbours of K.
+template <int D>
+__device__ bool window_changes(Bits128 g, Bits128 f) {
+  using L = Lat<D>;
+  constexpr int W = 5, NW = D == 3 ? 125 : 25, CEN = D == 3 ? 62 : 12;
+  const int lane = lane_id();
+  const bool active = lane < L::Q - 1;
+  const int i = active ? lane + 1 : 1;
+  const int shift = L::ex[i] + W * L::ey[i] + W * W * L::ez[i];
+  Bits128 valid = {{0, 0}}, inner = {{0, 0}};
+  for (int q = 0; q < NW; ++q) {
+    const int dx = q % W - 2, dy = (q / W) % W - 2, dz = D == 3 ? q / (W * W) - 2 : 0;
+    const int ax = dx + L::ex[i], ay = dy + L::ey[i], az = dz + L::ez[i];
+    if (ax >= -2 && ax <= 2 && ay >= -2 && ay <= 2 && az >= -2 && az <= 2) valid.w[q >> 6] |= 1ull << (q & 63);
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) inner.w[q >> 6] |= 1ull << (q & 63);
+  }
+  Bits128 cen = {{0, 0}};
+  cen.w[CEN >> 6] = 1ull << (CEN & 63);
+  Bits128 fin = {{f.w[0] & inner.w[0], f.w[1] & inner.w[1]}};
+  fin.w[CEN >> 6] |= 1ull << (CEN & 63);
+  const Bits128 K = flood(cen, fin, valid, shift, active);
+  const Bits128 DK = dilate(K, valid, shift, active);
+  // a leaving neighbour of K outside the block: the cluster may continue beyond the window
+  if ((DK.w[0] & f.w[0] & ~inner.w[0]) || (DK.w[1] & f.w[1] & ~inner.w[1])) return true;
+  const Bits128 R = {{DK.w[0] & g.w[0], DK.w[1] & g.w[1]}};
+  if (!R.w[0] && !R.w[1]) return true;
+  Bits128 seed = {{0, 0}};
+  if (R.w[0]) seed.w[0] = R.w[0] & (~R.w[0] + 1);
+  else seed.w[1] = R.w[1] & (~R.w[1] + 1);
+  const Bits128 reach = flood(seed, g, valid, shift, active);
+  return (R.w[0] & ~reach.w[0]) || (R.w[1] & ~reach.w[1]);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
+  using L = Lat<D>;
+  constexpr int W = 5, NW = D == 3 ? 125 : 25;
+  __shared__ int s_cand[256];
+  __shared__ int s_nc;
+  if (threadIdx.x == 0) s_nc = 0;
+  __syncthreads();
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nL;
+  // a periodic axis shorter than the window would wrap it onto itself: full labelling
+  bool change = total > 0 && ((p.per[0] && p.nx < W) || (p.per[1] && p.ny < W) || (D == 3 && p.per[2] && p.nz < W));
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total && !change; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k >= nI) {
+      const int64_t n = d.l2ilist[k - nI];
+      const int32_t lx = d.label[n];
+      int x, y, z;
+      cell_xyz(p, n, x, y, z);
+      for (int i = 1; i < L::Q; ++i) {
+        const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+        if (yy < 0) continue;
+        const int t = d.type[yy] & TMASK;
+        if ((t == TG || t == TI) && d.label[yy] != lx) change = true;
+      }
+      continue;
+    }
+    const int64_t n = d.ilist[k];
+    if (!(d.cflag[n] & CF_FILL)) continue;
+    int x, y, z;
+    cell_xyz(p, n, x, y, z);
+    // a leaving cell of the atmosphere (a gas / interface neighbour with id 0) changes no
+    // bubble: every piece of the atmosphere keeps id 0 and no bubble touches it
+    bool atm = false;
+    for (int i = 1; i < L::Q; ++i) {
+      const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+      if (yy < 0) continue;
+      const int t = d.type[yy] & TMASK;
+      if ((t == TG || t == TI) && d.label[yy] == 0) atm = true;
+    }
+    if (atm) continue;
+    const int c = atomicAdd(&s_nc, 1);  // LDS
+    if (c < 256) s_cand[c] = (int)n;
+    else change = true;
+  }
+  __syncthreads();
+  // window tests, one wave per candidate: the lanes load the window, lane 0 decides
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int nc = s_nc < 256 ? s_nc : 256;
+  for (int c = wave; c < nc; c += 4) {
+    const int64_t n = s_cand[c];
+    int x, y, z;
+    cell_xyz(p, n, x, y, z);
+    Bits128 g, f;
+    for (int h = 0; h < 2; ++h) {
+      const int q = lane + 64 * h;
+      bool gq = false, fq = false;
+      if (q < NW) {
+        const int dx = q % W - 2, dy = (q / W) % W - 2, dz = D == 3 ? q / (W * W) - 2 : 0;
+        const int64_t yy = nb_index_or_none(p, x, y, z, dx, dy, dz);
+        if (yy >= 0) {
+          const int t = d.type[yy] & TMASK;
+          gq = t == TG || t == TI;
+          fq = !gq && (d.cflag[yy] & CF_FILL);
+        }
+      }
+      g.w[h] = __ballot(gq);
+      f.w[h] = __ballot(fq);
+    }
+    if (window_changes<D>(g, f) && lane == 0) change = true;
+  }
+  if (__ballot(change) != 0 && lane_id() == 0) d.cnt[C_TOPO] = 1;
+}
+
 template <int D, int P>
 void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   const unsigned nb = list_blocks(c);
@@ -287,6 +462,7 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL((k_empty_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_l2i_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_apply<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_topo_check<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_ni_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);

@@ -49,6 +49,7 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
        k < ((total + 63) & ~(int64_t)63); k += (int64_t)gridDim.x * blockDim.x)
 
 __global__ __launch_bounds__(256) void k_ccl_init(DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
     const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(256) void k_ccl_init(DA d) {
 
 template <int D>
 __global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   using L = Lat<D>;
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
 }
 
 __global__ __launch_bounds__(256) void k_ccl_compress(DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
     const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
@@ -116,6 +119,7 @@ __device__ __forceinline__ int hash_insert(const KP &p, DA &d, unsigned long lon
 // volume share (1 - alpha) of every bubble cell, summed per (component root, old id)
 template <int P>
 __global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   using R = typename Prec<P>::R;
   CLIST_LOOP(k, n, total) {
     bool act = false;
@@ -198,6 +202,7 @@ __device__ void write_bubble(const KP &p, DA &d, int id, double m, __int128 vk) 
 // parallel; the few whose ids are shared with another component (splits) are done in
 // ascending root order by one thread, which is the order the assignment rule needs.
 __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_flux) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   const int tid = threadIdx.x, nt = blockDim.x;
   const int cap = p.cap;
   __shared__ int s_ncont, s_nroot;
@@ -403,6 +408,7 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
 }
 
 __global__ __launch_bounds__(256) void k_ccl_relabel(DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
     const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
@@ -412,6 +418,7 @@ __global__ __launch_bounds__(256) void k_ccl_relabel(DA d) {
 }
 
 __global__ __launch_bounds__(256) void k_ccl_clear(DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
     const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
@@ -419,9 +426,74 @@ __global__ __launch_bounds__(256) void k_ccl_clear(DA d) {
   }
 }
 
+// ------------------------------------------------------------------ fast path
+// Steps whose conversions cannot have changed any component (C_TOPO clear) keep every
+// id; each bubble then holds all of its gas, and only its volume and pressure change.
+// The sums are the same fixed-point sums as the full path's, so the results are
+// identical to what the full labelling would give.
+template <int P>
+__global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
+  CLIST_LOOP(k, n, total) {
+    bool act = false;
+    int lab = 0;
+    Fx3 v = {0, 0, 0};
+    if (k < total) {
+      const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+      const int t = d.type[n] & TMASK;
+      if (t == TG || t == TI) {
+        lab = d.label[n];
+        if (lab > 0 && lab < p.cap) {
+          act = true;
+          const R one_minus = t == TG ? R(1) : R(1) - ((const R *)d.alpha)[n];
+          v = fx3((double)one_minus);
+        }
+      }
+    }
+    wave_fx_add(d.vacc, act, lab, v);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_bubble_fast(KP p, DA d) {
+  if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ long long s_atm[3];
+  int jmax = *(volatile int32_t *)(d.cnt + C_NEXTID);
+  if (jmax > p.cap) jmax = p.cap;
+  if (tid == 0) {
+    s_atm[0] = d.phi[0] + d.gam[0];
+    s_atm[1] = d.phi[1] + d.gam[1];
+    s_atm[2] = d.phi[2] + d.gam[2];
+  }
+  __syncthreads();
+  for (int j = tid; j < jmax; j += nt) {
+    if (j > 0 && d.balive[j]) {
+      const double mp = d.bm[j] + fx_to_double(join3(&d.phi[3 * j]) + join3(&d.gam[3 * j]));
+      write_bubble(p, d, j, mp, join3(&d.vacc[3 * j]));
+    }
+    for (int c = 0; c < 3; ++c) d.phi[3 * j + c] = d.gam[3 * j + c] = d.vacc[3 * j + c] = 0;
+  }
+  if (tid == 0) {
+    d.ledtot[0] += join3(&d.led[0]);
+    d.ledtot[1] += join3(&d.led[3]) + fx3_join(s_atm[0], s_atm[1], s_atm[2]);
+    d.ledtot[2] += join3(&d.led[6]);
+    for (int c = 0; c < 9; ++c) d.led[c] = 0;
+    d.bp[0] = p.p_atm;
+    d.balive[0] = 1;
+    d.cnt[C_CONTESTED] = 0;
+  }
+}
+
+// outside the time step (nucleation, refresh) the full labelling always runs
+__global__ void k_force_full(DA d) { d.cnt[C_TOPO] = 1; }
+
 template <int D, int P>
 void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   const unsigned nb = list_blocks(c);
+  if (!apply_flux) hipLaunchKernelGGL(k_force_full, dim3(1), dim3(1), 0, s, c.d);
+  hipLaunchKernelGGL((k_vol_fast<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_bubble_fast, dim3(1), dim3(1024), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_ccl_init, dim3(nb), dim3(256), 0, s, c.d);
   hipLaunchKernelGGL((k_ccl_hook<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_ccl_compress, dim3(nb), dim3(256), 0, s, c.d);

@@ -26,7 +26,8 @@ constexpr int ST_NONFINITE = 4;   // non-finite density at an interface cell
 constexpr int ST_BADLABEL = 8;    // interface cell with an invalid bubble id
 
 // counters
-enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_NEXTID, C_NCOUNT = 16 };
+// C_TOPO: set when this step's conversions may have merged, split or removed a component
+enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_NEXTID, C_NCOUNT = 16 };
 
 // ------------------------------------------------------------------ lattices
 // D2Q9 / D3Q19 velocity sets and weights (Sec. 2); the ADE lattices D2Q5 / D3Q7 are
@@ -166,6 +167,7 @@ struct DA {
   int32_t *lab_first;         // smallest non-atmosphere root containing each id [cap]
   int32_t *lab_assigned;      // [cap]
   long long *lab_vtot, *lab_vatm; // [cap][3]
+  long long *vacc;            // per-id volume sums of the labelling fast path [cap][3], zero between steps
   int32_t *rh_key, *rh_head;  // root hash [RH]
   int32_t *rused;             // used root-hash slots [ecap]
   int32_t *contested;         // [ecap]

@@ -221,3 +221,62 @@ def test_low_precision_mass_and_volumes(case, prec):
             _say(f"  step {10 * (k + 1)}: max volume deviation {dv.max():.2e}")
             assert dv.max() < (0.005 if prec == "fp32" else 0.01), dv.max()
         assert abs(_liquid(gpu) - m0) / m0 < 1e-6
+
+
+def _dumbbell(neck_rows):
+    """Two gas blobs joined by a neck of interface cells one column wide; the neck has no
+    gas neighbour, so the cleanup rule fills it in the next step. With one neck row the
+    bubble splits in two; with two rows the blobs stay joined."""
+    nx, ny = 16, 11
+    T = np.full((1, ny, nx), 2, np.uint8)
+    T[0, 0, :] = T[0, -1, :] = 3
+    T[0, :, 0] = T[0, :, -1] = 3
+    lab = np.full((1, ny, nx), -1, np.int32)
+    al = np.ones((1, ny, nx))
+    c = 5
+    for cx in (4, 11):
+        for y in range(c - 2, c + 3):
+            for x in range(cx - 2, cx + 3):
+                T[0, y, x] = 1
+                lab[0, y, x] = 1
+                al[0, y, x] = 0.5
+        T[0, c, cx - 1:cx + 2] = 0
+        T[0, c - 1, cx] = T[0, c + 1, cx] = 0
+        al[0, T[0] == 0] = 0.0
+    rows = [c] if neck_rows == 1 else [c, c + 1]
+    for y in rows:
+        for x in (7, 8):
+            T[0, y, x] = 1
+            lab[0, y, x] = 1
+            al[0, y, x] = 0.5
+    return T, lab, al
+
+
+@pytest.mark.parametrize("neck_rows", [1, 2])
+def test_neck_fill_split_matches_oracle(neck_rows):
+    """A filling neck splits a bubble; with a two-row neck the halves join again one step
+    later. Every step (split, merge, and the steps in between, which the labelling may
+    take through its fast path) must match the oracle exactly."""
+    wl = _mk(name="neck", dim=2, nx=16, ny=11, nz=1, gas_from=-1, nuclei=None, S0=1.2, tau=0.8,
+             sigma=1e-3)
+    orc = Oracle(wl)
+    gpu = _sim(wl)
+    T, lab, al = _dumbbell(neck_rows)
+    for o in (orc, gpu):
+        o.write("type", T)
+        o.write("label", lab)
+        o.write("mass", al)
+        o.write("alpha", al)
+        o.write("rho", np.ones_like(al))
+        o.set_bubble(1, 0.2, 20.0, 1 / 3)
+    orc.geometry()
+    gpu.refresh(relabel=False)
+    _say("neck rows", neck_rows)
+    for k in range(3):
+        orc.step(1)
+        gpu.step(1)
+        compare_states(gpu, orc, tol_pop=0.0, tol_cell=0.0)
+        compare_bubbles(gpu, orc, 0.0)
+    nb = len(orc.bubbles()["id"])
+    _say("  bubbles after 3 steps:", nb)
+    assert nb == (2 if neck_rows == 1 else 1)
