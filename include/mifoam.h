@@ -259,6 +259,51 @@ int mf_attach_mlp(mf_ctx *ctx, const mf_mlp *m);
 int mf_profile_enable(mf_ctx *ctx, int32_t on);
 int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launches);
 
+/* ---------------------------------------------------------------- tuning, batching
+ * Production forms beyond the paper: a tuner for the launch shape of the bulk lattice
+ * sweep, and the advance of many independent domains by one graph launch per two steps.
+ */
+
+/* Number of launch variants of the bulk lattice sweep (cells per thread x threads per
+ * work-group: 0 = 4 x 256, 1 = 2 x 256, 2 = 4 x 128, 3 = 2 x 128). */
+#define MF_SWEEP_VARIANTS 4
+
+/* Time every applicable variant of the bulk sweep on the context's current state (reps
+ * launches each; the kernel writes only the spare population buffer, so the state is not
+ * changed), select the fastest for later steps and return it in *best_variant (-1 when
+ * the domain uses the per-cell sweep: binary64, periodic axes, or rows that are not a
+ * multiple of the vector width). ms_per_variant (MF_SWEEP_VARIANTS floats, nullable)
+ * receives the mean time per launch, -1 for variants that do not apply. Synchronises the
+ * context stream. Every variant computes the same results. */
+int mf_tune(mf_ctx *ctx, int32_t reps, int32_t *best_variant, float *ms_per_variant);
+
+/* Select a bulk-sweep variant by hand (-1: the default). */
+int mf_set_sweep_variant(mf_ctx *ctx, int32_t variant);
+
+/* A batch of n distinct contexts (created, nucleated and, for the learned curvature,
+ * with a network attached) advanced together. The batch owns a stream of its own and one
+ * per domain; the contexts stay owned by the caller and must outlive the batch. Errors
+ * are reported through mf_last_error(NULL). */
+typedef struct mf_batch mf_batch;
+int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out);
+
+/* Tune the bulk sweep once per distinct domain shape and storage form (reps launches per
+ * variant) and apply the choice to every domain of that shape; variants (n ints,
+ * nullable) receives each domain's variant. */
+int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants);
+
+/* Advance every domain by nsteps. Pairs of steps run as one launch of a graph that holds
+ * two steps of all domains (each domain's kernels on its own branch, so independent
+ * domains run side by side); the graph is captured on first use and again after any
+ * state change made outside the time step (nucleation, field writes, refresh, network
+ * attachment, tuning) or after an odd step count. Results are identical to mf_step on
+ * each context. Work already queued on the contexts' streams runs first, and later work
+ * queued there waits for the batch. Profiling must be off. */
+int mf_batch_step(mf_batch *b, int32_t nsteps);
+
+/* Wait for the batch stream and free the batch (not the contexts). */
+int mf_batch_destroy(mf_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,13 +33,15 @@ struct OpsTable {
   void (*build_lists)(Ctx &, hipStream_t);
   void (*read_field)(Ctx &, hipStream_t, int, double *);
   void (*write_field)(Ctx &, hipStream_t, int, const double *);
+  bool (*sweep_bulk)(Ctx &, hipStream_t, int);
 };
 
 template <int D, int P>
 OpsTable make_ops() {
   return OpsTable{&Ops<D, P>::sweep,    &Ops<D, P>::convert,     &Ops<D, P>::label,
                   &Ops<D, P>::geometry, &Ops<D, P>::init_box,    &Ops<D, P>::nucleate,
-                  &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field};
+                  &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field,
+                  &Ops<D, P>::sweep_bulk};
 }
 
 OpsTable ops_for(int dim, int prec) {
@@ -349,6 +351,7 @@ int mf_destroy(mf_ctx *c) {
 
 int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii, const double *p0) {
   if (!c) return MF_EINVAL;
+  c->epoch++;
   c->sword_dirty = true;
   if (c->nucleated || c->stepped) { c->err = "mf_nucleate is valid once, before mf_step"; return MF_ESTATE; }
   if (n < 0 || (n > 0 && (!centers || !radii || !p0))) { c->err = "bad nucleus arrays"; return MF_EINVAL; }
@@ -384,6 +387,23 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
   return device_status(c);
 }
 
+// one time step, enqueued on the context stream (host work: launches only, so that it
+// can be captured into a graph); ev: five profiling events or NULL
+static void step_once(mf_ctx *c, hipEvent_t *ev) {
+  if (ev) (void)hipEventRecord(ev[0], c->stream);
+  reset_counters(c);
+  c->ops.build_lists(*c, c->stream);
+  if (ev) (void)hipEventRecord(ev[1], c->stream);
+  c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr);
+  if (ev) (void)hipEventRecord(ev[3], c->stream);
+  c->cur ^= 1;
+  c->ops.convert(*c, c->stream);
+  c->ops.label(*c, c->stream, 1);
+  c->ops.geometry(*c, c->stream);
+  if (ev) (void)hipEventRecord(ev[4], c->stream);
+  c->step++;
+}
+
 int mf_step(mf_ctx *c, int32_t nsteps) {
   if (!c) return MF_EINVAL;
   if (nsteps < 0) { c->err = "nsteps < 0"; return MF_EINVAL; }
@@ -397,22 +417,54 @@ int mf_step(mf_ctx *c, int32_t nsteps) {
       }
       ev = &c->prof_ev.ev[c->prof_ev.used];
       c->prof_ev.used += 5;
-      (void)hipEventRecord(ev[0], c->stream);
     }
-    reset_counters(c);
-    c->ops.build_lists(*c, c->stream);
-    if (ev) (void)hipEventRecord(ev[1], c->stream);
-    c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr);
-    if (ev) (void)hipEventRecord(ev[3], c->stream);
-    c->cur ^= 1;
-    c->ops.convert(*c, c->stream);
-    c->ops.label(*c, c->stream, 1);
-    c->ops.geometry(*c, c->stream);
-    if (ev) (void)hipEventRecord(ev[4], c->stream);
-    c->step++;
+    step_once(c, ev);
   }
   c->stepped = c->stepped || nsteps > 0;
   HIPCHK(c, hipGetLastError());
+  return MF_OK;
+}
+
+int mf_tune(mf_ctx *c, int32_t reps, int32_t *best, float *ms) {
+  if (!c || !best || reps < 1) return MF_EINVAL;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int bv = -1;
+  float bt = 0.0f;
+  for (int v = 0; v < kNumSweepVariants; ++v) {
+    float t = -1.0f;
+    // the bulk kernel writes only the other population buffer: timing it changes no state
+    if (c->ops.sweep_bulk(*c, c->stream, v)) {
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps; ++r) c->ops.sweep_bulk(*c, c->stream, v);
+      (void)hipEventRecord(e1, c->stream);
+      hipError_t e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(c, e);
+      }
+      t /= (float)reps;
+      if (bv < 0 || t < bt) { bv = v; bt = t; }
+    }
+    if (ms) ms[v] = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(c, hipGetLastError());
+  c->sweep_variant = bv;  // -1 when no variant applies (per-cell sweep)
+  c->epoch++;
+  *best = bv;
+  return MF_OK;
+}
+
+int mf_set_sweep_variant(mf_ctx *c, int32_t v) {
+  if (!c) return MF_EINVAL;
+  if (v < -1 || v >= kNumSweepVariants) { c->err = "unknown sweep variant"; return MF_EINVAL; }
+  c->sweep_variant = v;
+  c->epoch++;
   return MF_OK;
 }
 
@@ -454,6 +506,7 @@ int mf_read_field(mf_ctx *c, int32_t field, void *dst, size_t dst_bytes, int32_t
 
 int mf_write_field(mf_ctx *c, int32_t field, const void *src, size_t src_bytes) {
   if (!c || !src) return MF_EINVAL;
+  c->epoch++;
   c->sword_dirty = true;
   if (c->stepped) { c->err = "mf_write_field is valid before the first mf_step"; return MF_ESTATE; }
   const size_t need = field_bytes(c, field);
@@ -508,6 +561,7 @@ int mf_set_bubble(mf_ctx *c, int32_t id, double gas_mass, double volume, double 
 
 int mf_refresh(mf_ctx *c, int32_t relabel) {
   if (!c) return MF_EINVAL;
+  c->epoch++;
   c->sword_dirty = true;
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
@@ -569,6 +623,7 @@ int mf_totals_get(mf_ctx *c, mf_totals *out) {
 
 int mf_attach_mlp(mf_ctx *c, const mf_mlp *m) {
   if (!c || !m) return MF_EINVAL;
+  c->epoch++;
   if (c->kp.curvature != MF_CURV_MLP) { c->err = "the context was created for the plain curvature"; return MF_ESTATE; }
   // weights (bfloat16), biases (binary32) and the canonical-slot table, 256-byte aligned
   const size_t wbytes = (2 * (128 * 64 + 64 * 64 + 64) + 255) & ~(size_t)255;
@@ -617,6 +672,190 @@ int mf_profile_get(mf_ctx *c, int32_t group, double *ms_total, int64_t *launches
   }
   *ms_total = tot;
   *launches = nl;
+  return MF_OK;
+}
+
+
+// ---------------------------------------------------------------- batched domains
+struct mf_batch {
+  std::vector<mf_ctx *> ctx;
+  hipStream_t sb = nullptr;             // the batch stream (graph launches)
+  std::vector<hipStream_t> ss;          // one stream per domain inside the graph
+  std::vector<hipEvent_t> ev_in, ev_join;
+  hipEvent_t ev_fork = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> epoch;          // context epochs and buffer parities at capture
+  std::vector<int> cur;
+};
+
+static void batch_drop_graph(mf_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+static int batch_fail(const char *msg, hipError_t e) {
+  g_thread_err = std::string(msg) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+  return e != hipSuccess ? MF_EHIP : MF_ESTATE;
+}
+
+int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out) {
+  if (n < 1 || !ctxs || !out) return MF_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return MF_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) { g_thread_err = "a context appears twice in the batch"; return MF_EINVAL; }
+  }
+  mf_batch *b = new mf_batch;
+  b->ctx.assign(ctxs, ctxs + n);
+  hipError_t e = hipStreamCreateWithFlags(&b->sb, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  b->ss.assign(n, nullptr);
+  b->ev_in.assign(n, nullptr);
+  b->ev_join.assign(n, nullptr);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&b->ss[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    mf_batch_destroy(b);
+    return batch_fail("creating the batch streams failed", e);
+  }
+  *out = b;
+  return MF_OK;
+}
+
+int mf_batch_destroy(mf_batch *b) {
+  if (!b) return MF_EINVAL;
+  if (b->sb) (void)hipStreamSynchronize(b->sb);
+  batch_drop_graph(b);
+  for (size_t i = 0; i < b->ss.size(); ++i) {
+    if (b->ss[i]) (void)hipStreamDestroy(b->ss[i]);
+    if (b->ev_in[i]) (void)hipEventDestroy(b->ev_in[i]);
+    if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->sb) (void)hipStreamDestroy(b->sb);
+  delete b;
+  return MF_OK;
+}
+
+// two time steps of every domain as one graph: each domain's kernels on its own stream,
+// forked from and joined back into the batch stream
+static hipError_t batch_capture(mf_batch *b) {
+  for (mf_ctx *c : b->ctx)
+    if (c->sword_dirty) c->ops.geometry(*c, b->sb);  // idempotent; rebuilds the stencil words
+  hipError_t e = hipStreamBeginCapture(b->sb, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  (void)hipEventRecord(b->ev_fork, b->sb);
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    mf_ctx *c = b->ctx[i];
+    (void)hipStreamWaitEvent(b->ss[i], b->ev_fork, 0);
+    hipStream_t own = c->stream;
+    c->stream = b->ss[i];
+    step_once(c, nullptr);
+    step_once(c, nullptr);
+    c->stream = own;
+    c->step -= 2;  // counted when the graph runs
+    (void)hipEventRecord(b->ev_join[i], b->ss[i]);
+    (void)hipStreamWaitEvent(b->sb, b->ev_join[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->sb, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  b->graph = g;
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    batch_drop_graph(b);
+    return e;
+  }
+  b->epoch.resize(b->ctx.size());
+  b->cur.resize(b->ctx.size());
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    b->epoch[i] = b->ctx[i]->epoch;
+    b->cur[i] = b->ctx[i]->cur;
+  }
+  return hipSuccess;
+}
+
+int mf_batch_step(mf_batch *b, int32_t nsteps) {
+  if (!b || nsteps < 0) return MF_EINVAL;
+  for (mf_ctx *c : b->ctx) {
+    if (c->kp.curvature == MF_CURV_MLP && !c->d.mlp_w) return batch_fail("a domain uses the learned curvature without a network", hipSuccess);
+    if (c->prof) return batch_fail("profiling is not available in batched steps", hipSuccess);
+  }
+  // a graph captured before a state change made outside the time step is rebuilt
+  bool stale = b->exec == nullptr;
+  for (size_t i = 0; i < b->ctx.size() && !stale; ++i)
+    stale = b->epoch[i] != b->ctx[i]->epoch || b->cur[i] != b->ctx[i]->cur;
+  if (stale && b->exec) batch_drop_graph(b);
+  // the batch waits for the work already queued on the domains' own streams
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    (void)hipEventRecord(b->ev_in[i], b->ctx[i]->stream);
+    (void)hipStreamWaitEvent(b->sb, b->ev_in[i], 0);
+  }
+  const int pairs = nsteps / 2;
+  if (pairs > 0) {
+    if (!b->exec) {
+      const hipError_t e = batch_capture(b);
+      if (e != hipSuccess) return batch_fail("capturing the batched step failed", e);
+    }
+    for (int k = 0; k < pairs; ++k) {
+      const hipError_t e = hipGraphLaunch(b->exec, b->sb);
+      if (e != hipSuccess) return batch_fail("launching the batched step failed", e);
+    }
+    for (mf_ctx *c : b->ctx) c->step += 2 * pairs;
+  }
+  if (nsteps & 1) {
+    // an odd step runs outside the graph (and flips the buffer parity the graph expects)
+    for (mf_ctx *c : b->ctx) {
+      hipStream_t own = c->stream;
+      c->stream = b->sb;
+      step_once(c, nullptr);
+      c->stream = own;
+    }
+  }
+  for (mf_ctx *c : b->ctx) c->stepped = c->stepped || nsteps > 0;
+  // the domains' own streams wait for the batch
+  (void)hipEventRecord(b->ev_out, b->sb);
+  for (mf_ctx *c : b->ctx) (void)hipStreamWaitEvent(c->stream, b->ev_out, 0);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return batch_fail("a batched launch failed", e);
+  return MF_OK;
+}
+
+int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants) {
+  if (!b || reps < 1) return MF_EINVAL;
+  // one tuning run per distinct domain shape and storage form
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    mf_ctx *c = b->ctx[i];
+    int v = -2;
+    for (size_t j = 0; j < i; ++j) {
+      const mf_ctx *o = b->ctx[j];
+      if (o->kp.dim == c->kp.dim && o->kp.nx == c->kp.nx && o->kp.ny == c->kp.ny && o->kp.nz == c->kp.nz &&
+          o->P.precision == c->P.precision && o->kp.rheology == c->kp.rheology) {
+        v = o->sweep_variant;
+        break;
+      }
+    }
+    if (v == -2) {
+      int32_t best = -1;
+      const int rc = mf_tune(c, reps, &best, nullptr);
+      if (rc) return rc;
+    } else {
+      c->sweep_variant = v;
+      c->epoch++;
+    }
+    if (variants) variants[i] = c->sweep_variant;
+  }
   return MF_OK;
 }
 

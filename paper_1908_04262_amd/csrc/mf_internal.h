@@ -290,6 +290,9 @@ template <int D, int P> struct Ops {
   // the lattice sweep; with mid != NULL, the event is recorded between the bulk kernel
   // and the interface / near-wall kernel
   static void sweep(Ctx &c, hipStream_t s, hipEvent_t mid);
+  // one launch of the bulk sweep kernel in tuning variant v (see kSweepVariants); false
+  // when the variant does not apply to this domain (nothing launched)
+  static bool sweep_bulk(Ctx &c, hipStream_t s, int v);
   static void convert(Ctx &c, hipStream_t s);
   static void label(Ctx &c, hipStream_t s, int apply_flux);
   static void geometry(Ctx &c, hipStream_t s);
@@ -312,6 +315,8 @@ struct Ctx {
   bool nucleated = false;
   bool stepped = false;
   bool sword_dirty = true;  // stencil words to be rebuilt over the whole grid
+  int sweep_variant = -1;   // bulk-sweep variant chosen by the tuner (-1: default)
+  uint64_t epoch = 0;       // bumped by every state change made outside mf_step
   int64_t step = 0;
   std::string err;
   bool prof = false;
@@ -323,6 +328,11 @@ struct Ctx {
 
 // message of the last failed call on this thread that has no context
 extern thread_local std::string g_thread_err;
+
+// bulk-sweep variants the tuner chooses from: cells per thread x threads per work-group
+struct SweepVariant { int vw, bs; };
+constexpr SweepVariant kSweepVariants[] = {{4, 256}, {2, 256}, {4, 128}, {2, 128}};
+constexpr int kNumSweepVariants = 4;
 
 // work-groups of the list builder (one per chunk of cells)
 int list_blocks_of(const KP &kp);

@@ -483,8 +483,8 @@ __device__ __forceinline__ void load_all(const KP &p, const typename Prec<P>::SF
 // Bulk kernel: VW consecutive cells n0 .. n0+VW-1 per thread (the grid is linear in the
 // cell index). Requires closed axes (no periodic wrap) and nx % VW == 0, so that every
 // group starts on a VW boundary and the pulls of a fluid cell are plain index offsets.
-template <int D, int P, int VW>
-__global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
+template <int D, int P, int VW, int BS>
+__global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
 
   const int64_t N = p.N;
   // plain block order: every XCD streams through neighbouring parts of the grid
-  const int64_t n0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VW;
+  const int64_t n0 = ((int64_t)blockIdx.x * BS + threadIdx.x) * VW;
   const int lane = lane_id();
 
   // cell types of the group
@@ -582,23 +582,44 @@ __global__ __launch_bounds__(256) void k_sweep_vec(KP p, DA d, int cur) {
 }
 
 // cells per thread of the bulk kernel: 8-byte population accesses per lane
-template <int P> constexpr int vec_width() { return P == 1 ? 2 : 4; }
+// the variant used when none was chosen by the tuner: 8-byte population accesses per lane
+template <int P> constexpr int default_variant() { return P == 1 ? 1 : 0; }
 
-template <int D, int P>
-bool use_vector(const Ctx &c) {
-  constexpr int VW = vec_width<P>();
+template <int D, int P, int VW>
+bool vector_ok(const Ctx &c) {
   if (P == 0) return false;
   if (c.kp.per[0] || c.kp.per[1] || c.kp.per[2]) return false;
   return c.kp.nx % VW == 0 && c.kp.nx >= 2 * VW && c.kp.ny >= 3 && (D == 2 || c.kp.nz >= 3);
 }
 
+template <int D, int P, int VW, int BS>
+bool launch_bulk(Ctx &c, hipStream_t s) {
+  if (!vector_ok<D, P, VW>(c)) return false;
+  const int64_t nb = (c.kp.N + (int64_t)BS * VW - 1) / ((int64_t)BS * VW);
+  hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
+  return true;
+}
+
+template <int D, int P>
+bool Ops<D, P>::sweep_bulk(Ctx &c, hipStream_t s, int variant) {
+  if constexpr (P == 0) {
+    return false;
+  } else {
+    switch (variant) {
+      case 0: return launch_bulk<D, P, 4, 256>(c, s);
+      case 1: return launch_bulk<D, P, 2, 256>(c, s);
+      case 2: return launch_bulk<D, P, 4, 128>(c, s);
+      case 3: return launch_bulk<D, P, 2, 128>(c, s);
+      default: return false;
+    }
+  }
+}
+
 template <int D, int P>
 void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t mid) {
   if constexpr (P != 0) {
-    if (use_vector<D, P>(c)) {
-      constexpr int VW = vec_width<P>();
-      const int64_t nb = (c.kp.N + 256 * VW - 1) / (256 * VW);
-      hipLaunchKernelGGL((k_sweep_vec<D, P, VW>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
+    const int v = c.sweep_variant >= 0 ? c.sweep_variant : default_variant<P>();
+    if (sweep_bulk(c, s, v) || (v != default_variant<P>() && sweep_bulk(c, s, default_variant<P>()))) {
       if (mid) (void)hipEventRecord(mid, s);
       hipLaunchKernelGGL((k_sweep_special<D, P>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
       return;

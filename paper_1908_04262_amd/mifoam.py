@@ -60,7 +60,10 @@ EXPORTS = ["mf_abi_version", "mf_last_error", "mf_workspace_bytes", "mf_create",
            "mf_set_bubble", "mf_refresh", "mf_read_bubbles", "mf_totals_get",
            "mf_profile_enable", "mf_profile_get", "mf_mlp_param_count", "mf_mlp_create",
            "mf_mlp_destroy", "mf_mlp_train", "mf_mlp_get_params", "mf_mlp_set_params",
-           "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_grad", "mf_attach_mlp"]
+           "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_grad", "mf_attach_mlp", "mf_tune",
+           "mf_set_sweep_variant", "mf_batch_create", "mf_batch_tune", "mf_batch_step",
+           "mf_batch_destroy"]
+SWEEP_VARIANTS = 4
 
 _LIB = None
 
@@ -104,6 +107,12 @@ def load_library():
     lib.mf_mlp_eval.argtypes = [vp, vp, C.c_int64, vp, vp]
     lib.mf_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp]
     lib.mf_attach_mlp.argtypes = [vp, vp]
+    lib.mf_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), vp]
+    lib.mf_set_sweep_variant.argtypes = [vp, C.c_int32]
+    lib.mf_batch_create.argtypes = [C.c_int32, vp, C.POINTER(vp)]
+    lib.mf_batch_tune.argtypes = [vp, C.c_int32, vp]
+    lib.mf_batch_step.argtypes = [vp, C.c_int32]
+    lib.mf_batch_destroy.argtypes = [vp]
     _LIB = lib
     return lib
 
@@ -245,6 +254,17 @@ class Sim:
         self._check(self.lib.mf_profile_get(self.h, int(group), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def tune(self, reps=5):
+        """Time the bulk-sweep launch variants on the current state and keep the fastest;
+        returns (variant, ms per launch of each variant, -1 where not applicable)."""
+        best = C.c_int32()
+        ms = np.zeros(SWEEP_VARIANTS, np.float32)
+        self._check(self.lib.mf_tune(self.h, int(reps), C.byref(best), ms.ctypes.data))
+        return best.value, ms
+
+    def set_sweep_variant(self, v):
+        self._check(self.lib.mf_set_sweep_variant(self.h, int(v)))
+
     def totals(self):
         """Liquid mass (rho over liquid cells plus M over interface cells), dissolved and
         bubble gas, and the ledgers."""
@@ -257,6 +277,37 @@ class Sim:
         b = self.bubbles()
         led = self.ledgers()
         return dict(liquid=liquid, dissolved=dissolved, bubble_gas=b["m"].sum(), **led)
+
+
+class Batch:
+    """Several domains (Sim objects) advanced together, one graph launch per two steps."""
+
+    def __init__(self, sims):
+        self.lib = load_library()
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        h = C.c_void_p()
+        _check_plain(self.lib, self.lib.mf_batch_create(len(self.sims), arr, C.byref(h)))
+        self.h = h
+
+    def tune(self, reps=5):
+        v = np.zeros(len(self.sims), np.int32)
+        _check_plain(self.lib, self.lib.mf_batch_tune(self.h, int(reps), v.ctypes.data))
+        return v
+
+    def step(self, n=1):
+        _check_plain(self.lib, self.lib.mf_batch_step(self.h, int(n)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _stream_ptr():

@@ -7,6 +7,7 @@ output without sharing code.
 from .workloads import (  # noqa: F401
     SplitMix64,
     WORKLOADS,
+    batch_workloads,
     place_nuclei,
     workload,
     small_case,

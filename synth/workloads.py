@@ -226,3 +226,33 @@ def place_nuclei(wl: dict):
         jump = (2.0 if dim == 3 else 1.0) * wl["sigma"] / radii
         p0 = wl["p_atm"] + jump
     return centers, radii, p0
+
+
+def batch_workloads(seed: int = 5, n: int = 48, sizes=(64, 96, 128, 160), precision: str = "f16s_g16",
+                    curvature: str = "mlp"):
+    """The batched ensemble: n independent 3D foaming domains with edge lengths drawn
+    uniformly from `sizes`, Poisson(0.02 per 1000 cells) nuclei of radius U[2,4],
+    supersaturation U[1.2, 2.0] and relaxation time U[0.6, 1.0]; binary16 storage and
+    the learned curvature by default. Domain k places its nuclei with seed
+    SplitMix64(seed) -> k-th draw."""
+    rng = SplitMix64(seed)
+    out = []
+    for k in range(n):
+        edge = sizes[min(len(sizes) - 1, int(rng.uniform() * len(sizes)))]
+        mean = 0.02 * edge ** 3 / 1000.0
+        # Poisson by inversion of the cumulative distribution
+        u, kk, pk = rng.uniform(), 0, math.exp(-mean)
+        cdf = pk
+        while u > cdf and kk < 100000:
+            kk += 1
+            pk *= mean / kk
+            cdf += pk
+        S0 = rng.uniform_range(1.2, 2.0)
+        tau = rng.uniform_range(0.6, 1.0)
+        dseed = rng.next_u64() & 0x7FFFFFFF
+        out.append(_mk(
+            name=f"batch{k:02d}_{edge}", dim=3, nx=edge, ny=edge, nz=edge, precision=precision,
+            tau=tau, sigma=5e-4, S0=S0, k_pi=0.0, steps=3000, seed=dseed, curvature=curvature,
+            max_ids=4096, nuclei=dict(n=max(1, kk), r_min=2.0, r_max=4.0, min_sep=None),
+        ))
+    return out

@@ -1,0 +1,120 @@
+"""Batched domains and the sweep tuner.
+
+* several uneven domains advanced by one graph launch per two steps give the same
+  results, bit for bit, as stepping each domain on its own, over several launches with
+  reads (eager work) in between, odd step counts and a state change that forces a new
+  capture; a binary64 domain of the batch also matches the FP64 oracle exactly;
+* every launch variant of the bulk sweep gives the same results;
+* the tuner picks an applicable variant.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from synth import place_nuclei, small_case
+from tests.parity_util import compare_bubbles, compare_states
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["type", "label", "f", "g", "alpha", "mass", "kappa", "rho"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    return [
+        small_case("c2_small", precision="f16s_g16", nx=64),
+        small_case("c3_small", precision="fp32"),
+        small_case("c2_small", precision="bf16s", nx=72, ny=36, nz=40, seed=7),
+        small_case("c1_small", precision="fp64"),
+    ]
+
+
+def _make(wl):
+    from paper_1908_04262_amd import Sim
+    s = Sim(wl)
+    s.nucleate(*place_nuclei(wl))
+    return s
+
+
+def _same(a, b):
+    """Bit-identical states. Populations are compared on liquid and interface cells, the
+    only cells whose populations are ever read (gas and wall cells may hold whatever a
+    launch shape left there)."""
+    T = a.read("type")
+    fluid = (T == 1) | (T == 2)
+    for name in FIELDS:
+        x, y = a.read(name), b.read(name)
+        if name in ("f", "g"):
+            x, y = x[:, fluid], y[:, fluid]
+        assert np.array_equal(x, y), (a.wl["name"], name, np.abs(np.asarray(x, float) - y).max())
+    ba, bb = a.bubbles(), b.bubbles()
+    for k in ba:
+        assert np.array_equal(ba[k], bb[k]), (k,)
+    la, lb = a.ledgers(), b.ledgers()
+    assert la == lb
+
+
+def test_batch_matches_individual_steps():
+    from paper_1908_04262_amd import Batch
+    cases = _cases()
+    solo = [_make(w) for w in cases]
+    grouped = [_make(w) for w in cases]
+    orc = Oracle(cases[3])
+    orc.nucleate(*place_nuclei(cases[3]))
+    batch = Batch(grouped)
+    _say("batch: 4 steps, read, 3 steps, refresh, 2 steps")
+    batch.step(4)
+    for s in solo:
+        s.step(4)
+    _same(grouped[0], solo[0])
+    batch.step(3)
+    for s in solo:
+        s.step(3)
+    for g, s in zip(grouped, solo):
+        _same(g, s)
+    # a state change outside the time step: the graph is captured again
+    grouped[1].refresh(relabel=False)
+    solo[1].refresh(relabel=False)
+    batch.step(2)
+    for s in solo:
+        s.step(2)
+    for g, s in zip(grouped, solo):
+        _same(g, s)
+    orc.step(9)
+    compare_states(grouped[3], orc, tol_pop=1e-12, tol_cell=1e-10)
+    compare_bubbles(grouped[3], orc, 1e-12)
+    batch.close()
+
+
+def test_sweep_variants_identical():
+    from paper_1908_04262_amd import SWEEP_VARIANTS  # noqa: F401
+    wl = small_case("c3_small", precision="f16s_g16")
+    runs = []
+    for v in range(4):
+        s = _make(wl)
+        s.set_sweep_variant(v)
+        s.step(6)
+        runs.append(s)
+    for s in runs[1:]:
+        _same(s, runs[0])
+
+
+def test_tuner_picks_a_variant():
+    from paper_1908_04262_amd import Batch
+    sims = [_make(small_case("c2_small", precision="f16s_g16", nx=64)),
+            _make(small_case("c2_small", precision="f16s_g16", nx=64, seed=9)),
+            _make(small_case("c1_small", precision="fp64"))]
+    best, ms = sims[0].tune(3)
+    _say("tuner:", best, ms)
+    assert 0 <= best < 4 and ms[best] > 0
+    batch = Batch(sims)
+    v = batch.tune(3)
+    assert v[0] == v[1] and v[0] >= 0 and v[2] == -1
+    batch.step(2)
+    batch.close()
