@@ -10,8 +10,13 @@ whole-step MLUPS of run (ii); run (i) and the ratio are reported beside it. The 
 of run (ii) is trained on the GPU by the library before the timed region (2M generated
 stencils by default), and its training time and validation error are reported.
 
+A third measurement covers the batched ensemble (48 independent domains of 64^3 to 160^3,
+binary16 storage, learned curvature): MLUPS over all domains stepped one after another,
+and with the tuned bulk sweep and one graph launch per two steps of all domains.
+
 Prints one JSON line. Options: --gpus N (only 1), --steps K, --warmup W,
---workload NAME, --no-cpu-baseline, --mlp-train N, --mlp-epochs E.
+--workload NAME, --no-cpu-baseline, --mlp-train N, --mlp-epochs E, --no-ensemble,
+--ensemble-steps S.
 """
 import argparse
 import json
@@ -145,6 +150,57 @@ def run_one(wl, steps, warmup, log, net=None):
     return res
 
 
+def run_ensemble(net, steps, log):
+    """The batched ensemble (48 domains of 64^3..160^3, binary16 storage, learned
+    curvature): MLUPS over all domains when every domain is stepped in turn, and with the
+    tuned bulk sweep and one graph launch per two steps for all domains."""
+    import numpy as np
+    import torch
+
+    from paper_1908_04262_amd import Batch, Sim
+    from synth import batch_workloads, place_nuclei
+
+    wls = batch_workloads()
+    t0 = time.time()
+    sims = []
+    for wl in wls:
+        s = Sim(wl, device=0)
+        s.attach_mlp(net)
+        s.nucleate(*place_nuclei(wl))
+        sims.append(s)
+    cells = int(sum(np.prod(s.shape) for s in sims))
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    log(f"[ensemble] {len(sims)} domains, {cells / 1e6:.1f}M cells, set up in {time.time() - t0:.1f}s")
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for s in sims:
+            s.step(1)
+    torch.cuda.synchronize()
+    seq = cells * steps / (time.perf_counter() - t1) / 1e6
+    batch = Batch(sims)
+    variants = batch.tune(3)
+    batch.step(2)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    bat = cells * steps / (time.perf_counter() - t2) / 1e6
+    st = [s.ledgers()["status"] for s in sims]
+    log(f"[ensemble] sequential {seq:.0f} MLUPS, batched graph {bat:.0f} MLUPS, variants "
+        f"{dict(zip(*np.unique(variants, return_counts=True)))}")
+    batch.close()
+    for s in sims:
+        s.close()
+    del sims
+    torch.cuda.empty_cache()
+    return {"domains": len(wls), "cells": cells, "steps": steps,
+            "mlups_sequential": round(seq, 1), "mlups_batched": round(bat, 1),
+            "speedup": round(bat / seq, 3), "status_ok": all(x == 0 for x in st),
+            "tuned_variants": [int(v) for v in variants]}
+
+
 def cpu_baseline(log, budget_s=20.0):
     """The FP64 oracle on the host: the same recipe (power-law foam, supersaturation
     1.5, r ~ U[2,4]) on a 96^3 crop with the bubble density of the 384^3 case, timed over
@@ -184,6 +240,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mlp-train", type=int, default=1966080)
     ap.add_argument("--mlp-epochs", type=int, default=4)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -202,6 +260,7 @@ def main():
     net, train_info = train_net(a.mlp_train, a.mlp_epochs, log)
     r16 = run_one(dict(wl, precision="f16s_g16", curvature="mlp"), a.steps, a.warmup, log, net=net)
     r16f = run_one(dict(wl, precision="f16s", curvature="mlp"), a.steps, a.warmup, log, net=net)
+    ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
 
     def brief(r):
@@ -248,6 +307,7 @@ def main():
             "bytes_per_launch": r16["bulk_sweep_bytes"],
             "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
         },
+        "batched_ensemble": ens,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
