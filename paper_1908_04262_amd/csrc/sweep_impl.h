@@ -566,7 +566,9 @@ __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
     }
   }
 
-  // Whole-group stores for every lane holding a liquid cell. The other cells of the group
+  // Whole-group streaming (non-temporal) stores for every lane holding a liquid cell: the
+  // populations are read again only in the next step, after gigabytes of other traffic,
+  // so they are kept out of the caches. The other cells of the group
   // receive values that nothing reads: populations of wall and gas cells are never used
   // (bounce-back and the gas-side rebuild take the receiving cell's own values, and a
   // gas cell that turns interface is initialised afresh), and interface cells are
@@ -575,9 +577,9 @@ __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
   SG *gout = (SG *)d.g[cur ^ 1];
   if (anyliquid) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) *(VF *)(fout + (int64_t)i * p.Np + n0) = fv[i];
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(fv[i], (VF *)(fout + (int64_t)i * p.Np + n0));
 #pragma unroll
-    for (int i = 0; i < Qg; ++i) *(VG *)(gout + (int64_t)i * p.Np + n0) = gv[i];
+    for (int i = 0; i < Qg; ++i) __builtin_nontemporal_store(gv[i], (VG *)(gout + (int64_t)i * p.Np + n0));
   }
 }
 
