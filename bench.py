@@ -19,8 +19,10 @@ Prints one JSON line. Options: --gpus N (only 1), --steps K, --warmup W,
 --ensemble-steps S.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,6 +30,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# Counter-derived HBM traffic of the bulk sweep, valid only for the sources it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_vec_c3_foam_384_traffic.md")
+TRAFFIC_SOURCES = ("paper_1908_04262_amd/csrc/sweep_impl.h",
+                   "paper_1908_04262_amd/csrc/sweep_f16.hip",
+                   "paper_1908_04262_amd/csrc/sweep_f32.hip",
+                   "paper_1908_04262_amd/csrc/mf_internal.h",
+                   "paper_1908_04262_amd/build.py")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE summary
+    (already scaled by the copy-kernel calibration), or None when the summary is missing or
+    the sweep sources have changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    m = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    m = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": (\d+)", text)
+    return int(m.group(1)) if m else None
 METRIC = "MLUPS & %HBM peak, 384^3 foam; FP16-store+MLP-curvature vs FP32 plain"
 
 
@@ -298,12 +327,12 @@ def main():
         "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep_vec<3,4,4> (bulk sweep, binary16 f and g)",
+            "kernel": "k_sweep_vec<3,4,4,256> (bulk sweep, binary16 f and g)",
             "achieved": round(r16["bulk_sweep_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(r16["bulk_sweep_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic("k_sweep_vec<3,4,4,256>"),
             "bytes_per_launch": r16["bulk_sweep_bytes"],
             "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
         },
