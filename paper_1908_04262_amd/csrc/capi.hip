@@ -115,6 +115,8 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.alive_prev = cv.take<int32_t>(cap * 4);
   d.phi = cv.take<long long>(cap * 24);
   d.gam = cv.take<long long>(cap * 24);
+  d.phi0 = cv.take<long long>(NSPREAD * 24);
+  d.gam0 = cv.take<long long>(NSPREAD * 24);
   d.led = cv.take<long long>(9 * 8);
   d.ledtot = cv.take<__int128>(3 * 16);
   d.hkeys = cv.take<unsigned long long>((size_t)kp.H * 8);
@@ -625,22 +627,16 @@ int mf_attach_mlp(mf_ctx *c, const mf_mlp *m) {
   if (!c || !m) return MF_EINVAL;
   c->epoch++;
   if (c->kp.curvature != MF_CURV_MLP) { c->err = "the context was created for the plain curvature"; return MF_ESTATE; }
-  // weights (bfloat16), biases (binary32) and the canonical-slot table, 256-byte aligned
+  // weights (bfloat16) and biases (binary32), 256-byte aligned
   const size_t wbytes = (2 * (128 * 64 + 64 * 64 + 64) + 255) & ~(size_t)255;
   const size_t bbytes = (4 * (2 * 64 + 1) + 255) & ~(size_t)255;
-  const size_t tbytes = 48 * 128;
-  if (!c->mlp_buf) {
-    HIPCHK(c, hipMalloc(&c->mlp_buf, wbytes + bbytes + tbytes));
-    build_canon_table((uint8_t *)c->mlp_buf + wbytes + bbytes, c->stream);
-    HIPCHK(c, hipGetLastError());
-  }
+  if (!c->mlp_buf) HIPCHK(c, hipMalloc(&c->mlp_buf, wbytes + bbytes));
   uint16_t *w = (uint16_t *)c->mlp_buf;
   float *b = (float *)((char *)c->mlp_buf + wbytes);
   const int rc = mf_mlp_export_weights(m, w, b, c->stream);
   if (rc) { c->err = "copying the network weights failed"; return rc; }
   c->d.mlp_w = w;
   c->d.mlp_b = b;
-  c->d.mlp_canon = (const uint8_t *)c->mlp_buf + wbytes + bbytes;
   return MF_OK;
 }
 

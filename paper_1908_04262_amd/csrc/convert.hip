@@ -20,22 +20,23 @@ __global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
       n = d.ilist[k];
       act = (d.cflag[n] & CF_FILL) != 0;
     }
-    if (act) {
-      int x, y, z;
-      cell_xyz(p, n, x, y, z);
-      for (int i = 1; i < L::Q; ++i) {
-        const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+    if (!__ballot(act)) continue;  // wave-uniform
+    int x = 0, y = 0, z = 0;
+    if (act) cell_xyz(p, n, x, y, z);
+    for (int i = 1; i < L::Q; ++i) {
+      bool add = false;
+      int64_t yy = 0;
+      if (act) {
+        yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
         const int ty = d.type[yy] & TMASK;
         if (ty == TG) {
-          const uint32_t old = flag_or(d.cflag, yy, CF_NEWI);
-          if (!(old & CF_NEWI)) {
-            const int slot = atomicAdd(d.cnt + C_NI, 1);
-            d.nilist[slot] = (int32_t)yy;
-          }
+          add = !(flag_or(d.cflag, yy, CF_NEWI) & CF_NEWI);
         } else if (ty == TI) {
           if (d.cflag[yy] & CF_EMPTY) flag_clear(d.cflag, yy, CF_EMPTY);
         }
       }
+      const int slot = wave_append_slot(d.cnt + C_NI, add);
+      if (add) d.nilist[slot] = (int32_t)yy;
     }
   }
 }
@@ -46,24 +47,31 @@ template <int D>
 __global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
   using L = Lat<D>;
   LIST_LOOP(k, d.cnt + C_I) {
+    bool act = false;
+    int64_t n = 0;
     if (k < *(volatile int32_t *)(d.cnt + C_I)) {
-      const int64_t n = d.ilist[k];
-      if (d.cflag[n] & CF_EMPTY) {
-        int x, y, z;
-        cell_xyz(p, n, x, y, z);
-        const int32_t lab = d.label[n];
-        for (int i = 1; i < L::Q; ++i) {
-          const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-          if ((d.type[yy] & TMASK) == TL) {
-            atomicMin((unsigned int *)&d.label[yy], (unsigned int)lab);
-            const uint32_t old = flag_or(d.cflag, yy, CF_L2I);
-            if (!(old & CF_L2I)) {
-              const int slot = atomicAdd(d.cnt + C_L2I, 1);
-              d.l2ilist[slot] = (int32_t)yy;
-            }
-          }
+      n = d.ilist[k];
+      act = (d.cflag[n] & CF_EMPTY) != 0;
+    }
+    if (!__ballot(act)) continue;  // wave-uniform
+    int x = 0, y = 0, z = 0;
+    int32_t lab = 0;
+    if (act) {
+      cell_xyz(p, n, x, y, z);
+      lab = d.label[n];
+    }
+    for (int i = 1; i < L::Q; ++i) {
+      bool add = false;
+      int64_t yy = 0;
+      if (act) {
+        yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+        if ((d.type[yy] & TMASK) == TL) {
+          atomicMin((unsigned int *)&d.label[yy], (unsigned int)lab);
+          add = !(flag_or(d.cflag, yy, CF_L2I) & CF_L2I);
         }
       }
+      const int slot = wave_append_slot(d.cnt + C_L2I, add);
+      if (add) d.l2ilist[slot] = (int32_t)yy;
     }
   }
 }
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
       const int64_t n = k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI];
       d.type[n] = (d.type[n] & ~TMASK) | TI;
     }
-    wave_fx_add(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg));
+    wave_fx_add(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg), d.gam0);
   }
 }
 
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
       if (D == 3) ((R *)d.uz)[n] = ubz;
       ((R *)d.M)[n] = R(0);
     }
-    wave_fx_add(d.gam, act && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg));
+    wave_fx_add(d.gam, act && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg), d.gam0);
   }
 }
 

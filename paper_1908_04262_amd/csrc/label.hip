@@ -166,6 +166,20 @@ __global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
 }
 
 __device__ __forceinline__ __int128 join3(const long long *a) { return fx3_join(a[0], a[1], a[2]); }
+
+// the copies of the atmosphere's step accumulators (gas-side flux and conversion terms),
+// summed and cleared by the first wave of the block; lane 0 holds the total
+static_assert(NSPREAD == 64, "one copy per lane");
+__device__ __forceinline__ void take_atm_copies(DA &d, long long s[3]) {
+  const int lane = lane_id();
+  for (int c = 0; c < 3; ++c) {
+    s[c] = d.phi0[3 * lane + c] + d.gam0[3 * lane + c];
+    d.phi0[3 * lane + c] = 0;
+    d.gam0[3 * lane + c] = 0;
+  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int c = 0; c < 3; ++c) s[c] += __shfl_xor(s[c], off);
+}
 __device__ __forceinline__ void add3(long long *acc, const long long *v) {
   atomicAdd((unsigned long long *)&acc[0], (unsigned long long)v[0]);
   atomicAdd((unsigned long long *)&acc[1], (unsigned long long)v[1]);
@@ -244,6 +258,12 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
     d.bm[j] = 0.0;
     d.bV[j] = 0.0;
     d.bp[j] = 0.0;
+  }
+  if (tid < 64) {
+    long long sa[3];
+    take_atm_copies(d, sa);
+    if (tid == 0 && apply_flux)
+      for (int c = 0; c < 3; ++c) s_atm[c] += sa[c];
   }
   __syncthreads();
   // phase A: entries out of the pair hash; per-id sums; group non-atmosphere entries
@@ -461,10 +481,11 @@ __global__ __launch_bounds__(1024) void k_bubble_fast(KP p, DA d) {
   __shared__ long long s_atm[3];
   int jmax = *(volatile int32_t *)(d.cnt + C_NEXTID);
   if (jmax > p.cap) jmax = p.cap;
-  if (tid == 0) {
-    s_atm[0] = d.phi[0] + d.gam[0];
-    s_atm[1] = d.phi[1] + d.gam[1];
-    s_atm[2] = d.phi[2] + d.gam[2];
+  if (tid < 64) {
+    long long sa[3];
+    take_atm_copies(d, sa);
+    if (tid == 0)
+      for (int c = 0; c < 3; ++c) s_atm[c] = d.phi[c] + d.gam[c] + sa[c];
   }
   __syncthreads();
   for (int j = tid; j < jmax; j += nt) {

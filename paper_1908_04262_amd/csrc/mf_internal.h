@@ -155,6 +155,7 @@ struct DA {
   double *mprime;
   int32_t *alive_prev;
   long long *phi, *gam;       // per-id step accumulators [cap][3]
+  long long *phi0, *gam0;     // copies of the id-0 entries [NSPREAD][3]
   long long *led;             // per-step ledger accumulators [3][3]: lost, atm, collapsed
   __int128 *ledtot;           // persistent ledgers [3]
   // bubble-update scratch
@@ -175,7 +176,6 @@ struct DA {
   // learned curvature (NULL unless a network is attached)
   const uint16_t *mlp_w;      // bfloat16 W1 [128][64], W2 [64][64], W3 [64]
   const float *mlp_b;         // b1 [64], b2 [64], b3
-  const uint8_t *mlp_canon;   // canonical slot of each stencil element [48 symmetries][128]
   uint32_t *sword;            // stencil word of every cell (learned curvature only; see stencil_word)
 };
 
@@ -212,9 +212,16 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Id 0 (the atmosphere) takes a term from nearly every wave along the free surface; with
+// `spread0` its sums go to one of NSPREAD copies chosen by work-group, so that no address
+// takes thousands of atomics in one step (same-address atomics from different XCDs are
+// serialised far from the CUs). The reader adds the copies word by word, exactly.
+constexpr int NSPREAD = 64;
+
 // add a fixed-point value to acc[key*3 .. +2] for every lane with pred; lanes that share
 // a key are summed inside the wave first. Called by the whole wave.
-__device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, Fx3 v) {
+__device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, Fx3 v,
+                                            long long *spread0 = nullptr) {
   unsigned long long act = __ballot(pred);
   int lane = lane_id();
   while (act) {
@@ -229,9 +236,10 @@ __device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, 
       sh += __shfl_xor(sh, off);
     }
     if (lane == leader) {
-      atomicAdd((unsigned long long *)&acc[3 * k + 0], (unsigned long long)sl);
-      atomicAdd((unsigned long long *)&acc[3 * k + 1], (unsigned long long)sm);
-      atomicAdd((unsigned long long *)&acc[3 * k + 2], (unsigned long long)sh);
+      long long *dst = k == 0 && spread0 ? spread0 + 3 * (blockIdx.x & (NSPREAD - 1)) : acc + 3 * k;
+      atomicAdd((unsigned long long *)&dst[0], (unsigned long long)sl);
+      atomicAdd((unsigned long long *)&dst[1], (unsigned long long)sm);
+      atomicAdd((unsigned long long *)&dst[2], (unsigned long long)sh);
     }
     act &= ~mm;
     pred = pred && !mine;
@@ -239,6 +247,18 @@ __device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, 
 }
 
 __device__ __forceinline__ void raise_status(int32_t *st, int bits) { atomicOr(st, bits); }
+
+// a slot of a device-counted list for every lane with pred, with one atomic per wave;
+// called by the whole wave
+__device__ __forceinline__ int wave_append_slot(int32_t *counter, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if (!m) return -1;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader);
+  return base + (int)__popcll(m & ((1ull << lane_id()) - 1ull));
+}
 
 // byte flags through 32-bit atomics on the containing word
 __device__ __forceinline__ uint32_t flag_or(uint8_t *cflag, int64_t n, uint32_t bits) {
@@ -354,7 +374,6 @@ __device__ __forceinline__ uint32_t stencil_word(uint8_t tb, R alpha, int32_t la
 void launch_mlp_curv(Ctx &c, hipStream_t s);
 
 // table of canonical stencil slots for the 48 cube symmetries (48 x 128 bytes)
-void build_canon_table(uint8_t *lut, hipStream_t s);
 
 // initial gas content and pressure of the nucleus ids 1..nn (p0 in device memory)
 void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn);

@@ -411,7 +411,11 @@ static void backward(Net &n, hipStream_t s, const float *X, const float *Y, int 
 // and writes each value to its canonical position in the wave's LDS rows as bfloat16,
 // runs the two hidden layers on the matrix cores (16 cells x 64 units, weights held
 // transposed in LDS so that each B fragment is one 8-byte read), and the output layer
-// as a 16-lane shuffle reduction. A cell whose stencil meets a wall, leaves the domain
+// as a 16-lane shuffle reduction. The canonical position of an element is linear in its
+// offsets (dx, dy, dz): 62 + cx dx + cy dy + cz dz, where each coefficient is +-1, +-5 or
+// +-25 (the place value of the canonical axis the source axis goes to, negated when the
+// axis is flipped), so each cell carries three small integers instead of a table. The
+// gathers of the next 16 cells are issued before the products of the current ones. A cell whose stencil meets a wall, leaves the domain
 // or meets a gas / interface cell of another bubble, or whose network curvature exceeds
 // the trained range |kappa| <= 1/2, is left to the plain fit.
 struct MlpWaveLds {
@@ -422,7 +426,7 @@ struct MlpWaveLds {
     short h[16][NH + 4];
   };
   // the 64 cells of the wave's tile
-  int cell[64], x[64], y[64], z[64], lab[64], code[64];
+  int cell[64], x[64], y[64], z[64], lab[64], code[64], coef[64];
   float ac[64];
 };
 
@@ -441,37 +445,6 @@ __device__ __forceinline__ float gelu_fast(float z) {
   poly = fmaf(poly, t, 0.254829592f);
   const float y = 1.0f - poly * t * __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);
   return 0.5f * z * (1.0f + (z < 0.0f ? -y : y));
-}
-
-// index of a cube symmetry: 6 axis orders times 8 flip patterns
-__device__ __forceinline__ int sym_index(const int order[3], const int flip[3]) {
-  const int perm = order[0] == 0 ? (order[1] == 1 ? 0 : 1) : (order[0] == 1 ? (order[1] == 0 ? 2 : 3) : (order[1] == 0 ? 4 : 5));
-  return perm * 8 + flip[0] + 2 * flip[1] + 4 * flip[2];
-}
-
-// canonical slot of each natural stencil element for each of the 48 symmetries: the
-// canonical axis a reads source axis order[a], negated when that axis is flipped
-__global__ void k_canon_table(uint8_t *lut) {
-  static constexpr int ord[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 48 * NPD; i += gridDim.x * blockDim.x) {
-    const int k = i / NPD, j = i % NPD;
-    uint8_t v = 0;
-    if (j < NF) {
-      const int flip[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
-      const int dsrc[3] = {j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2};
-      int e[3];
-      for (int a = 0; a < 3; ++a) {
-        const int o = ord[k >> 3][a];
-        e[a] = flip[o] ? -dsrc[o] : dsrc[o];
-      }
-      v = (uint8_t)((e[0] + 2) + 5 * (e[1] + 2) + 25 * (e[2] + 2));
-    }
-    lut[i] = v;
-  }
-}
-
-void build_canon_table(uint8_t *lut, hipStream_t s) {
-  hipLaunchKernelGGL(k_canon_table, dim3(24), dim3(256), 0, s, lut);
 }
 
 // fill fraction a stencil reads at a cell of type t (walls read the centre value)
@@ -494,7 +467,6 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint16_t *W = d.mlp_w;  // bf16: W1 [128][64], W2 [64][64], W3 [64]
   const float *bias = d.mlp_b;  // b1 [64], b2 [64], b3
-  const uint8_t *lut = d.mlp_canon;
   for (int i = tid; i < NPD * NH; i += 256) sW1[i % NH][i / NH] = (short)W[i];
   for (int i = tid; i < NH * NH; i += 256) sW2[i % NH][i / NH] = (short)W[NPD * NH + i];
   if (tid < NH) {
@@ -514,10 +486,40 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
   const int64_t nxy = (int64_t)p.nx * p.ny;
   const bool periodic = p.per[0] || p.per[1] || p.per[2];
   const int r = lane & 15, kq = (lane >> 4) * 4;
-  // the lane's two stencil elements j = lane and lane + 64 as index offsets
-  const int64_t off0 = (int64_t)(lane % 5 - 2) + (int64_t)p.nx * ((lane / 5) % 5 - 2) + nxy * (lane / 25 - 2);
+  // the lane's two stencil elements j = lane and lane + 64: offsets and index offsets
   const int j1 = lane + 64;
-  const int64_t off1 = (int64_t)(j1 % 5 - 2) + (int64_t)p.nx * ((j1 / 5) % 5 - 2) + nxy * (j1 / 25 - 2);
+  const int dx0 = lane % 5 - 2, dy0 = (lane / 5) % 5 - 2, dz0 = lane / 25 - 2;
+  const int dx1 = j1 % 5 - 2, dy1 = (j1 / 5) % 5 - 2, dz1 = j1 / 25 - 2;
+  const int64_t off0 = (int64_t)dx0 + (int64_t)p.nx * dy0 + nxy * dz0;
+  const int64_t off1 = (int64_t)dx1 + (int64_t)p.nx * dy1 + nxy * dz1;
+  // stencil words of cells sb .. sb+15: slot m of a lane is element lane + 64 (m & 1) of
+  // cell sb + (m >> 1); all 32 loads are issued before any is used
+  uint32_t wd[32];
+  auto gather = [&](int sb) {
+    if (!periodic) {
+      // without wrap every load is issued; a slot that reads nothing loads the cell's own
+      // word (or word 0) and is replaced by the outside marker
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int c = sb + (m >> 1), h = m & 1;
+        const int cc = uniform(M.cell[c]);
+        const bool ok = cc >= 0 && !(uniform(M.code[c]) & 64) && (h == 0 || j1 < NF);
+        const int64_t yy = ok ? (int64_t)cc + (h ? off1 : off0) : (cc >= 0 ? (int64_t)cc : 0);
+        const uint32_t w = d.sword[yy];
+        wd[m] = ok ? w : 0xFFFF0000u;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int c = sb + (m >> 1), h = m & 1;
+        const int cc = uniform(M.cell[c]);
+        int64_t yy = -1;
+        if (cc >= 0 && !(uniform(M.code[c]) & 64) && (h == 0 || j1 < NF))
+          yy = nb_index_or_none(p, M.x[c], M.y[c], M.z[c], h ? dx1 : dx0, h ? dy1 : dy0, h ? dz1 : dz0);
+        wd[m] = yy >= 0 ? d.sword[yy] : 0xFFFF0000u;
+      }
+    }
+  };
   for (int64_t t0 = ((int64_t)blockIdx.x * 4 + wave) * 64; t0 < total; t0 += (int64_t)gridDim.x * 4 * 64) {
     // set-up, one cell per lane: the cell and its six axis neighbours are loaded
     // together once the list entry is known
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       const int64_t k = t0 + lane;
       int cell = -1;
       if (k < total) cell = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-      int cx = 0, cy = 0, cz = 0, code = 0, lab = 0;
+      int cx = 0, cy = 0, cz = 0, code = 0, lab = 0, coef = 0;
       float ac = 0.0f;
       if (cell >= 0) {
         cell_xyz(p, cell, cx, cy, cz);
@@ -552,7 +554,10 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
           for (int q = 0; q < 6; ++q) v6[q] = stencil_value<R>(tn6[q], al6[q], ac);
           int order[3], flip[3];
           canon_map(0.5f * (v6[0] - v6[1]), 0.5f * (v6[2] - v6[3]), 0.5f * (v6[4] - v6[5]), order, flip);
-          code = sym_index(order, flip);
+          int cf[3];
+          const int place[3] = {1, 5, 25};
+          for (int a = 0; a < 3; ++a) cf[order[a]] = flip[order[a]] ? -place[a] : place[a];
+          coef = (cf[0] & 0xFF) | ((cf[1] & 0xFF) << 8) | ((cf[2] & 0xFF) << 16);
           // on a closed axis, a cell within two cells of the wall layer has a wall in
           // its stencil: left to the plain fit without a gather
           const int cxyz[3] = {cx, cy, cz}, dims[3] = {p.nx, p.ny, p.nz};
@@ -566,49 +571,34 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       M.z[lane] = cz;
       M.lab[lane] = lab;
       M.code[lane] = code;
+      M.coef[lane] = coef;
       M.ac[lane] = ac;
     }
     wave_lds_sync();
+    gather(0);
     for (int sb = 0; sb < 64; sb += 16) {
       if (t0 + sb >= total) break;  // wave-uniform
-      // gather: slot m of a lane is element j = lane + 64 (m & 1) of cell sb + (m >> 1),
-      // at the lane's fixed offset from the cell, one stencil word per element; the loads
-      // of sixteen slots are issued before any is used
+      // each gathered word to its canonical slot; a wall (or the outside of a closed
+      // axis), or gas / interface of another bubble, sends the cell to the plain fit
       unsigned badm = 0;
-#pragma unroll 1
-      for (int m0 = 0; m0 < 32; m0 += 16) {
-        uint32_t wd[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int m = m0 + u, c = sb + (m >> 1), h = m & 1;
-          const int cc = uniform(M.cell[c]);
-          const int cd = uniform(M.code[c]);
-          int64_t yy = -1;
-          if (cc >= 0 && !(cd & 64) && (h == 0 || lane < NF - 64)) {
-            if (periodic) {
-              const int j = lane + 64 * h;
-              yy = nb_index_or_none(p, M.x[c], M.y[c], M.z[c], j % 5 - 2, (j / 5) % 5 - 2, j / 25 - 2);
-            } else {
-              yy = (int64_t)cc + (h ? off1 : off0);
-            }
-          }
-          wd[u] = yy >= 0 ? d.sword[yy] : 0xFFFF0000u;
+      for (int m = 0; m < 32; ++m) {
+        const int c = sb + (m >> 1), h = m & 1, j = lane + 64 * h;
+        const int cc = uniform(M.cell[c]);
+        if (cc < 0 || j >= NF) {
+          M.a[m >> 1][j] = 0;
+          continue;
         }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int m = m0 + u, c = sb + (m >> 1), h = m & 1, j = lane + 64 * h;
-          const int cc = uniform(M.cell[c]);
-          if (cc < 0 || j >= NF) {
-            M.a[m >> 1][j] = 0;
-            continue;
-          }
-          const uint32_t code = wd[u] >> 16;
-          // a wall (or the outside of a closed axis), or gas / interface of another bubble
-          if (code == 0xFFFFu || (code != 0u && code != (uint32_t)(uniform(M.lab[c]) + 1))) badm |= 1u << (m >> 1);
-          const short bits = code == 0xFFFFu ? bf16_hw(uniform(M.ac[c])) : (short)(wd[u] & 0xFFFFu);
-          M.a[m >> 1][lut[(uniform(M.code[c]) & 63) * NPD + j]] = bits;
-        }
+        const uint32_t code = wd[m] >> 16;
+        if (code == 0xFFFFu || (code != 0u && code != (uint32_t)(uniform(M.lab[c]) + 1))) badm |= 1u << (m >> 1);
+        const short bits = code == 0xFFFFu ? bf16_hw(uniform(M.ac[c])) : (short)(wd[m] & 0xFFFFu);
+        const int cf = uniform(M.coef[c]);
+        const int slot = 62 + (int)(int8_t)cf * (h ? dx1 : dx0) + (int)(int8_t)(cf >> 8) * (h ? dy1 : dy0) +
+                         (int)(int8_t)(cf >> 16) * (h ? dz1 : dz0);
+        M.a[m >> 1][slot] = bits;
       }
+      // the next 16 cells' loads run under this sub-tile's products
+      if (sb + 16 < 64 && t0 + sb + 16 < total) gather(sb + 16);
       for (int o = 32; o > 0; o >>= 1) badm |= __shfl_xor(badm, o);
       wave_lds_sync();
       // first hidden layer
@@ -671,8 +661,9 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
 }
 
 void launch_mlp_curv(Ctx &c, hipStream_t s) {
-  // persistent work-groups (each stages the weights once); about four per CU
-  const unsigned nb = list_blocks(c) < 1024 ? list_blocks(c) : 1024;
+  // persistent work-groups (each stages the weights once): the LDS of a CU holds three,
+  // so three per CU of the 256 run in one round
+  const unsigned nb = list_blocks(c) < 768 ? list_blocks(c) : 768;
   if (c.kp.dim != 3) return;
   switch (c.P.precision) {
     case 0: hipLaunchKernelGGL(k_mlp_curv<0>, dim3(nb), dim3(256), 0, s, c.kp, c.d); break;
