@@ -117,6 +117,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.gam = cv.take<long long>(cap * 24);
   d.phi0 = cv.take<long long>(NSPREAD * 24);
   d.gam0 = cv.take<long long>(NSPREAD * 24);
+  d.tcand = cv.take<int32_t>((size_t)TCAND_CAP * 4);
   d.led = cv.take<long long>(9 * 8);
   d.ledtot = cv.take<__int128>(3 * 16);
   d.hkeys = cv.take<unsigned long long>((size_t)kp.H * 8);

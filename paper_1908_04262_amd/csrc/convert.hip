@@ -293,117 +293,112 @@ __global__ __launch_bounds__(256) void k_clear_conv_flags(DA d) {
 //  - A joining cell whose gas / interface neighbours all carry its own id merges nothing.
 //  - A leaving cell of the atmosphere (next to a gas / interface cell with id 0) changes
 //    nothing: every piece of the atmosphere keeps id 0, and no bubble touches it.
-//  - Another leaving cell x: let K be the leaving cells connected to x inside its 3^d block
-//    (none of them with a leaving lattice neighbour outside that block, else the test
-//    fails), and R the remaining gas / interface lattice neighbours of K. If R is not
-//    empty and connected inside the 5^d window around x without the leaving cells, every
-//    path through K has a detour, so nothing splits or disappears.
+//  - Another leaving cell x, in the window of 7^d cells centred on it: let K be the leaving
+//    cells connected to x inside the inner 5^d block (none of them with a leaving lattice
+//    neighbour outside that block, else the test fails), and R the remaining gas /
+//    interface lattice neighbours of K. If R is not empty and connected inside the window
+//    without the leaving cells, every path through K has a detour, so nothing splits or
+//    disappears.
 // When any cell fails, the flag is set and the full labelling runs; otherwise ids, merges
 // and splits stay as they were.
-struct Bits128 {
-  uint64_t w[2];
-  __device__ bool get(int q) const { return (w[q >> 6] >> (q & 63)) & 1ull; }
-  __device__ void set(int q) { w[q >> 6] |= 1ull << (q & 63); }
+//
+// The window is held one x-row per lane (W bits; lane = (dy + H) + W (dz + H)), so a step
+// of lattice dilation is two shifts along x and a few shuffles for the rows around.
+template <int D> struct RowWindow {
+  static constexpr int W = 7, H = W / 2;
+  static constexpr int NR = D == 3 ? W * W : W;  // rows in the window
+  static constexpr uint32_t XM = (1u << W) - 1;
+  static constexpr uint32_t XIN = XM & ~1u & ~(1u << (W - 1));  // the inner x range
+  int ry = 0, rz = 0;
+  bool row = false, in_row = false;
+  __device__ RowWindow() {
+    const int lane = lane_id();
+    row = lane < NR;
+    ry = lane % W - H;
+    rz = D == 3 ? lane / W - H : 0;
+    in_row = row && ry > -H && ry < H && (D == 2 || (rz > -H && rz < H));
+  }
+  // the row at (ry + dy, rz + dz), empty outside the window
+  __device__ uint32_t at(uint32_t v, int dy, int dz) const {
+    const int y = ry + dy, z = rz + dz;
+    const bool ok = row && y >= -H && y <= H && z >= -H && z <= H;
+    const int src = ok ? (y + H) + W * (z + H) : lane_id();
+    const uint32_t t = __shfl(v, src);
+    return ok ? t : 0u;
+  }
+  __device__ static uint32_t xs(uint32_t r) { return ((r << 1) | (r >> 1)) & XM; }
+  // one step of dilation along the lattice directions of D2Q9 / D3Q19
+  __device__ uint32_t dilate(uint32_t v) const {
+    uint32_t o = v | xs(v);
+    if (D == 2) {
+      const uint32_t a = at(v, -1, 0), b = at(v, 1, 0);
+      o |= a | b | xs(a) | xs(b);
+    } else {
+      const uint32_t a = at(v, -1, 0), b = at(v, 1, 0), c = at(v, 0, -1), e = at(v, 0, 1);
+      o |= a | b | c | e | xs(a) | xs(b) | xs(c) | xs(e);
+      o |= at(v, -1, -1) | at(v, 1, -1) | at(v, -1, 1) | at(v, 1, 1);
+    }
+    return row ? o : 0u;
+  }
+  // flood of `seed` inside `allowed` (wave-uniform loop)
+  __device__ uint32_t flood(uint32_t seed, uint32_t allowed) const {
+    uint32_t r = seed;
+    for (int it = 0; it < NR * W; ++it) {
+      const uint32_t n = (dilate(r) & allowed) | seed;
+      if (!__ballot(n != r)) break;
+      r = n;
+    }
+    return r;
+  }
+  // gas / interface cells (g) and leaving cells (f) of the lane's row around (x, y, z)
+  __device__ void load(const KP &p, const DA &d, int x, int y, int z, uint32_t &g, uint32_t &f) const {
+    g = f = 0;
+    if (!row) return;
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const int64_t yy = nb_index_or_none(p, x, y, z, b - H, ry, rz);
+      if (yy < 0) continue;
+      const int t = d.type[yy] & TMASK;
+      if (t == TG || t == TI) g |= 1u << b;
+      else if (d.cflag[yy] & CF_FILL) f |= 1u << b;
+    }
+  }
+  // true when the leaving cell at the centre may split or remove a component
+  __device__ bool changes(uint32_t g, uint32_t f) const {
+    const uint32_t inner = in_row ? XIN : 0u;
+    const uint32_t cen = (row && ry == 0 && rz == 0) ? 1u << H : 0u;
+    const uint32_t K = flood(cen, (f & inner) | cen);
+    const uint32_t DK = dilate(K);
+    if (__ballot((DK & f & ~inner) != 0)) return true;  // the cluster reaches past the block
+    const uint32_t R = DK & g;
+    const unsigned long long has = __ballot(R != 0);
+    if (!has) return true;  // nothing of the set remains next to the cluster
+    const int first = __ffsll((long long)has) - 1;
+    const uint32_t seed = lane_id() == first ? R & (~R + 1u) : 0u;
+    const uint32_t reach = flood(seed, g);
+    return __ballot((R & ~reach) != 0) != 0;
+  }
 };
 
-__device__ __forceinline__ Bits128 shift128(Bits128 v, int s) {
-  Bits128 o;
-  if (s > 0) {
-    o.w[0] = v.w[0] << s;
-    o.w[1] = (v.w[1] << s) | (v.w[0] >> (64 - s));
-  } else if (s < 0) {
-    const int t = -s;
-    o.w[0] = (v.w[0] >> t) | (v.w[1] << (64 - t));
-    o.w[1] = v.w[1] >> t;
-  } else {
-    o = v;
-  }
-  return o;
-}
-
-// One step of lattice dilation of a window mask, computed by the whole wave: lane i < Q-1
-// moves the set along direction i+1 (positions whose step leaves the window are dropped
-// by the lane's mask `valid`), and the lanes' results are OR-ed together.
-__device__ __forceinline__ Bits128 dilate(Bits128 v, Bits128 valid, int shift, bool active) {
-  Bits128 m = {{v.w[0] & valid.w[0], v.w[1] & valid.w[1]}};
-  Bits128 o = active ? shift128(m, shift) : Bits128{{0, 0}};
-  for (int off = 32; off > 0; off >>= 1) {
-    o.w[0] |= __shfl_xor(o.w[0], off);
-    o.w[1] |= __shfl_xor(o.w[1], off);
-  }
-  o.w[0] |= v.w[0];
-  o.w[1] |= v.w[1];
-  return o;
-}
-
-// flood of `seed` inside `allowed` (wave-uniform loop)
-__device__ __forceinline__ Bits128 flood(Bits128 seed, Bits128 allowed, Bits128 valid, int shift, bool active) {
-  Bits128 r = seed;
-  for (int it = 0; it < 16; ++it) {
-    Bits128 n = dilate(r, valid, shift, active);
-    n.w[0] &= allowed.w[0];
-    n.w[1] &= allowed.w[1];
-    n.w[0] |= seed.w[0];
-    n.w[1] |= seed.w[1];
-    if (n.w[0] == r.w[0] && n.w[1] == r.w[1]) break;
-    r = n;
-  }
-  return r;
-}
-
-// The window test of one leaving cell, by the whole wave, from the masks of gas /
-// interface cells (g) and leaving cells (f) of its 5^d window (position dx + 5 dy +
-// 25 dz, offsets -2..2); true when the cell may split or remove a component. K: the
-// leaving cells connected to the centre inside its 3^d block; R: the gas / interface
-// lattice neighbours of K.
-template <int D>
-__device__ bool window_changes(Bits128 g, Bits128 f) {
-  using L = Lat<D>;
-  constexpr int W = 5, NW = D == 3 ? 125 : 25, CEN = D == 3 ? 62 : 12;
-  const int lane = lane_id();
-  const bool active = lane < L::Q - 1;
-  const int i = active ? lane + 1 : 1;
-  const int shift = L::ex[i] + W * L::ey[i] + W * W * L::ez[i];
-  Bits128 valid = {{0, 0}}, inner = {{0, 0}};
-  for (int q = 0; q < NW; ++q) {
-    const int dx = q % W - 2, dy = (q / W) % W - 2, dz = D == 3 ? q / (W * W) - 2 : 0;
-    const int ax = dx + L::ex[i], ay = dy + L::ey[i], az = dz + L::ez[i];
-    if (ax >= -2 && ax <= 2 && ay >= -2 && ay <= 2 && az >= -2 && az <= 2) valid.w[q >> 6] |= 1ull << (q & 63);
-    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) inner.w[q >> 6] |= 1ull << (q & 63);
-  }
-  Bits128 cen = {{0, 0}};
-  cen.w[CEN >> 6] = 1ull << (CEN & 63);
-  Bits128 fin = {{f.w[0] & inner.w[0], f.w[1] & inner.w[1]}};
-  fin.w[CEN >> 6] |= 1ull << (CEN & 63);
-  const Bits128 K = flood(cen, fin, valid, shift, active);
-  const Bits128 DK = dilate(K, valid, shift, active);
-  // a leaving neighbour of K outside the block: the cluster may continue beyond the window
-  if ((DK.w[0] & f.w[0] & ~inner.w[0]) || (DK.w[1] & f.w[1] & ~inner.w[1])) return true;
-  const Bits128 R = {{DK.w[0] & g.w[0], DK.w[1] & g.w[1]}};
-  if (!R.w[0] && !R.w[1]) return true;
-  Bits128 seed = {{0, 0}};
-  if (R.w[0]) seed.w[0] = R.w[0] & (~R.w[0] + 1);
-  else seed.w[1] = R.w[1] & (~R.w[1] + 1);
-  const Bits128 reach = flood(seed, g, valid, shift, active);
-  return (R.w[0] & ~reach.w[0]) || (R.w[1] & ~reach.w[1]);
-}
-
+// cheap per-cell tests over the interface list: joining cells are decided here, filling
+// cells that need the window test are listed
 template <int D>
 __global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
   using L = Lat<D>;
-  constexpr int W = 5, NW = D == 3 ? 125 : 25;
-  __shared__ int s_cand[256];
-  __shared__ int s_nc;
-  if (threadIdx.x == 0) s_nc = 0;
-  __syncthreads();
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
   const int64_t total = (int64_t)nI + nL;
-  // a periodic axis shorter than the window would wrap it onto itself: full labelling
-  bool change = total > 0 && ((p.per[0] && p.nx < W) || (p.per[1] && p.ny < W) || (D == 3 && p.per[2] && p.nz < W));
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total && !change; k += (int64_t)gridDim.x * blockDim.x) {
-    if (k >= nI) {
-      const int64_t n = d.l2ilist[k - nI];
+  // a periodic axis shorter than the widest window would wrap it onto itself: full
+  // labelling
+  constexpr int WMAX = 7;
+  bool change = total > 0 && ((p.per[0] && p.nx < WMAX) || (p.per[1] && p.ny < WMAX) || (D == 3 && p.per[2] && p.nz < WMAX));
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
+       k += (int64_t)gridDim.x * blockDim.x) {
+    bool cand = false;
+    int64_t n = 0;
+    if (k >= total || change) {
+    } else if (k >= nI) {
+      n = d.l2ilist[k - nI];
       const int32_t lx = d.label[n];
       int x, y, z;
       cell_xyz(p, n, x, y, z);
@@ -413,53 +408,51 @@ __global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
         const int t = d.type[yy] & TMASK;
         if ((t == TG || t == TI) && d.label[yy] != lx) change = true;
       }
-      continue;
-    }
-    const int64_t n = d.ilist[k];
-    if (!(d.cflag[n] & CF_FILL)) continue;
-    int x, y, z;
-    cell_xyz(p, n, x, y, z);
-    // a leaving cell of the atmosphere (a gas / interface neighbour with id 0) changes no
-    // bubble: every piece of the atmosphere keeps id 0 and no bubble touches it
-    bool atm = false;
-    for (int i = 1; i < L::Q; ++i) {
-      const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-      if (yy < 0) continue;
-      const int t = d.type[yy] & TMASK;
-      if ((t == TG || t == TI) && d.label[yy] == 0) atm = true;
-    }
-    if (atm) continue;
-    const int c = atomicAdd(&s_nc, 1);  // LDS
-    if (c < 256) s_cand[c] = (int)n;
-    else change = true;
-  }
-  __syncthreads();
-  // window tests, one wave per candidate: the lanes load the window, lane 0 decides
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int nc = s_nc < 256 ? s_nc : 256;
-  for (int c = wave; c < nc; c += 4) {
-    const int64_t n = s_cand[c];
-    int x, y, z;
-    cell_xyz(p, n, x, y, z);
-    Bits128 g, f;
-    for (int h = 0; h < 2; ++h) {
-      const int q = lane + 64 * h;
-      bool gq = false, fq = false;
-      if (q < NW) {
-        const int dx = q % W - 2, dy = (q / W) % W - 2, dz = D == 3 ? q / (W * W) - 2 : 0;
-        const int64_t yy = nb_index_or_none(p, x, y, z, dx, dy, dz);
-        if (yy >= 0) {
+    } else {
+      n = d.ilist[k];
+      if (d.cflag[n] & CF_FILL) {
+        int x, y, z;
+        cell_xyz(p, n, x, y, z);
+        // a leaving cell of the atmosphere (a gas / interface neighbour with id 0) changes
+        // no bubble: every piece of the atmosphere keeps id 0 and no bubble touches it
+        bool atm = false;
+        for (int i = 1; i < L::Q; ++i) {
+          const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+          if (yy < 0) continue;
           const int t = d.type[yy] & TMASK;
-          gq = t == TG || t == TI;
-          fq = !gq && (d.cflag[yy] & CF_FILL);
+          if ((t == TG || t == TI) && d.label[yy] == 0) atm = true;
         }
+        cand = !atm;
       }
-      g.w[h] = __ballot(gq);
-      f.w[h] = __ballot(fq);
     }
-    if (window_changes<D>(g, f) && lane == 0) change = true;
+    const int slot = wave_append_slot(d.cnt + C_TCAND, cand);
+    if (cand) {
+      if (slot < TCAND_CAP) d.tcand[slot] = (int32_t)n;
+      else change = true;
+    }
   }
   if (__ballot(change) != 0 && lane_id() == 0) d.cnt[C_TOPO] = 1;
+}
+
+// the window tests of the listed filling cells, one wave per cell: the lanes load the
+// window, the whole wave runs the floods
+template <int D>
+__global__ __launch_bounds__(256) void k_topo_window(KP p, DA d) {
+  const int nc = min(*(volatile int32_t *)(d.cnt + C_TCAND), TCAND_CAP);
+  const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+  if (wave >= nc || *(volatile int32_t *)(d.cnt + C_TOPO)) return;  // wave-uniform
+  const RowWindow<D> w;
+  for (int c = wave; c < nc; c += nwaves) {
+    int x, y, z;
+    cell_xyz(p, d.tcand[c], x, y, z);
+    uint32_t g, f;
+    w.load(p, d, x, y, z, g, f);
+    if (w.changes(g, f)) {
+      if (lane_id() == 0) d.cnt[C_TOPO] = 1;
+      return;
+    }
+  }
 }
 
 template <int D, int P>
@@ -471,6 +464,7 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL((k_l2i_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_apply<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_topo_check<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_topo_window<D>), dim3(256), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_ni_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);

@@ -27,7 +27,9 @@ constexpr int ST_BADLABEL = 8;    // interface cell with an invalid bubble id
 
 // counters
 // C_TOPO: set when this step's conversions may have merged, split or removed a component
-enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_NEXTID, C_NCOUNT = 16 };
+enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_NEXTID, C_NCOUNT = 16 };
+// capacity of the list of filling cells whose neighbourhood the topology test examines
+constexpr int TCAND_CAP = 65536;
 
 // ------------------------------------------------------------------ lattices
 // D2Q9 / D3Q19 velocity sets and weights (Sec. 2); the ADE lattices D2Q5 / D3Q7 are
@@ -156,6 +158,7 @@ struct DA {
   int32_t *alive_prev;
   long long *phi, *gam;       // per-id step accumulators [cap][3]
   long long *phi0, *gam0;     // copies of the id-0 entries [NSPREAD][3]
+  int32_t *tcand;             // filling cells for the window topology test [TCAND_CAP]
   long long *led;             // per-step ledger accumulators [3][3]: lost, atm, collapsed
   __int128 *ledtot;           // persistent ledgers [3]
   // bubble-update scratch
