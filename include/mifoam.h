@@ -181,11 +181,13 @@ int mf_read_field(mf_ctx *ctx, int32_t field, void *dst, size_t dst_bytes, int32
  * field must keep walls on the outer layer of every closed axis (MF_EINVAL otherwise). */
 int mf_write_field(mf_ctx *ctx, int32_t field, const void *src, size_t src_bytes);
 
-/* Set one bubble-table entry (hand-built test states). */
+/* Set one bubble-table entry (hand-built test states). The gas side of the interface
+ * cells (rebuilt populations at the bubble pressure) follows before the next step. */
 int mf_set_bubble(mf_ctx *ctx, int32_t id, double gas_mass, double volume, double pressure, int32_t alive);
 
-/* Recompute the derived state of a hand-written state: interface lists, curvature and
- * disjoining pressure. relabel = 1 also runs bubble labelling with no gas flux. */
+/* Recompute the derived state of a hand-written state: interface lists, curvature,
+ * disjoining pressure and the gas side of the interface cells. relabel = 1 also runs
+ * bubble labelling with no gas flux. */
 int mf_refresh(mf_ctx *ctx, int32_t relabel);
 
 /* Live bubbles (atmosphere excluded) in ascending id; *n_out = number of live bubbles

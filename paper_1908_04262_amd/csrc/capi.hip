@@ -93,7 +93,8 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   for (int b = 0; b < 2; b++) d.g[b] = cv.take<void>(Qg * Np * sg);
   d.type = cv.take<uint8_t>(Np);
   d.cflag = cv.take<uint8_t>(Np);
-  void **rarr[] = {&d.M, &d.alpha, &d.rho, &d.ux, &d.uy, &d.uz, &d.kappa, &d.Pi, &d.exc, &d.mx, &d.my, &d.mz, &d.soff};
+  void **rarr[] = {&d.M,  &d.alpha, &d.rho, &d.ux, &d.uy,   &d.uz,  &d.kappa, &d.Pi,
+                   &d.exc, &d.mx,   &d.my,  &d.mz, &d.soff, &d.rgas, &d.pbub};
   for (void **a : rarr) *a = cv.take<void>(Np * rb);
   d.label = cv.take<int32_t>(Np * 4);
   d.parent = cv.take<int32_t>(Np * 4);
@@ -411,6 +412,7 @@ int mf_step(mf_ctx *c, int32_t nsteps) {
   if (!c) return MF_EINVAL;
   if (nsteps < 0) { c->err = "nsteps < 0"; return MF_EINVAL; }
   if (c->kp.curvature == MF_CURV_MLP && !c->d.mlp_w) { c->err = "learned curvature selected but no network attached"; return MF_ESTATE; }
+  if (nsteps > 0 && c->gas_dirty) c->ops.geometry(*c, c->stream);  // idempotent
   for (int k = 0; k < nsteps; k++) {
     hipEvent_t *ev = nullptr;
     if (c->prof) {
@@ -551,6 +553,9 @@ int mf_set_bubble(mf_ctx *c, int32_t id, double gas_mass, double volume, double 
   HIPCHK(c, hipMemcpyAsync(c->d.bV + id, &volume, 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d.bp + id, &pressure, 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d.balive + id, &al, 4, hipMemcpyHostToDevice, c->stream));
+  // the gas side of the interface cells follows the bubble pressures before the next step
+  c->gas_dirty = true;
+  c->epoch++;
   int32_t next = 0;
   HIPCHK(c, hipMemcpyAsync(&next, c->d.cnt + C_NEXTID, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -746,7 +751,7 @@ int mf_batch_destroy(mf_batch *b) {
 // forked from and joined back into the batch stream
 static hipError_t batch_capture(mf_batch *b) {
   for (mf_ctx *c : b->ctx)
-    if (c->sword_dirty) c->ops.geometry(*c, b->sb);  // idempotent; rebuilds the stencil words
+    if (c->sword_dirty || c->gas_dirty) c->ops.geometry(*c, b->sb);  // idempotent
   hipError_t e = hipStreamBeginCapture(b->sb, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   (void)hipEventRecord(b->ev_fork, b->sb);
@@ -816,6 +821,7 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
     for (mf_ctx *c : b->ctx) {
       hipStream_t own = c->stream;
       c->stream = b->sb;
+      if (c->gas_dirty) c->ops.geometry(*c, c->stream);
       step_once(c, nullptr);
       c->stream = own;
     }

@@ -408,6 +408,14 @@ __global__ __launch_bounds__(256) void k_disjoining(KP p, DA d) {
       }
     }
     ((R *)d.Pi)[n] = Pi;
+    // gas-side density and bubble pressure the next sweep rebuilds missing populations with
+    const int32_t lab = d.label[n];
+    double pb = p.p_atm;
+    if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
+    else raise_status(d.status, ST_BADLABEL);
+    const R kap = ((const R *)d.kappa)[n];
+    ((R *)d.rgas)[n] = R(3) * ((R(pb) - R(2) * R(p.sigma) * kap) - Pi);
+    ((R *)d.pbub)[n] = R(pb);
   }
 }
 
@@ -455,6 +463,7 @@ void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
   if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
   hipLaunchKernelGGL((k_curvature<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_disjoining<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  c.gas_dirty = false;
 }
 
 #define MF_INST(D, P) template void Ops<D, P>::geometry(Ctx &, hipStream_t);

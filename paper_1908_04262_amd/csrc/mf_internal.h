@@ -145,6 +145,9 @@ struct DA {
   void *f[2], *g[2];
   uint8_t *type, *cflag;
   void *M, *alpha, *rho, *ux, *uy, *uz, *kappa, *Pi, *exc, *mx, *my, *mz, *soff;
+  // gas side of each interface cell for the next sweep: density 3 (p_b - 2 sigma kappa - Pi)
+  // and bubble pressure p_b, set with the geometry
+  void *rgas, *pbub;
   int32_t *label, *parent;
   int32_t *ilist, *blist, *nilist, *l2ilist;
   int32_t *lcnt;              // per-block counts / offsets of the list builder [2][blocks]
@@ -338,6 +341,7 @@ struct Ctx {
   bool nucleated = false;
   bool stepped = false;
   bool sword_dirty = true;  // stencil words to be rebuilt over the whole grid
+  bool gas_dirty = false;   // bubble table changed since the gas side was last set
   int sweep_variant = -1;   // bulk-sweep variant chosen by the tuner (-1: default)
   uint64_t epoch = 0;       // bumped by every state change made outside mf_step
   int64_t step = 0;

@@ -234,19 +234,22 @@ __device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64
     if (i < Qg) gown[i] = GC::dec(gin[(int64_t)i * Np + n], p);
     tsrc[i] = d.type[src(i)] & TMASK;
   }
-  R rg = R(1), uox = R(0), uoy = R(0), uoz = R(0), uou = R(0), cH = R(0), dcH = R(0);
+  R rg = R(1), uox = R(0), uoy = R(0), uoz = R(0), uou = R(0), cH = R(0), dcH = R(0), ax = R(0), Mo = R(0);
+  R ay[Q];
   if (isI) {
-    double pb = p.p_atm;
-    if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
-    else raise_status(d.status, ST_BADLABEL);
-    const R kap = ((const R *)d.kappa)[n], pi = ((const R *)d.Pi)[n];
-    rg = R(3) * ((R(pb) - R(2) * R(p.sigma) * kap) - pi);
-    cH = R(p.kH) * R(pb);
+    // everything an interface cell reads is addressed by its index alone: the loads are
+    // issued together (fill fractions of all neighbours, used where they are interface)
+    rg = ((const R *)d.rgas)[n];
+    cH = R(p.kH) * ((const R *)d.pbub)[n];
     dcH = cH - R(p.c0);
     uox = ((const R *)d.ux)[n];
     uoy = ((const R *)d.uy)[n];
     uoz = D == 3 ? ((const R *)d.uz)[n] : R(0);
     uou = usq<D, R>(uox, uoy, uoz);
+    ax = ((const R *)d.alpha)[n];
+    Mo = ((const R *)d.M)[n];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) ay[i] = ((const R *)d.alpha)[dst(i)];
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -272,7 +275,6 @@ __device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64
   }
   if (isI) {
     // interface mass exchange with liquid and interface neighbours y = x + e_i
-    const R ax = ((const R *)d.alpha)[n];
     R dm = R(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -280,11 +282,10 @@ __device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64
       if (tn == TL) {
         dm = dm + (ft[opp(i)] - own[i]);
       } else if (tn == TI) {
-        const R ay = ((const R *)d.alpha)[dst(i)];
-        dm = dm + (R(0.5) * (ax + ay)) * (ft[opp(i)] - own[i]);
+        dm = dm + (R(0.5) * (ax + ay[i])) * (ft[opp(i)] - own[i]);
       }
     }
-    Ms = ((const R *)d.M)[n] + dm;
+    Ms = Mo + dm;
   }
 }
 
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
     int x = 0, y = 0, z = 0;
     if (k < *(volatile int32_t *)(d.cnt + C_I)) {
       n = d.ilist[k];
-      tb = d.type[n];
+      tb = TI;  // the near-wall bit only matters for liquid cells
       fluid = true;
       lab = d.label[n];
       cell_xyz(p, n, x, y, z);
