@@ -33,7 +33,10 @@ namespace mf {
 
 // Power-law relaxation time in binary32 (the same root as powerlaw_tau): Newton's
 // method on u = log2(tau - 1/2), whose iterates are those on ln(tau - 1/2) scaled by
-// 1/ln 2, with the hardware base-2 exponential and logarithm.
+// 1/ln 2, with the hardware base-2 exponential and logarithm. From the same start, three
+// iterations reach the root to binary32 precision over the whole clamped range (the
+// fourth of the binary64 form changes nothing at this precision); the derivative
+// 1 - m e / (e + 1/2) is used as (n e + 1/2) / (e + 1/2), one reciprocal per iteration.
 __device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float pn) {
   const float n = (float)p.pl_n;
   float tau;
@@ -45,12 +48,11 @@ __device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float
     const float m = 1.0f - n;
     float u = l3;
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < 3; ++it) {
       const float e = __builtin_amdgcn_exp2f(u);
-      const float r = __builtin_amdgcn_rcpf(e + 0.5f);
-      const float F = (u - m * __builtin_amdgcn_logf(e + 0.5f)) - la;
-      const float dF = 1.0f - (m * e) * r;
-      u = u - F * __builtin_amdgcn_rcpf(dF);
+      const float eh = e + 0.5f;
+      const float F = (u - m * __builtin_amdgcn_logf(eh)) - la;
+      u = u - (F * eh) * __builtin_amdgcn_rcpf(n * e + 0.5f);
     }
     tau = 0.5f + __builtin_amdgcn_exp2f(u);
   }
@@ -59,16 +61,33 @@ __device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float
   return tau;
 }
 
-// BGK collision of one cell on offsets in binary32 (instances 1-4): one reciprocal of
-// the density, equilibria built in pairs of opposite directions (even part
-// w (drho + rho (4.5 (e.u)^2 - 1.5 u.u)), odd part 3 w rho e.u).
+// BGK collision of one cell on offsets in binary32 (instances 1-4). Directions come in
+// opposite pairs (2k+1, 2k+2): the moments are taken from the pair sums s and
+// differences d (density from s, momentum from d, the momentum flux from s, whose
+// products e_a e_b are the same for both members), the density is inverted once, and the
+// equilibria are built per pair (even part w (drho + rho (4.5 (e.u)^2 - 1.5 u.u)), odd
+// part 3 w rho e.u).
+// c0 and q are the reference concentration and the source in the units gt is held in.
 template <int D>
 __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft, float *gt, float &rho, float &ux,
-                                            float &uy, float &uz) {
+                                            float &uy, float &uz, float c0, float q) {
   using L = Lat<D>;
-  constexpr int Q = L::Q, Qg = L::Qg;
-  float s, jx, jy, jz;
-  sums<D, float>(ft, s, jx, jy, jz);
+  constexpr int Q = L::Q, Qg = L::Qg, NP = (Q - 1) / 2;
+  float sp[NP], dp[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    sp[k] = ft[2 * k + 1] + ft[2 * k + 2];
+    dp[k] = ft[2 * k + 1] - ft[2 * k + 2];
+  }
+  float s = ft[0], jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int i = 2 * k + 1;
+    s = s + sp[k];
+    if (L::ex[i]) jx = L::ex[i] > 0 ? jx + dp[k] : jx - dp[k];
+    if (L::ey[i]) jy = L::ey[i] > 0 ? jy + dp[k] : jy - dp[k];
+    if (D == 3 && L::ez[i]) jz = L::ez[i] > 0 ? jz + dp[k] : jz - dp[k];
+  }
   const float drho = s;
   rho = 1.0f + s;
   if (!(rho > 0.0f)) raise_status(d.status, ST_NONFINITE);
@@ -83,15 +102,16 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
     // rho c_s^2 I + rho u u taken relative to the rest state (I/3)
     float pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const float dd = ft[i];
+    for (int k = 0; k < NP; ++k) {
+      const int i = 2 * k + 1;
       const int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
-      if (ex) pxx = pxx + dd;
-      if (ey) pyy = pyy + dd;
-      if (D == 3 && ez) pzz = pzz + dd;
-      if (ex && ey) pxy = pxy + float(ex * ey) * dd;
-      if (D == 3 && ex && ez) pxz = pxz + float(ex * ez) * dd;
-      if (D == 3 && ey && ez) pyz = pyz + float(ey * ez) * dd;
+      const float v = sp[k];
+      if (ex) pxx = pxx + v;
+      if (ey) pyy = pyy + v;
+      if (D == 3 && ez) pzz = pzz + v;
+      if (ex && ey) pxy = ex * ey > 0 ? pxy + v : pxy - v;
+      if (D == 3 && ex && ez) pxz = ex * ez > 0 ? pxz + v : pxz - v;
+      if (D == 3 && ey && ez) pyz = ey * ez > 0 ? pyz + v : pyz - v;
     }
     const float d3 = drho * (1.0f / 3.0f);
     pxx = pxx - (d3 + rho * ux * ux);
@@ -123,8 +143,8 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
   float dc = gt[0];
 #pragma unroll
   for (int i = 1; i < Qg; ++i) dc = dc + gt[i];
-  const float c = (float)p.c0 + dc;
-  const float og = (float)p.omega_g, q = (float)p.q;
+  const float c = c0 + dc;
+  const float og = (float)p.omega_g;
   {
     const float wg = (float)L::wg[0];
     gt[0] = (gt[0] - og * (gt[0] - wg * dc)) + wg * q;
@@ -148,7 +168,7 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
                                              typename Prec<P>::R &ux, typename Prec<P>::R &uy,
                                              typename Prec<P>::R &uz) {
   if constexpr (P != 0) {
-    collide_f32<D>(p, d, ft, gt, rho, ux, uy, uz);
+    collide_f32<D>(p, d, ft, gt, rho, ux, uy, uz, (float)p.c0, (float)p.q);
     return;
   }
   using L = Lat<D>;
@@ -424,6 +444,15 @@ template <class T> __device__ __forceinline__ T from_lane_bits(uint32_t u) {
 // only ever feeds a wall cell).
 template <class T, int VW> using Vec = T __attribute__((ext_vector_type(VW)));
 
+// directions whose source lies on the side sx of the cell along x (ex = sx): the wall
+// pattern of a cell next to the low (sx = 1) or high (sx = -1) x wall of the box
+template <int D> constexpr uint32_t xwall_mask(int sx) {
+  uint32_t m = 0;
+  for (int i = 1; i < Lat<D>::Q; ++i)
+    if (Lat<D>::ex[i] == sx) m |= 1u << i;
+  return m;
+}
+
 template <class T, int VW, int EX>
 __device__ __forceinline__ Vec<T, VW> load_shifted(const T *plane, int64_t base, int64_t off, int64_t N, bool selfprev,
                                                    bool selfnext) {
@@ -537,6 +566,16 @@ __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
 
   const SF *fin = (const SF *)d.f[cur];
   const SG *gin = (const SG *)d.g[cur];
+  // instance 4 collides the dissolved gas in its stored units (offsets divided by the
+  // scale), with the reference concentration and the source divided likewise
+  auto gdec = [&](SG v) -> R {
+    if constexpr (P == 4) return (float)v;
+    else return GC::dec(v, p);
+  };
+  auto genc = [&](R v) -> SG {
+    if constexpr (P == 4) return (_Float16)v;
+    else return GC::enc(v, p);
+  };
 #pragma unroll
   for (int e = 0; e < VW; ++e) {
     if (liquid[e]) {
@@ -544,26 +583,38 @@ __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) ft[i] = FC::dec(fv[i][e], i);
 #pragma unroll
-      for (int i = 0; i < Qg; ++i) gt[i] = GC::dec(gv[i][e], p);
+      for (int i = 0; i < Qg; ++i) gt[i] = gdec(gv[i][e]);
       const int64_t n = n0 + e;
       if (anywall && (tv[e] & NEARWALL)) {
         // bounce-back: a population whose source is a wall is the cell's own outgoing
-        // population of the opposite direction
+        // population of the opposite direction. Every row has a cell next to each x wall,
+        // so nearly every wave has such lanes: their two wall patterns (all sources on the
+        // low or on the high x side) take a fixed set of directions without a test per
+        // direction; any other pattern tests them all.
         const uint32_t wm = d.wmask[n];
+        auto bounce = [&](uint32_t mask) {
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          if (wm & (1u << i)) {
-            ft[i] = FC::dec(fin[(int64_t)opp(i) * p.Np + n], i);
-            if (i < Qg) gt[i] = GC::dec(gin[(int64_t)opp(i) * p.Np + n], p);
+          for (int i = 1; i < Q; ++i) {
+            if (mask & (1u << i)) {
+              ft[i] = FC::dec(fin[(int64_t)opp(i) * p.Np + n], i);
+              if (i < Qg) gt[i] = gdec(gin[(int64_t)opp(i) * p.Np + n]);
+            }
           }
-        }
+        };
+        constexpr uint32_t XLO = xwall_mask<D>(1), XHI = xwall_mask<D>(-1);
+        if (wm == XLO) bounce(XLO);
+        else if (wm == XHI) bounce(XHI);
+        else bounce(wm);
       }
       R rho, ux, uy, uz;
-      collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
+      if constexpr (P == 4)
+        collide_f32<D>(p, d, ft, gt, rho, ux, uy, uz, (float)p.c0 * p.ginv, (float)p.q * p.ginv);
+      else
+        collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
 #pragma unroll
       for (int i = 0; i < Q; ++i) fv[i][e] = FC::enc(ft[i], i);
 #pragma unroll
-      for (int i = 0; i < Qg; ++i) gv[i][e] = GC::enc(gt[i], p);
+      for (int i = 0; i < Qg; ++i) gv[i][e] = genc(gt[i]);
     }
   }
 
