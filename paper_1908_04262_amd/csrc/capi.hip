@@ -103,7 +103,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.nilist = cv.take<int32_t>(Np * 4);
   d.l2ilist = cv.take<int32_t>(Np * 4);
   d.wmask = cv.take<uint32_t>(Np * 4);
-  d.lcnt = cv.take<int32_t>((size_t)2 * list_blocks_of(kp) * 4);
+  d.lcnt = cv.take<int32_t>((size_t)list_blocks_of(kp) * 4);
   d.sword = P.curvature == MF_CURV_MLP ? cv.take<uint32_t>(Np * 4) : nullptr;
   d.cnt = cv.take<int32_t>(C_NCOUNT * 4);
   d.status = cv.take<int32_t>(4);
@@ -135,6 +135,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.lab_vtot = cv.take<long long>(cap * 24);
   d.lab_vatm = cv.take<long long>(cap * 24);
   d.vacc = cv.take<long long>(cap * 24);
+  d.bng = cv.take<int32_t>(cap * 4);
   d.rh_key = cv.take<int32_t>((size_t)kp.RH * 4);
   d.rh_head = cv.take<int32_t>((size_t)kp.RH * 4);
   d.contested = cv.take<int32_t>((size_t)kp.ecap * 4);
@@ -573,6 +574,7 @@ int mf_refresh(mf_ctx *c, int32_t relabel) {
   c->sword_dirty = true;
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
+  recount_gas(*c, c->stream);
   if (relabel) c->ops.label(*c, c->stream, 0);
   c->ops.geometry(*c, c->stream);
   HIPCHK(c, hipStreamSynchronize(c->stream));

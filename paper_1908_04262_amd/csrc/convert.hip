@@ -136,7 +136,8 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
       const int64_t n = k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI];
       d.type[n] = (d.type[n] & ~TMASK) | TI;
     }
-    wave_fx_add(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg), d.gam0);
+    wave_fx_add_runs(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg), d.gam0);
+    wave_count_add(d.bng, emptied && lab > 0 && lab < p.cap, lab, 1);  // one more gas cell
   }
 }
 
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
       if (D == 3) ((R *)d.uz)[n] = ubz;
       ((R *)d.M)[n] = R(0);
     }
-    wave_fx_add(d.gam, act && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg), d.gam0);
+    wave_fx_add_runs(d.gam, act && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg), d.gam0);
+    wave_count_add(d.bng, act && lab > 0 && lab < p.cap, lab, -1);  // one gas cell fewer
   }
 }
 

@@ -433,7 +433,9 @@ __global__ __launch_bounds__(256) void k_sword_all(KP p, DA d) {
 template <int P>
 __global__ __launch_bounds__(256) void k_sword_lists(KP p, DA d) {
   using R = typename Prec<P>::R;
-  const int nI = *(volatile int32_t *)(d.cnt + C_I), nB = *(volatile int32_t *)(d.cnt + C_B);
+  // bubble cells change their ids only on relabelling steps
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nB = *(volatile int32_t *)(d.cnt + C_TOPO) ? *(volatile int32_t *)(d.cnt + C_B) : 0;
   const int nNI = *(volatile int32_t *)(d.cnt + C_NI), nL = *(volatile int32_t *)(d.cnt + C_L2I);
   const int64_t total = (int64_t)nI + nB + nNI + nL;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {

@@ -181,19 +181,22 @@ __global__ __launch_bounds__(256) void k_nuc_fix2(KP p, DA d) {
   }
 }
 
-// interface and bubble lists of the current types (the sweep builds them every step;
-// this full pass serves initial and hand-written states)
-// Interface list (type I) and bubble list (gas or interface with a non-zero bubble id),
-// in cell order, without atomics: each thread classifies 64 consecutive cells (16-byte
-// type loads; labels only where there is gas or interface); a count pass writes the
-// per-block totals, one work-group scans them, and a write pass places every entry at
-// its block's offset plus its rank inside the block.
+// Cell lists in cell order, without atomics: the interface list (type I) at the start of
+// every step, and the bubble list (gas or interface with a non-zero bubble id) on the
+// steps that relabel. The grid is cut into chunks of 16384 cells, each classified by a
+// work-group whose threads take 64 consecutive cells (16-byte type loads; labels only
+// where there is gas or interface); a count pass writes the per-chunk totals, one
+// work-group scans them, and a write pass places every entry at its chunk's offset plus
+// its rank inside the chunk. The work-groups step over the chunks, so the passes that
+// return at once (the bubble list on a step without relabelling) cost one small launch.
 constexpr int LIST_CPT = 64;
 constexpr int LIST_CHUNK = 256 * LIST_CPT;
+constexpr int LIST_GRID = 1024;
 
-__device__ __forceinline__ void list_masks(const KP &p, const DA &d, int64_t c0, unsigned long long &mi,
-                                           unsigned long long &mb) {
-  mi = mb = 0;
+// list 0: interface cells; list 1: gas / interface cells with a non-zero bubble id
+template <int WHICH>
+__device__ __forceinline__ unsigned long long list_mask(const KP &p, const DA &d, int64_t c0) {
+  unsigned long long mk = 0;
 #pragma unroll
   for (int g = 0; g < LIST_CPT / 16; ++g) {
     const int64_t n = c0 + g * 16;
@@ -212,126 +215,122 @@ __device__ __forceinline__ void list_masks(const KP &p, const DA &d, int64_t c0,
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int tt = t[k] & TMASK;
-      if (tt == TI) mi |= 1ull << (g * 16 + k);
+      if (WHICH == 0 && tt == TI) mk |= 1ull << (g * 16 + k);
       if (tt == TG || tt == TI) gi |= 1u << k;
     }
+    if (WHICH == 1) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((gi >> (4 * q)) & 15u)) continue;
-      int32_t lb[4];
-      if (n + 4 * q + 4 <= p.N) {
-        const int4 v = *(const int4 *)(d.label + n + 4 * q);
-        lb[0] = v.x; lb[1] = v.y; lb[2] = v.z; lb[3] = v.w;
-      } else {
+      for (int q = 0; q < 4; ++q) {
+        if (!((gi >> (4 * q)) & 15u)) continue;
+        int32_t lb[4];
+        if (n + 4 * q + 4 <= p.N) {
+          const int4 v = *(const int4 *)(d.label + n + 4 * q);
+          lb[0] = v.x; lb[1] = v.y; lb[2] = v.z; lb[3] = v.w;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lb[k] = n + 4 * q + k < p.N ? d.label[n + 4 * q + k] : 0;
+          for (int k = 0; k < 4; ++k) lb[k] = n + 4 * q + k < p.N ? d.label[n + 4 * q + k] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (((gi >> (4 * q + k)) & 1u) && lb[k] != 0) mk |= 1ull << (g * 16 + 4 * q + k);
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (((gi >> (4 * q + k)) & 1u) && lb[k] != 0) mb |= 1ull << (g * 16 + 4 * q + k);
     }
   }
+  return mk;
 }
 
-// block-wide inclusive scan of two counts (256 threads); returns the block totals
-__device__ __forceinline__ void block_scan2(int &si, int &sb, int &ti, int &tb) {
-  __shared__ int s_w[2][4];
+// block-wide inclusive scan of one count (256 threads); returns the block total
+__device__ __forceinline__ int block_scan(int &si) {
+  __shared__ int s_w[4];
   const int lane = lane_id(), w = threadIdx.x >> 6;
   for (int o = 1; o < 64; o <<= 1) {
-    const int a = __shfl_up(si, o), b = __shfl_up(sb, o);
-    if (lane >= o) { si += a; sb += b; }
+    const int a = __shfl_up(si, o);
+    if (lane >= o) si += a;
   }
-  if (lane == 63) {
-    s_w[0][w] = si;
-    s_w[1][w] = sb;
-  }
+  if (lane == 63) s_w[w] = si;
   __syncthreads();
-  ti = tb = 0;
+  int tot = 0;
   for (int k = 0; k < 4; ++k) {
-    if (k < w) {
-      si += s_w[0][k];
-      sb += s_w[1][k];
-    }
-    ti += s_w[0][k];
-    tb += s_w[1][k];
+    if (k < w) si += s_w[k];
+    tot += s_w[k];
   }
   __syncthreads();
+  return tot;
 }
 
-__global__ __launch_bounds__(256) void k_list_count(KP p, DA d) {
-  const int64_t c0 = (int64_t)blockIdx.x * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
-  unsigned long long mi, mb;
-  list_masks(p, d, c0, mi, mb);
-  int si = __popcll(mi), sb = __popcll(mb), ti, tb;
-  block_scan2(si, sb, ti, tb);
-  if (threadIdx.x == 0) {
-    d.lcnt[2 * blockIdx.x] = ti;
-    d.lcnt[2 * blockIdx.x + 1] = tb;
+template <int WHICH> __device__ __forceinline__ bool list_skipped(const DA &d) {
+  return WHICH == 1 && !*(volatile int32_t *)(d.cnt + C_TOPO);
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_list_count(KP p, DA d, int nchunks) {
+  if (list_skipped<WHICH>(d)) return;
+  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
+    int si = __popcll(list_mask<WHICH>(p, d, c0));
+    const int tot = block_scan(si);
+    if (threadIdx.x == 0) d.lcnt[ch] = tot;
   }
 }
 
-// exclusive scan of the per-block counts (in place) and the list lengths
-__global__ __launch_bounds__(1024) void k_list_scan(DA d, int nb) {
-  __shared__ int s_w[2][16];
+// exclusive scan of the per-chunk counts (in place) and the list length
+template <int WHICH>
+__global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
+  if (list_skipped<WHICH>(d)) return;
+  __shared__ int s_w[16];
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int per = (nb + 1023) / 1024;
+  const int per = (nchunks + 1023) / 1024;
   const int b0 = threadIdx.x * per;
-  int si = 0, sb = 0;
-  for (int k = 0; k < per && b0 + k < nb; ++k) {
-    si += d.lcnt[2 * (b0 + k)];
-    sb += d.lcnt[2 * (b0 + k) + 1];
-  }
-  const int ci = si, cb = sb;
+  int si = 0;
+  for (int k = 0; k < per && b0 + k < nchunks; ++k) si += d.lcnt[b0 + k];
+  const int ci = si;
   for (int o = 1; o < 64; o <<= 1) {
-    const int a = __shfl_up(si, o), b = __shfl_up(sb, o);
-    if (lane >= o) { si += a; sb += b; }
+    const int a = __shfl_up(si, o);
+    if (lane >= o) si += a;
   }
-  if (lane == 63) {
-    s_w[0][w] = si;
-    s_w[1][w] = sb;
-  }
+  if (lane == 63) s_w[w] = si;
   __syncthreads();
-  int oi = si - ci, ob = sb - cb, ti = 0, tb = 0;
+  int oi = si - ci, ti = 0;
   for (int k = 0; k < 16; ++k) {
-    if (k < w) {
-      oi += s_w[0][k];
-      ob += s_w[1][k];
-    }
-    ti += s_w[0][k];
-    tb += s_w[1][k];
+    if (k < w) oi += s_w[k];
+    ti += s_w[k];
   }
-  for (int k = 0; k < per && b0 + k < nb; ++k) {
-    const int a = d.lcnt[2 * (b0 + k)], b = d.lcnt[2 * (b0 + k) + 1];
-    d.lcnt[2 * (b0 + k)] = oi;
-    d.lcnt[2 * (b0 + k) + 1] = ob;
+  for (int k = 0; k < per && b0 + k < nchunks; ++k) {
+    const int a = d.lcnt[b0 + k];
+    d.lcnt[b0 + k] = oi;
     oi += a;
-    ob += b;
   }
-  if (threadIdx.x == 0) {
-    d.cnt[C_I] = ti;
-    d.cnt[C_B] = tb;
+  if (threadIdx.x == 0) d.cnt[WHICH == 0 ? C_I : C_B] = ti;
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
+  if (list_skipped<WHICH>(d)) return;
+  int32_t *list = WHICH == 0 ? d.ilist : d.blist;
+  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
+    unsigned long long mk = list_mask<WHICH>(p, d, c0);
+    const int ci = __popcll(mk);
+    int si = ci;
+    block_scan(si);
+    int o = d.lcnt[ch] + si - ci;
+    while (mk) {
+      const int b = __ffsll((long long)mk) - 1;
+      mk &= mk - 1;
+      list[o++] = (int32_t)(c0 + b);
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_list_write(KP p, DA d) {
-  const int64_t c0 = (int64_t)blockIdx.x * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
-  unsigned long long mi, mb;
-  list_masks(p, d, c0, mi, mb);
-  const int ci = __popcll(mi), cb = __popcll(mb);
-  int si = ci, sb = cb, ti, tb;
-  block_scan2(si, sb, ti, tb);
-  int oi = d.lcnt[2 * blockIdx.x] + si - ci, ob = d.lcnt[2 * blockIdx.x + 1] + sb - cb;
-  while (mi) {
-    const int b = __ffsll((long long)mi) - 1;
-    mi &= mi - 1;
-    d.ilist[oi++] = (int32_t)(c0 + b);
-  }
-  while (mb) {
-    const int b = __ffsll((long long)mb) - 1;
-    mb &= mb - 1;
-    d.blist[ob++] = (int32_t)(c0 + b);
-  }
+template <int WHICH> static void launch_list(const Ctx &c, hipStream_t s) {
+  const int nch = list_blocks_of(c.kp);
+  const unsigned g = (unsigned)(nch < LIST_GRID ? nch : LIST_GRID);
+  hipLaunchKernelGGL(k_list_count<WHICH>, dim3(g), dim3(256), 0, s, c.kp, c.d, nch);
+  hipLaunchKernelGGL(k_list_scan<WHICH>, dim3(1), dim3(1024), 0, s, c.d, nch);
+  hipLaunchKernelGGL(k_list_write<WHICH>, dim3(g), dim3(256), 0, s, c.kp, c.d, nch);
 }
+
+void build_bubble_list(const Ctx &c, hipStream_t s) { launch_list<1>(c, s); }
 
 int list_blocks_of(const KP &kp) { return (int)((kp.N + LIST_CHUNK - 1) / LIST_CHUNK); }
 
@@ -459,10 +458,7 @@ void launch_init_mass(Ctx &c, hipStream_t s, const double *p0_dev, int nn) {
 
 template <int D, int P>
 void Ops<D, P>::build_lists(Ctx &c, hipStream_t s) {
-  const int nb = list_blocks_of(c.kp);
-  hipLaunchKernelGGL(k_list_count, dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, c.d, nb);
-  hipLaunchKernelGGL(k_list_write, dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d);
+  launch_list<0>(c, s);
 }
 
 template <int D, int P>

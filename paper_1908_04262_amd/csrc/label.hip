@@ -39,12 +39,10 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
   }
 }
 
-// the union-find runs over the bubble cells listed by the sweep (gas / interface with
-// a non-zero id) plus the liquid cells that turned interface this step
+// the union-find runs over the bubble cells of the state after this step's conversions
+// (gas / interface with a non-zero id), listed at the start of a relabelling step
 #define CLIST_LOOP(k, n, total)                                                   \
-  const int _nB = *(volatile int32_t *)(d.cnt + C_B);                               \
-  const int _nL = *(volatile int32_t *)(d.cnt + C_L2I);                             \
-  const int64_t total = (int64_t)_nB + _nL;                                        \
+  const int64_t total = *(volatile int32_t *)(d.cnt + C_B);                       \
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                 \
        k < ((total + 63) & ~(int64_t)63); k += (int64_t)gridDim.x * blockDim.x)
 
@@ -52,7 +50,7 @@ __global__ __launch_bounds__(256) void k_ccl_init(DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
-    const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+    const int64_t n = d.blist[k];
     const int t = d.type[n] & TMASK;
     if ((t == TG || t == TI) && d.label[n] != 0) {
       d.parent[n] = (int32_t)n;
@@ -67,7 +65,7 @@ __global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
   using L = Lat<D>;
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
-    const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+    const int64_t n = d.blist[k];
     if (!(d.cflag[n] & CF_VALID)) continue;
     int x, y, z;
     cell_xyz(p, n, x, y, z);
@@ -87,7 +85,7 @@ __global__ __launch_bounds__(256) void k_ccl_compress(DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
-    const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+    const int64_t n = d.blist[k];
     const uint8_t cl = d.cflag[n];
     if (!(cl & CF_VALID)) continue;
     const int32_t r = uf_find(d.parent, (int32_t)n);
@@ -126,7 +124,7 @@ __global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
     unsigned long long key = 0;
     Fx3 v = {0, 0, 0};
     if (k < total) {
-      const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+      const int64_t n = d.blist[k];
       if (d.cflag[n] & CF_VALID) {
         act = true;
         const int32_t r = uf_find(d.parent, (int32_t)n);
@@ -258,6 +256,7 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
     d.bm[j] = 0.0;
     d.bV[j] = 0.0;
     d.bp[j] = 0.0;
+    d.bng[j] = 0;
   }
   if (tid < 64) {
     long long sa[3];
@@ -431,17 +430,59 @@ __global__ __launch_bounds__(256) void k_ccl_relabel(DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
-    const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+    const int64_t n = d.blist[k];
     if (!(d.cflag[n] & CF_VALID)) continue;
     d.label[n] = d.label[d.parent[n]];
   }
+}
+
+// gas cells of every bubble under the new ids (kept up to date by the conversions on
+// the steps that do not relabel)
+__global__ __launch_bounds__(256) void k_count_gas(KP p, DA d) {
+  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
+  CLIST_LOOP(k, n, total) {
+    bool act = false;
+    int lab = 0;
+    if (k < total) {
+      const int64_t n = d.blist[k];
+      if ((d.type[n] & TMASK) == TG) {
+        lab = d.label[n];
+        act = lab > 0 && lab < p.cap;
+      }
+    }
+    wave_count_add(d.bng, act, lab, 1);
+  }
+}
+
+__global__ void k_fill_words(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// the same counts from scratch over the whole grid (hand-written states)
+__global__ __launch_bounds__(256) void k_recount_gas(KP p, DA d) {
+  for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x; n0 < p.N; n0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = n0 + threadIdx.x;
+    bool act = false;
+    int lab = 0;
+    if (n < p.N && (d.type[n] & TMASK) == TG) {
+      lab = d.label[n];
+      act = lab > 0 && lab < p.cap;
+    }
+    wave_count_add(d.bng, act, lab, 1);
+  }
+}
+
+void recount_gas(const Ctx &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_words, dim3(64), dim3(256), 0, s, c.d.bng, (int64_t)c.kp.cap, 0);
+  const int64_t g = (c.kp.N + 255) / 256;
+  hipLaunchKernelGGL(k_recount_gas, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, s, c.kp, c.d);
 }
 
 __global__ __launch_bounds__(256) void k_ccl_clear(DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
     if (k >= total) continue;
-    const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
+    const int64_t n = d.blist[k];
     d.cflag[n] = 0;
   }
 }
@@ -455,23 +496,28 @@ template <int P>
 __global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
   using R = typename Prec<P>::R;
   if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
-  CLIST_LOOP(k, n, total) {
+  // the interface cells after the conversions: old ones that stayed, new ones from gas
+  // and from liquid; the gas cells of each bubble are counted (bng)
+  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
+  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const int64_t total = (int64_t)nI + nNI + nL;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
+       k += (int64_t)gridDim.x * blockDim.x) {
     bool act = false;
     int lab = 0;
     Fx3 v = {0, 0, 0};
     if (k < total) {
-      const int64_t n = k < _nB ? d.blist[k] : d.l2ilist[k - _nB];
-      const int t = d.type[n] & TMASK;
-      if (t == TG || t == TI) {
+      const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
+      if ((d.type[n] & TMASK) == TI) {
         lab = d.label[n];
         if (lab > 0 && lab < p.cap) {
           act = true;
-          const R one_minus = t == TG ? R(1) : R(1) - ((const R *)d.alpha)[n];
-          v = fx3((double)one_minus);
+          v = fx3((double)(R(1) - ((const R *)d.alpha)[n]));
         }
       }
     }
-    wave_fx_add(d.vacc, act, lab, v);
+    wave_fx_add_runs(d.vacc, act, lab, v);
   }
 }
 
@@ -491,7 +537,8 @@ __global__ __launch_bounds__(1024) void k_bubble_fast(KP p, DA d) {
   for (int j = tid; j < jmax; j += nt) {
     if (j > 0 && d.balive[j]) {
       const double mp = d.bm[j] + fx_to_double(join3(&d.phi[3 * j]) + join3(&d.gam[3 * j]));
-      write_bubble(p, d, j, mp, join3(&d.vacc[3 * j]));
+      // volume: one per gas cell, 1 - alpha per interface cell (fixed point, 2^64 = 1)
+      write_bubble(p, d, j, mp, join3(&d.vacc[3 * j]) + ((__int128)d.bng[j] << 64));
     }
     for (int c = 0; c < 3; ++c) d.phi[3 * j + c] = d.gam[3 * j + c] = d.vacc[3 * j + c] = 0;
   }
@@ -512,16 +559,21 @@ __global__ void k_force_full(DA d) { d.cnt[C_TOPO] = 1; }
 template <int D, int P>
 void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   const unsigned nb = list_blocks(c);
+  // the relabelling kernels return at once on most steps: a smaller grid keeps those
+  // launches cheap, and their grid-stride loops cover the list when they do run
+  const unsigned nf = nb < 1024 ? nb : 1024;
   if (!apply_flux) hipLaunchKernelGGL(k_force_full, dim3(1), dim3(1), 0, s, c.d);
   hipLaunchKernelGGL((k_vol_fast<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_bubble_fast, dim3(1), dim3(1024), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_ccl_init, dim3(nb), dim3(256), 0, s, c.d);
-  hipLaunchKernelGGL((k_ccl_hook<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_ccl_compress, dim3(nb), dim3(256), 0, s, c.d);
-  hipLaunchKernelGGL((k_ccl_accum<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  build_bubble_list(c, s);
+  hipLaunchKernelGGL(k_ccl_init, dim3(nf), dim3(256), 0, s, c.d);
+  hipLaunchKernelGGL((k_ccl_hook<D>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_ccl_compress, dim3(nf), dim3(256), 0, s, c.d);
+  hipLaunchKernelGGL((k_ccl_accum<P>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_bubble_update, dim3(1), dim3(1024), 0, s, c.kp, c.d, apply_flux);
-  hipLaunchKernelGGL(k_ccl_relabel, dim3(nb), dim3(256), 0, s, c.d);
-  hipLaunchKernelGGL(k_ccl_clear, dim3(nb), dim3(256), 0, s, c.d);
+  hipLaunchKernelGGL(k_ccl_relabel, dim3(nf), dim3(256), 0, s, c.d);
+  hipLaunchKernelGGL(k_count_gas, dim3(nf), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_ccl_clear, dim3(nf), dim3(256), 0, s, c.d);
 }
 
 #define MF_INST(D, P) template void Ops<D, P>::label(Ctx &, hipStream_t, int);

@@ -150,7 +150,8 @@ struct DA {
   void *rgas, *pbub;
   int32_t *label, *parent;
   int32_t *ilist, *blist, *nilist, *l2ilist;
-  int32_t *lcnt;              // per-block counts / offsets of the list builder [2][blocks]
+  int32_t *lcnt;              // per-chunk counts / offsets of the list builder [chunks]
+  int32_t *bng;               // gas cells of each bubble id [cap]
   uint32_t *wmask;            // static: bit i set when the source x - e_i of the cell is a wall
   int32_t *cnt;
   int32_t *status;
@@ -252,7 +253,49 @@ __device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, 
   }
 }
 
+// The same sum for keys (>= 0) that come in runs of neighbouring lanes, as along a list in
+// cell order: a segmented scan over the runs (six shuffle steps whatever the number of
+// keys) and one atomic per run from its last lane. Called by the whole wave.
+__device__ __forceinline__ void wave_fx_add_runs(long long *acc, bool pred, int key, Fx3 v,
+                                                 long long *spread0 = nullptr) {
+  const int lane = lane_id();
+  const int kk = pred ? key : -1;
+  const int prev = __shfl_up(kk, 1), next = __shfl_down(kk, 1);
+  const unsigned long long heads = __ballot(lane == 0 || prev != kk);
+  const int seg = __popcll(heads & ((2ull << lane) - 1ull));  // runs that start at or below
+  long long l = pred ? v.l : 0, m = pred ? v.m : 0, h = pred ? v.h : 0;
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long al = __shfl_up(l, o), am = __shfl_up(m, o), ah = __shfl_up(h, o);
+    const int so = __shfl_up(seg, o);
+    if (lane >= o && so == seg) {
+      l += al;
+      m += am;
+      h += ah;
+    }
+  }
+  if (pred && (lane == 63 || next != kk)) {
+    long long *dst = kk == 0 && spread0 ? spread0 + 3 * (blockIdx.x & (NSPREAD - 1)) : acc + 3 * kk;
+    atomicAdd((unsigned long long *)&dst[0], (unsigned long long)l);
+    atomicAdd((unsigned long long *)&dst[1], (unsigned long long)m);
+    atomicAdd((unsigned long long *)&dst[2], (unsigned long long)h);
+  }
+}
+
 __device__ __forceinline__ void raise_status(int32_t *st, int bits) { atomicOr(st, bits); }
+
+// add the wave-uniform v to acc[key] for every lane with pred, one atomic per key and
+// wave. Called by the whole wave.
+__device__ __forceinline__ void wave_count_add(int32_t *acc, bool pred, int key, int v) {
+  unsigned long long act = __ballot(pred);
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int k = __shfl(key, leader);
+    const unsigned long long mm = __ballot(pred && key == k);
+    if (lane_id() == leader) atomicAdd(&acc[k], v * (int)__popcll(mm));
+    act &= ~mm;
+    pred = pred && key != k;
+  }
+}
 
 // a slot of a device-counted list for every lane with pred, with one atomic per wave;
 // called by the whole wave
@@ -363,6 +406,10 @@ constexpr int kNumSweepVariants = 4;
 
 // work-groups of the list builder (one per chunk of cells)
 int list_blocks_of(const KP &kp);
+// the bubble list (gas / interface cells with a non-zero id) on a relabelling step
+void build_bubble_list(const Ctx &c, hipStream_t s);
+// gas cells of every bubble id counted over the whole grid
+void recount_gas(const Ctx &c, hipStream_t s);
 
 // Stencil word of a cell, read by the learned curvature's 5x5x5 gather in one load:
 // bits 0-15 the bfloat16 (nearest even) of the fill fraction a stencil reads there (1 for

@@ -375,7 +375,7 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
     for (int i = 0; i < Qg; ++i) gout[(int64_t)i * Np + n] = GC::enc(gt[i], p);
     if (isI) store_interface<D, R>(p, d, n, rho, ux, uy, uz, Ms, hasG, hasF);
   }
-  wave_fx_add(d.phi, hasgas && lab >= 0 && lab < p.cap, lab, fx3((double)phic), d.phi0);
+  wave_fx_add_runs(d.phi, hasgas && lab >= 0 && lab < p.cap, lab, fx3((double)phic), d.phi0);
 }
 
 // block index remapped so that consecutive tiles go to the same XCD (of 8): the
