@@ -76,38 +76,17 @@ __global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
   }
 }
 
-// liquid cells turned interface: M = rho, with rho and u the moments of their
+// (c) apply the new types; (e) an emptied cell hands its dissolved gas to its bubble; a
+// liquid cell turned interface takes M = rho, with rho and u the moments of its
 // post-collision populations
-template <int D, int P>
-__global__ __launch_bounds__(256) void k_l2i_init(KP p, DA d, int cur) {
-  using R = typename Prec<P>::R;
-  using SF = typename Prec<P>::SF;
-  using L = Lat<D>;
-  const SF *f = (const SF *)d.f[cur];
-  LIST_LOOP(k, d.cnt + C_L2I) {
-    if (k < *(volatile int32_t *)(d.cnt + C_L2I)) {
-      const int64_t n = d.l2ilist[k];
-      R fv[L::Q];
-#pragma unroll
-      for (int i = 0; i < L::Q; ++i) fv[i] = FCodec<P, D>::dec(f[(int64_t)i * p.Np + n], i);
-      R r, dr, ux, uy, uz;
-      Arith<D, P>::mom(fv, r, dr, ux, uy, uz);
-      ((R *)d.rho)[n] = r;
-      ((R *)d.ux)[n] = ux;
-      ((R *)d.uy)[n] = uy;
-      if (D == 3) ((R *)d.uz)[n] = uz;
-      ((R *)d.M)[n] = r;
-    }
-  }
-}
-
-// (c) apply the new types; (e) an emptied cell hands its dissolved gas to its bubble
 template <int D, int P>
 __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
   using SG = typename Prec<P>::SG;
+  using SF = typename Prec<P>::SF;
   using R = typename Prec<P>::R;
   using L = Lat<D>;
   const SG *g = (const SG *)d.g[cur];
+  const SF *f = (const SF *)d.f[cur];
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
   const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
@@ -133,8 +112,21 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
         sg = Arith<D, P>::conc(gv, R(p.c0), dc);
       }
     } else if (k < total) {
-      const int64_t n = k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI];
+      const bool l2i = k >= (int64_t)nI + nNI;
+      const int64_t n = l2i ? d.l2ilist[k - nI - nNI] : d.nilist[k - nI];
       d.type[n] = (d.type[n] & ~TMASK) | TI;
+      if (l2i) {
+        R fv[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) fv[i] = FCodec<P, D>::dec(f[(int64_t)i * p.Np + n], i);
+        R r, dr, ux, uy, uz;
+        Arith<D, P>::mom(fv, r, dr, ux, uy, uz);
+        ((R *)d.rho)[n] = r;
+        ((R *)d.ux)[n] = ux;
+        ((R *)d.uy)[n] = uy;
+        if (D == 3) ((R *)d.uz)[n] = uz;
+        ((R *)d.M)[n] = r;
+      }
     }
     wave_fx_add_runs(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg), d.gam0);
     wave_count_add(d.bng, emptied && lab > 0 && lab < p.cap, lab, 1);  // one more gas cell
@@ -273,19 +265,6 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
     }
     ((R *)d.M)[n] = acc;
     ((R *)d.alpha)[n] = acc / ((const R *)d.rho)[n];
-  }
-}
-
-// conversion flags are cleared once the new state is complete
-__global__ __launch_bounds__(256) void k_clear_conv_flags(DA d) {
-  const int nI = *(volatile int32_t *)(d.cnt + C_I);
-  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
-  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
-  const int64_t total = (int64_t)nI + nNI + nL;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-    d.cflag[n] = 0;
   }
 }
 
@@ -463,14 +442,12 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   const int cur = c.cur;  // buffer holding this step's post-collision populations
   hipLaunchKernelGGL((k_fill_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_empty_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL((k_l2i_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_apply<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_topo_check<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_topo_window<D>), dim3(256), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_ni_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_clear_conv_flags, dim3(nb), dim3(256), 0, s, c.d);
 }
 
 #define MF_INST(D, P) template void Ops<D, P>::convert(Ctx &, hipStream_t);

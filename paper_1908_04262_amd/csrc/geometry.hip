@@ -158,11 +158,15 @@ __device__ __forceinline__ R alpha_seen(const DA &d, int64_t y, R ac) {
            : (k < (int64_t)_nI + _nNI ? (int64_t)d.nilist[k - _nI] : (int64_t)d.l2ilist[k - _nI - _nNI]))
 
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_normals(KP p, DA d) {
+__global__ __launch_bounds__(256) void k_normals(KP p, DA d, int sword_all) {
   using R = typename Prec<P>::R;
   NEWI_LOOP(k, n) {
     const int64_t n = NEWI_CELL(k);
-    if ((d.type[n] & TMASK) != TI) continue;
+    const uint8_t tb = d.type[n];
+    // the cells of this step's lists are the ones whose type or fill fraction changed:
+    // their stencil words (learned curvature) follow here
+    if (d.sword && !sword_all) d.sword[n] = stencil_word<R>(tb, ((const R *)d.alpha)[n], d.label[n]);
+    if ((tb & TMASK) != TI) continue;
     int x, y, z;
     cell_xyz(p, n, x, y, z);
     const R ac = clamp01(((const R *)d.alpha)[n]);
@@ -253,20 +257,16 @@ __device__ __forceinline__ void add_point(R (&A)[NU][NU], R (&rhs)[NU], const R 
   }
 }
 
+// plain curvature of interface cell n: paraboloid (parabola in 2D) least squares through
+// the PLIC points of the cell and of the interface cells of its block
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
+__device__ __forceinline__ typename Prec<P>::R plain_fit(const KP &p, const DA &d, int64_t n) {
   using R = typename Prec<P>::R;
   constexpr int NU = D == 3 ? 6 : 3;
   constexpr int RR = D == 3 ? 1 : 2;
   const R rel = sizeof(R) == 8 ? R(1e-9) : R(1e-6);
   const R *MX = (const R *)d.mx, *MY = (const R *)d.my, *MZ = (const R *)d.mz, *SO = (const R *)d.soff;
-  NEWI_LOOP(k, n) {
-    const int64_t n = NEWI_CELL(k);
-    if ((d.type[n] & TMASK) != TI) continue;
-    if (d.cflag[n] & CF_MLPOK) {  // the network already gave this cell's curvature
-      d.cflag[n] = 0;
-      continue;
-    }
+  {
     const R m0 = MX[n], m1 = MY[n], m2 = MZ[n];
     R kap = R(0);
     if (m0 != R(0) || m1 != R(0) || m2 != R(0)) {
@@ -352,16 +352,16 @@ __global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
         if (kap < R(-1)) kap = R(-1);
       }
     }
-    ((R *)d.kappa)[n] = kap;
+    return kap;
   }
 }
 
+// disjoining pressure of interface cell n (ray march along its normal) and the gas side
+// the next sweep rebuilds missing populations with
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_disjoining(KP p, DA d) {
+__device__ __forceinline__ void disjoining_cell(const KP &p, DA &d, int64_t n, typename Prec<P>::R kap) {
   using R = typename Prec<P>::R;
-  NEWI_LOOP(k, n) {
-    const int64_t n = NEWI_CELL(k);
-    if ((d.type[n] & TMASK) != TI) continue;
+  {
     R Pi = R(0);
     const R m[3] = {((const R *)d.mx)[n], ((const R *)d.my)[n], ((const R *)d.mz)[n]};
     if (p.k_pi > 0.0 && (m[0] != R(0) || m[1] != R(0) || m[2] != R(0))) {
@@ -413,16 +413,33 @@ __global__ __launch_bounds__(256) void k_disjoining(KP p, DA d) {
     double pb = p.p_atm;
     if (lab >= 0 && lab < p.cap && d.balive[lab]) pb = d.bp[lab];
     else raise_status(d.status, ST_BADLABEL);
-    const R kap = ((const R *)d.kappa)[n];
     ((R *)d.rgas)[n] = R(3) * ((R(pb) - R(2) * R(p.sigma) * kap) - Pi);
     ((R *)d.pbub)[n] = R(pb);
   }
 }
 
-// stencil words (learned curvature): over the whole grid after a state change made
-// outside the time step, else over the cells whose type, fill fraction or bubble id can
-// have changed in this step (this step's interface list, the new interface cells and the
-// relabelled bubble cells)
+// per interface cell: curvature (the plain fit, unless the network already gave it),
+// disjoining pressure and gas side
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  NEWI_LOOP(k, n) {
+    const int64_t n = NEWI_CELL(k);
+    if ((d.type[n] & TMASK) != TI) continue;
+    R kap;
+    if (d.cflag[n] & CF_MLPOK) {  // the network already gave this cell's curvature
+      d.cflag[n] = 0;
+      kap = ((const R *)d.kappa)[n];
+    } else {
+      kap = plain_fit<D, P>(p, d, n);
+      ((R *)d.kappa)[n] = kap;
+    }
+    disjoining_cell<D, P>(p, d, n, kap);
+  }
+}
+
+// stencil words (learned curvature) over the whole grid, after a state change made
+// outside the time step
 template <int P>
 __global__ __launch_bounds__(256) void k_sword_all(KP p, DA d) {
   using R = typename Prec<P>::R;
@@ -430,41 +447,20 @@ __global__ __launch_bounds__(256) void k_sword_all(KP p, DA d) {
     d.sword[n] = stencil_word<R>(d.type[n], ((const R *)d.alpha)[n], d.label[n]);
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_sword_lists(KP p, DA d) {
-  using R = typename Prec<P>::R;
-  // bubble cells change their ids only on relabelling steps
-  const int nI = *(volatile int32_t *)(d.cnt + C_I);
-  const int nB = *(volatile int32_t *)(d.cnt + C_TOPO) ? *(volatile int32_t *)(d.cnt + C_B) : 0;
-  const int nNI = *(volatile int32_t *)(d.cnt + C_NI), nL = *(volatile int32_t *)(d.cnt + C_L2I);
-  const int64_t total = (int64_t)nI + nB + nNI + nL;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
-    int64_t q = k;
-    int32_t n;
-    if (q < nI) n = d.ilist[q];
-    else if ((q -= nI) < nB) n = d.blist[q];
-    else if ((q -= nB) < nNI) n = d.nilist[q];
-    else n = d.l2ilist[q - nNI];
-    d.sword[n] = stencil_word<R>(d.type[n], ((const R *)d.alpha)[n], d.label[n]);
-  }
-}
-
 template <int D, int P>
 void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
   const unsigned nb = list_blocks(c);
-  if (c.d.sword) {
-    if (c.sword_dirty) {
-      const int64_t g = (c.kp.N + 255) / 256;
-      hipLaunchKernelGGL((k_sword_all<P>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, c.kp, c.d);
-      c.sword_dirty = false;
-    } else {
-      hipLaunchKernelGGL((k_sword_lists<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-    }
+  // stencil words: over the whole grid after a state change made outside the time step,
+  // else with the normals (this step's list cells) and the relabelling (bubble cells)
+  const int sword_all = c.d.sword && c.sword_dirty;
+  if (sword_all) {
+    const int64_t g = (c.kp.N + 255) / 256;
+    hipLaunchKernelGGL((k_sword_all<P>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, c.kp, c.d);
+    c.sword_dirty = false;
   }
-  hipLaunchKernelGGL((k_normals<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_normals<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, sword_all);
   if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
   hipLaunchKernelGGL((k_curvature<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL((k_disjoining<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   c.gas_dirty = false;
 }
 

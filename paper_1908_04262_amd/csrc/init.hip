@@ -317,7 +317,13 @@ __global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
     while (mk) {
       const int b = __ffsll((long long)mk) - 1;
       mk &= mk - 1;
-      list[o++] = (int32_t)(c0 + b);
+      const int32_t n = (int32_t)(c0 + b);
+      list[o++] = n;
+      if (WHICH == 1) {
+        // union-find start of the relabelling: each bubble cell its own root
+        d.parent[n] = n;
+        flag_or(d.cflag, n, CF_VALID);
+      }
     }
   }
 }

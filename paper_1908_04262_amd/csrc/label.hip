@@ -46,19 +46,6 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                 \
        k < ((total + 63) & ~(int64_t)63); k += (int64_t)gridDim.x * blockDim.x)
 
-__global__ __launch_bounds__(256) void k_ccl_init(DA d) {
-  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
-  CLIST_LOOP(k, n, total) {
-    if (k >= total) continue;
-    const int64_t n = d.blist[k];
-    const int t = d.type[n] & TMASK;
-    if ((t == TG || t == TI) && d.label[n] != 0) {
-      d.parent[n] = (int32_t)n;
-      flag_or(d.cflag, n, CF_VALID);
-    }
-  }
-}
-
 template <int D>
 __global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
@@ -78,18 +65,6 @@ __global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
       else if (yy > n) uf_union(d.parent, (int32_t)n, (int32_t)yy);
     }
     if (atm) flag_or(d.cflag, n, CF_ATM);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_ccl_compress(DA d) {
-  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
-  CLIST_LOOP(k, n, total) {
-    if (k >= total) continue;
-    const int64_t n = d.blist[k];
-    const uint8_t cl = d.cflag[n];
-    if (!(cl & CF_VALID)) continue;
-    const int32_t r = uf_find(d.parent, (int32_t)n);
-    if (cl & CF_ATM) flag_or(d.cflag, r, CF_ATMROOT);
   }
 }
 
@@ -114,7 +89,8 @@ __device__ __forceinline__ int hash_insert(const KP &p, DA &d, unsigned long lon
   return -1;
 }
 
-// volume share (1 - alpha) of every bubble cell, summed per (component root, old id)
+// final roots (a cell next to the atmosphere marks its root), and the volume share
+// (1 - alpha) of every bubble cell summed per (component root, old id)
 template <int P>
 __global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
@@ -125,10 +101,12 @@ __global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
     Fx3 v = {0, 0, 0};
     if (k < total) {
       const int64_t n = d.blist[k];
-      if (d.cflag[n] & CF_VALID) {
+      const uint8_t cl = d.cflag[n];
+      if (cl & CF_VALID) {
         act = true;
         const int32_t r = uf_find(d.parent, (int32_t)n);
         d.parent[n] = r;
+        if (cl & CF_ATM) flag_or(d.cflag, r, CF_ATMROOT);
         key = ((unsigned long long)(uint32_t)r << 32) | (unsigned long long)(uint32_t)d.label[n];
         const int t = d.type[n] & TMASK;
         const R one_minus = t == TG ? R(1) : R(1) - ((const R *)d.alpha)[n];
@@ -426,31 +404,29 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
   }
 }
 
-__global__ __launch_bounds__(256) void k_ccl_relabel(DA d) {
+// new ids onto every cell from its root, the gas cells of every bubble counted under the
+// new ids (kept up to date by the conversions on the steps that do not relabel), and the
+// labelling flags cleared
+template <int P>
+__global__ __launch_bounds__(256) void k_ccl_relabel(KP p, DA d) {
+  using R = typename Prec<P>::R;
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
-    if (k >= total) continue;
-    const int64_t n = d.blist[k];
-    if (!(d.cflag[n] & CF_VALID)) continue;
-    d.label[n] = d.label[d.parent[n]];
-  }
-}
-
-// gas cells of every bubble under the new ids (kept up to date by the conversions on
-// the steps that do not relabel)
-__global__ __launch_bounds__(256) void k_count_gas(KP p, DA d) {
-  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
-  CLIST_LOOP(k, n, total) {
-    bool act = false;
+    bool gas = false;
     int lab = 0;
     if (k < total) {
       const int64_t n = d.blist[k];
-      if ((d.type[n] & TMASK) == TG) {
-        lab = d.label[n];
-        act = lab > 0 && lab < p.cap;
+      if (d.cflag[n] & CF_VALID) {
+        lab = d.label[d.parent[n]];
+        d.label[n] = lab;
+        const uint8_t tb = d.type[n];
+        gas = (tb & TMASK) == TG && lab > 0 && lab < p.cap;
+        // the stencil words (learned curvature) carry the id
+        if (d.sword) d.sword[n] = stencil_word<R>(tb, ((const R *)d.alpha)[n], lab);
       }
+      d.cflag[n] = 0;
     }
-    wave_count_add(d.bng, act, lab, 1);
+    wave_count_add(d.bng, gas, lab, 1);
   }
 }
 
@@ -458,7 +434,7 @@ __global__ void k_fill_words(int32_t *p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// the same counts from scratch over the whole grid (hand-written states)
+// the gas-cell counts from scratch over the whole grid (hand-written states)
 __global__ __launch_bounds__(256) void k_recount_gas(KP p, DA d) {
   for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x; n0 < p.N; n0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t n = n0 + threadIdx.x;
@@ -478,24 +454,16 @@ void recount_gas(const Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL(k_recount_gas, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, s, c.kp, c.d);
 }
 
-__global__ __launch_bounds__(256) void k_ccl_clear(DA d) {
-  if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
-  CLIST_LOOP(k, n, total) {
-    if (k >= total) continue;
-    const int64_t n = d.blist[k];
-    d.cflag[n] = 0;
-  }
-}
-
 // ------------------------------------------------------------------ fast path
 // Steps whose conversions cannot have changed any component (C_TOPO clear) keep every
 // id; each bubble then holds all of its gas, and only its volume and pressure change.
 // The sums are the same fixed-point sums as the full path's, so the results are
 // identical to what the full labelling would give.
+// Also clears the conversion flags of this step's list cells, on every step.
 template <int P>
 __global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
   using R = typename Prec<P>::R;
-  if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
+  const bool fast = !*(volatile int32_t *)(d.cnt + C_TOPO);
   // the interface cells after the conversions: old ones that stayed, new ones from gas
   // and from liquid; the gas cells of each bubble are counted (bng)
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
@@ -509,7 +477,8 @@ __global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
     Fx3 v = {0, 0, 0};
     if (k < total) {
       const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-      if ((d.type[n] & TMASK) == TI) {
+      d.cflag[n] = 0;
+      if (fast && (d.type[n] & TMASK) == TI) {
         lab = d.label[n];
         if (lab > 0 && lab < p.cap) {
           act = true;
@@ -517,7 +486,7 @@ __global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
         }
       }
     }
-    wave_fx_add_runs(d.vacc, act, lab, v);
+    if (fast) wave_fx_add_runs(d.vacc, act, lab, v);
   }
 }
 
@@ -565,15 +534,11 @@ void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   if (!apply_flux) hipLaunchKernelGGL(k_force_full, dim3(1), dim3(1), 0, s, c.d);
   hipLaunchKernelGGL((k_vol_fast<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_bubble_fast, dim3(1), dim3(1024), 0, s, c.kp, c.d);
-  build_bubble_list(c, s);
-  hipLaunchKernelGGL(k_ccl_init, dim3(nf), dim3(256), 0, s, c.d);
+  build_bubble_list(c, s);  // also starts the union-find: every listed cell its own root
   hipLaunchKernelGGL((k_ccl_hook<D>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_ccl_compress, dim3(nf), dim3(256), 0, s, c.d);
   hipLaunchKernelGGL((k_ccl_accum<P>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_bubble_update, dim3(1), dim3(1024), 0, s, c.kp, c.d, apply_flux);
-  hipLaunchKernelGGL(k_ccl_relabel, dim3(nf), dim3(256), 0, s, c.d);
-  hipLaunchKernelGGL(k_count_gas, dim3(nf), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_ccl_clear, dim3(nf), dim3(256), 0, s, c.d);
+  hipLaunchKernelGGL((k_ccl_relabel<P>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
 }
 
 #define MF_INST(D, P) template void Ops<D, P>::label(Ctx &, hipStream_t, int);
