@@ -426,8 +426,9 @@ struct MlpWaveLds {
     short h[16][NH + 4];
   };
   // the 64 cells of the wave's tile
-  int cell[64], x[64], y[64], z[64], lab[64], code[64], coef[64];
-  float ac[64];
+  // per cell: index, coordinates, id + 1, flags, packed canonical-slot coefficients,
+  // and the bfloat16 bits of its clamped fill fraction (what a wall element reads)
+  int cell[64], x[64], y[64], z[64], lab1[64], code[64], coef[64], acb[64];
 };
 
 // bfloat16 bits of a binary32 value, round to nearest even (hardware conversion)
@@ -492,6 +493,9 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
   const int dx1 = j1 % 5 - 2, dy1 = (j1 / 5) % 5 - 2, dz1 = j1 / 25 - 2;
   const int64_t off0 = (int64_t)dx0 + (int64_t)p.nx * dy0 + nxy * dz0;
   const int64_t off1 = (int64_t)dx1 + (int64_t)p.nx * dy1 + nxy * dz1;
+  // the same offsets as packed signed bytes, for the canonical-slot dot product
+  const int dpk0 = (dx0 & 0xFF) | ((dy0 & 0xFF) << 8) | ((dz0 & 0xFF) << 16);
+  const int dpk1 = (dx1 & 0xFF) | ((dy1 & 0xFF) << 8) | ((dz1 & 0xFF) << 16);
   // stencil words of cells sb .. sb+15: slot m of a lane is element lane + 64 (m & 1) of
   // cell sb + (m >> 1); all 32 loads are issued before any is used
   uint32_t wd[32];
@@ -569,10 +573,10 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       M.x[lane] = cx;
       M.y[lane] = cy;
       M.z[lane] = cz;
-      M.lab[lane] = lab;
+      M.lab1[lane] = lab + 1;
       M.code[lane] = code;
       M.coef[lane] = coef;
-      M.ac[lane] = ac;
+      M.acb[lane] = (int)(uint16_t)bf16_hw(ac);
     }
     wave_lds_sync();
     gather(0);
@@ -590,11 +594,11 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
           continue;
         }
         const uint32_t code = wd[m] >> 16;
-        if (code == 0xFFFFu || (code != 0u && code != (uint32_t)(uniform(M.lab[c]) + 1))) badm |= 1u << (m >> 1);
-        const short bits = code == 0xFFFFu ? bf16_hw(uniform(M.ac[c])) : (short)(wd[m] & 0xFFFFu);
-        const int cf = uniform(M.coef[c]);
-        const int slot = 62 + (int)(int8_t)cf * (h ? dx1 : dx0) + (int)(int8_t)(cf >> 8) * (h ? dy1 : dy0) +
-                         (int)(int8_t)(cf >> 16) * (h ? dz1 : dz0);
+        // a wall (0xFFFF never equals an id + 1) or gas / interface of another bubble
+        if (code != 0u && code != (uint32_t)uniform(M.lab1[c])) badm |= 1u << (m >> 1);
+        const short bits = (short)(code == 0xFFFFu ? (uint32_t)uniform(M.acb[c]) : wd[m] & 0xFFFFu);
+        // 62 + cx dx + cy dy + cz dz on packed signed bytes
+        const int slot = __builtin_amdgcn_sdot4(h ? dpk1 : dpk0, uniform(M.coef[c]), 62, false);
         M.a[m >> 1][slot] = bits;
       }
       // the next 16 cells' loads run under this sub-tile's products
