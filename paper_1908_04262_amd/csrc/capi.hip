@@ -102,6 +102,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.blist = cv.take<int32_t>(Np * 4);
   d.nilist = cv.take<int32_t>(Np * 4);
   d.l2ilist = cv.take<int32_t>(Np * 4);
+  d.clist = cv.take<int32_t>(Np * 4);
   d.wmask = cv.take<uint32_t>(Np * 4);
   d.lcnt = cv.take<int32_t>((size_t)list_blocks_of(kp) * 4);
   d.sword = P.curvature == MF_CURV_MLP ? cv.take<uint32_t>(Np * 4) : nullptr;

@@ -13,30 +13,43 @@ namespace mf {
 template <int D>
 __global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
   using L = Lat<D>;
-  LIST_LOOP(k, d.cnt + C_I) {
+  SPREAD_LOOP(k, d.cnt + C_CONV) {
     bool act = false;
     int64_t n = 0;
-    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
-      n = d.ilist[k];
+    if (k < *(volatile int32_t *)(d.cnt + C_CONV)) {
+      n = d.clist[k];
       act = (d.cflag[n] & CF_FILL) != 0;
     }
     if (!__ballot(act)) continue;  // wave-uniform
-    int x = 0, y = 0, z = 0;
-    if (act) cell_xyz(p, n, x, y, z);
+    // neighbour types first (all loads in flight together), then the flag updates, then
+    // the list appends
+    int64_t yy[L::Q];
+    int ty[L::Q];
+#pragma unroll
     for (int i = 1; i < L::Q; ++i) {
-      bool add = false;
-      int64_t yy = 0;
-      if (act) {
-        yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-        const int ty = d.type[yy] & TMASK;
-        if (ty == TG) {
-          add = !(flag_or(d.cflag, yy, CF_NEWI) & CF_NEWI);
-        } else if (ty == TI) {
-          if (d.cflag[yy] & CF_EMPTY) flag_clear(d.cflag, yy, CF_EMPTY);
-        }
-      }
+      yy[i] = 0;
+      ty[i] = TW;
+    }
+    if (act) {
+      int x, y, z;
+      cell_xyz(p, n, x, y, z);
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) yy[i] = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) ty[i] = d.type[yy[i]] & TMASK;
+    }
+    uint32_t old[L::Q];
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      old[i] = CF_NEWI;
+      if (ty[i] == TG) old[i] = flag_or(d.cflag, yy[i], CF_NEWI);
+      else if (ty[i] == TI && (d.cflag[yy[i]] & CF_EMPTY)) flag_clear(d.cflag, yy[i], CF_EMPTY);
+    }
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      const bool add = !(old[i] & CF_NEWI);
       const int slot = wave_append_slot(d.cnt + C_NI, add);
-      if (add) d.nilist[slot] = (int32_t)yy;
+      if (add) d.nilist[slot] = (int32_t)yy[i];
     }
   }
 }
@@ -46,32 +59,45 @@ __global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
 template <int D>
 __global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
   using L = Lat<D>;
-  LIST_LOOP(k, d.cnt + C_I) {
+  SPREAD_LOOP(k, d.cnt + C_CONV) {
     bool act = false;
     int64_t n = 0;
-    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
-      n = d.ilist[k];
+    if (k < *(volatile int32_t *)(d.cnt + C_CONV)) {
+      n = d.clist[k];
       act = (d.cflag[n] & CF_EMPTY) != 0;
     }
     if (!__ballot(act)) continue;  // wave-uniform
-    int x = 0, y = 0, z = 0;
+    int64_t yy[L::Q];
+    int ty[L::Q];
     int32_t lab = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      yy[i] = 0;
+      ty[i] = TW;
+    }
     if (act) {
+      int x, y, z;
       cell_xyz(p, n, x, y, z);
       lab = d.label[n];
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) yy[i] = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) ty[i] = d.type[yy[i]] & TMASK;
     }
+    uint32_t old[L::Q];
+#pragma unroll
     for (int i = 1; i < L::Q; ++i) {
-      bool add = false;
-      int64_t yy = 0;
-      if (act) {
-        yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-        if ((d.type[yy] & TMASK) == TL) {
-          atomicMin((unsigned int *)&d.label[yy], (unsigned int)lab);
-          add = !(flag_or(d.cflag, yy, CF_L2I) & CF_L2I);
-        }
+      old[i] = CF_L2I;
+      if (ty[i] == TL) {
+        atomicMin((unsigned int *)&d.label[yy[i]], (unsigned int)lab);
+        old[i] = flag_or(d.cflag, yy[i], CF_L2I);
       }
+    }
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      const bool add = !(old[i] & CF_L2I);
       const int slot = wave_append_slot(d.cnt + C_L2I, add);
-      if (add) d.l2ilist[slot] = (int32_t)yy;
+      if (add) d.l2ilist[slot] = (int32_t)yy[i];
     }
   }
 }
@@ -87,17 +113,16 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
   using L = Lat<D>;
   const SG *g = (const SG *)d.g[cur];
   const SF *f = (const SF *)d.f[cur];
-  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nI = *(volatile int32_t *)(d.cnt + C_CONV);  // the cells that fill or empty
   const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
   const int64_t total = (int64_t)nI + nNI + nL;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
-       k += (int64_t)gridDim.x * blockDim.x) {
+  SPREAD_LOOP_N(k, total) {
     bool emptied = false;
     int32_t lab = 0;
     R sg = R(0);
     if (k < nI) {
-      const int64_t n = d.ilist[k];
+      const int64_t n = d.clist[k];
       const uint8_t cl = d.cflag[n];
       if (cl & CF_FILL) {
         d.type[n] = (d.type[n] & ~TMASK) | TL;
@@ -145,7 +170,7 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
   using L = Lat<D>;
   SF *f = (SF *)d.f[cur];
   SG *g = (SG *)d.g[cur];
-  LIST_LOOP(k, d.cnt + C_NI) {
+  SPREAD_LOOP(k, d.cnt + C_NI) {
     bool act = false;
     int32_t lab = 0;
     R sg = R(0);
@@ -218,11 +243,11 @@ template <int D, int P>
 __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
   using R = typename Prec<P>::R;
   using L = Lat<D>;
-  LIST_LOOP(k, d.cnt + C_I) {
+  SPREAD_LOOP(k, d.cnt + C_CONV) {
     bool lost = false;
     R e = R(0);
-    if (k < *(volatile int32_t *)(d.cnt + C_I)) {
-      const int64_t n = d.ilist[k];
+    if (k < *(volatile int32_t *)(d.cnt + C_CONV)) {
+      const int64_t n = d.clist[k];
       const uint8_t cl = d.cflag[n];
       if (cl & (CF_FILL | CF_EMPTY)) {
         const R Ms = ((const R *)d.M)[n];
@@ -230,9 +255,19 @@ __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
         int x, y, z;
         cell_xyz(p, n, x, y, z);
         int cnt = 0;
+        int64_t yy[L::Q];
+        int ty[L::Q];
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) yy[i] = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) ty[i] = d.type[yy[i]] & TMASK;
+#pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-          const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-          if ((d.type[yy] & TMASK) == TI) cnt++;
+          if (ty[i] == TI) {
+            cnt++;
+            // it gathers a share
+            atomicOr((uint32_t *)(d.cflag + (yy[i] & ~(int64_t)3)), CF_EXNB << (8 * (int)(yy[i] & 3)));
+          }
         }
         if (cnt > 0) ((R *)d.exc)[n] = e / R(cnt);
         else lost = true;
@@ -255,13 +290,16 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-    if (k < nI && (d.cflag[n] & (CF_FILL | CF_EMPTY))) continue;
-    int x, y, z;
-    cell_xyz(p, n, x, y, z);
+    const uint8_t cl = d.cflag[n];
+    if (k < nI && (cl & (CF_FILL | CF_EMPTY))) continue;
     R acc = ((const R *)d.M)[n];
-    for (int i = 1; i < L::Q; ++i) {
-      const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-      if (d.cflag[yy] & (CF_FILL | CF_EMPTY)) acc = acc + ((const R *)d.exc)[yy];
+    if (cl & CF_EXNB) {  // next to a converted cell
+      int x, y, z;
+      cell_xyz(p, n, x, y, z);
+      for (int i = 1; i < L::Q; ++i) {
+        const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+        if (d.cflag[yy] & (CF_FILL | CF_EMPTY)) acc = acc + ((const R *)d.exc)[yy];
+      }
     }
     ((R *)d.M)[n] = acc;
     ((R *)d.alpha)[n] = acc / ((const R *)d.rho)[n];
@@ -361,49 +399,52 @@ template <int D> struct RowWindow {
   }
 };
 
-// cheap per-cell tests over the interface list: joining cells are decided here, filling
+// cheap per-cell tests over the converted cells: joining cells are decided here, filling
 // cells that need the window test are listed
 template <int D>
 __global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
   using L = Lat<D>;
-  const int nI = *(volatile int32_t *)(d.cnt + C_I);
+  const int nI = *(volatile int32_t *)(d.cnt + C_CONV);  // the cells that fill or empty
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
   const int64_t total = (int64_t)nI + nL;
   // a periodic axis shorter than the widest window would wrap it onto itself: full
   // labelling
   constexpr int WMAX = 7;
   bool change = total > 0 && ((p.per[0] && p.nx < WMAX) || (p.per[1] && p.ny < WMAX) || (D == 3 && p.per[2] && p.nz < WMAX));
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
-       k += (int64_t)gridDim.x * blockDim.x) {
+  SPREAD_LOOP_N(k, total) {
     bool cand = false;
     int64_t n = 0;
     if (k >= total || change) {
-    } else if (k >= nI) {
-      n = d.l2ilist[k - nI];
-      const int32_t lx = d.label[n];
-      int x, y, z;
-      cell_xyz(p, n, x, y, z);
-      for (int i = 1; i < L::Q; ++i) {
-        const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-        if (yy < 0) continue;
-        const int t = d.type[yy] & TMASK;
-        if ((t == TG || t == TI) && d.label[yy] != lx) change = true;
-      }
     } else {
-      n = d.ilist[k];
-      if (d.cflag[n] & CF_FILL) {
+      // both tests read the types and ids of the lattice neighbours: loaded together
+      const bool join = k >= nI;
+      n = join ? d.l2ilist[k - nI] : d.clist[k];
+      if (join || (d.cflag[n] & CF_FILL)) {
         int x, y, z;
         cell_xyz(p, n, x, y, z);
-        // a leaving cell of the atmosphere (a gas / interface neighbour with id 0) changes
-        // no bubble: every piece of the atmosphere keeps id 0 and no bubble touches it
-        bool atm = false;
-        for (int i = 1; i < L::Q; ++i) {
-          const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-          if (yy < 0) continue;
-          const int t = d.type[yy] & TMASK;
-          if ((t == TG || t == TI) && d.label[yy] == 0) atm = true;
+        int64_t yy[L::Q];
+        int t[L::Q];
+        int32_t lb[L::Q];
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) yy[i] = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) t[i] = yy[i] >= 0 ? d.type[yy[i]] & TMASK : TW;
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) lb[i] = yy[i] >= 0 ? d.label[yy[i]] : 0;
+        if (join) {
+          const int32_t lx = d.label[n];
+#pragma unroll
+          for (int i = 1; i < L::Q; ++i)
+            if ((t[i] == TG || t[i] == TI) && lb[i] != lx) change = true;
+        } else {
+          // a leaving cell of the atmosphere (a gas / interface neighbour with id 0) changes
+          // no bubble: every piece of the atmosphere keeps id 0 and no bubble touches it
+          bool atm = false;
+#pragma unroll
+          for (int i = 1; i < L::Q; ++i)
+            if ((t[i] == TG || t[i] == TI) && lb[i] == 0) atm = true;
+          cand = !atm;
         }
-        cand = !atm;
       }
     }
     const int slot = wave_append_slot(d.cnt + C_TCAND, cand);

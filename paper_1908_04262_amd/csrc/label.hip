@@ -490,20 +490,22 @@ __global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_bubble_fast(KP p, DA d) {
+// Several work-groups over the ids; the first also folds the atmosphere's terms and the
+// step's ledgers into the running totals.
+__global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
   if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   __shared__ long long s_atm[3];
   int jmax = *(volatile int32_t *)(d.cnt + C_NEXTID);
   if (jmax > p.cap) jmax = p.cap;
-  if (tid < 64) {
+  if (blockIdx.x == 0 && tid < 64) {
     long long sa[3];
     take_atm_copies(d, sa);
     if (tid == 0)
       for (int c = 0; c < 3; ++c) s_atm[c] = d.phi[c] + d.gam[c] + sa[c];
   }
   __syncthreads();
-  for (int j = tid; j < jmax; j += nt) {
+  for (int j = blockIdx.x * blockDim.x + tid; j < jmax; j += gridDim.x * blockDim.x) {
     if (j > 0 && d.balive[j]) {
       const double mp = d.bm[j] + fx_to_double(join3(&d.phi[3 * j]) + join3(&d.gam[3 * j]));
       // volume: one per gas cell, 1 - alpha per interface cell (fixed point, 2^64 = 1)
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(1024) void k_bubble_fast(KP p, DA d) {
     }
     for (int c = 0; c < 3; ++c) d.phi[3 * j + c] = d.gam[3 * j + c] = d.vacc[3 * j + c] = 0;
   }
-  if (tid == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     d.ledtot[0] += join3(&d.led[0]);
     d.ledtot[1] += join3(&d.led[3]) + fx3_join(s_atm[0], s_atm[1], s_atm[2]);
     d.ledtot[2] += join3(&d.led[6]);
@@ -533,7 +535,7 @@ void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   const unsigned nf = nb < 1024 ? nb : 1024;
   if (!apply_flux) hipLaunchKernelGGL(k_force_full, dim3(1), dim3(1), 0, s, c.d);
   hipLaunchKernelGGL((k_vol_fast<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_bubble_fast, dim3(1), dim3(1024), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_bubble_fast, dim3((unsigned)((c.kp.cap + 255) / 256 < 64 ? (c.kp.cap + 255) / 256 : 64)), dim3(256), 0, s, c.kp, c.d);
   build_bubble_list(c, s);  // also starts the union-find: every listed cell its own root
   hipLaunchKernelGGL((k_ccl_hook<D>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_ccl_accum<P>), dim3(nf), dim3(256), 0, s, c.kp, c.d);

@@ -17,6 +17,10 @@ constexpr uint8_t TMASK = 3, NEARWALL = 4;
 // conversion flag byte (one per cell; zero between steps)
 constexpr uint32_t CF_FILL = 1, CF_EMPTY = 2, CF_NEWI = 4, CF_L2I = 8, CF_ATM = 16,
                    CF_ATMROOT = 32, CF_VALID = 64, CF_MLPOK = 128;
+// interface cell next to a filled or emptied cell (excess redistribution); shares its bit
+// with CF_VALID: it lives only from the excess split to the flag clear at the start of the
+// labelling, and CF_VALID only within a relabelling after that
+constexpr uint32_t CF_EXNB = CF_VALID;
 constexpr int32_t NOLAB = -1;
 
 // status bits raised by kernels
@@ -27,7 +31,7 @@ constexpr int ST_BADLABEL = 8;    // interface cell with an invalid bubble id
 
 // counters
 // C_TOPO: set when this step's conversions may have merged, split or removed a component
-enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_NEXTID, C_NCOUNT = 16 };
+enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_CONV, C_NEXTID, C_NCOUNT = 16 };
 // capacity of the list of filling cells whose neighbourhood the topology test examines
 constexpr int TCAND_CAP = 65536;
 
@@ -150,6 +154,7 @@ struct DA {
   void *rgas, *pbub;
   int32_t *label, *parent;
   int32_t *ilist, *blist, *nilist, *l2ilist;
+  int32_t *clist;             // interface cells that fill or empty this step (sweep appends)
   int32_t *lcnt;              // per-chunk counts / offsets of the list builder [chunks]
   int32_t *bng;               // gas cells of each bubble id [cap]
   uint32_t *wmask;            // static: bit i set when the source x - e_i of the cell is a wall
@@ -351,6 +356,18 @@ __device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y,
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x,               \
                _n = (int64_t)(*(volatile int32_t *)(countptr));                    \
        idx < ((_n + 63) & ~(int64_t)63); idx += (int64_t)gridDim.x * blockDim.x)
+
+// The same over a short list (a few thousand entries), with the entries dealt lane-major
+// over the waves of the grid: lanes of one wave take entries a wave-count apart, so the
+// scattered work spreads over every CU instead of a few full waves, and the atomics of
+// neighbouring cells do not meet in one instruction. Wave-uniform bounds; idx may exceed
+// the count (test it).
+#define SPREAD_LOOP_N(idx, count)                                                              \
+  for (int64_t _T = (int64_t)gridDim.x * blockDim.x, _n = (int64_t)(count), _r0 = 0, idx = 0;    \
+       _r0 < _n && (idx = _r0 + (int64_t)(threadIdx.x & 63) * (_T >> 6) +                      \
+                          (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6), true);       \
+       _r0 += _T)
+#define SPREAD_LOOP(idx, countptr) SPREAD_LOOP_N(idx, *(volatile int32_t *)(countptr))
 
 // ------------------------------------------------------------------ launchers
 // every kernel family is a template over (D, P); the dispatcher picks one instance

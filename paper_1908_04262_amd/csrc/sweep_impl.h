@@ -312,8 +312,8 @@ __device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64
 // what an interface cell stores besides its populations: density, velocity, mass and
 // its fill / empty class (Sec. 2.1)
 template <int D, class R>
-__device__ __forceinline__ void store_interface(const KP &p, DA &d, int64_t n, R rho, R ux, R uy, R uz, R Ms,
-                                                bool hasG, bool hasF) {
+__device__ __forceinline__ uint8_t store_interface(const KP &p, DA &d, int64_t n, R rho, R ux, R uy, R uz, R Ms,
+                                                   bool hasG, bool hasF) {
   ((R *)d.rho)[n] = rho;
   ((R *)d.ux)[n] = ux;
   ((R *)d.uy)[n] = uy;
@@ -327,6 +327,7 @@ __device__ __forceinline__ void store_interface(const KP &p, DA &d, int64_t n, R
     else if (!hasF) cl = CF_EMPTY;
   }
   d.cflag[n] = cl;
+  return cl;
 }
 
 // The whole update of one cell (x, y, z) = n with type byte tb and bubble id lab; lanes
@@ -344,7 +345,7 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
   constexpr int Q = L::Q, Qg = L::Qg;
   const int t = tb & TMASK;
   const bool isI = fluid && t == TI;
-  bool hasgas = false;
+  bool hasgas = false, conv = false;
   R phic = R(0);
 
   if (fluid) {
@@ -373,8 +374,11 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
     for (int i = 0; i < Q; ++i) fout[(int64_t)i * Np + n] = FC::enc(ft[i], i);
 #pragma unroll
     for (int i = 0; i < Qg; ++i) gout[(int64_t)i * Np + n] = GC::enc(gt[i], p);
-    if (isI) store_interface<D, R>(p, d, n, rho, ux, uy, uz, Ms, hasG, hasF);
+    if (isI) conv = (store_interface<D, R>(p, d, n, rho, ux, uy, uz, Ms, hasG, hasF) & (CF_FILL | CF_EMPTY)) != 0;
   }
+  // the cells that fill or empty, listed for the conversion kernels
+  const int slot = wave_append_slot(d.cnt + C_CONV, conv);
+  if (conv) d.clist[slot] = (int32_t)n;
   wave_fx_add_runs(d.phi, hasgas && lab >= 0 && lab < p.cap, lab, fx3((double)phic), d.phi0);
 }
 
