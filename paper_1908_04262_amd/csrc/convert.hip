@@ -277,8 +277,12 @@ __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
   }
 }
 
-// every interface cell of the new types gathers the shares of its converted
-// neighbours in ascending direction order; alpha = M / rho
+// Every interface cell of the new types gathers the shares of its converted neighbours in
+// ascending direction order; alpha = M / rho. On a step whose conversions leave every
+// bubble as it was (the topology test passed), the same pass adds each interface cell's
+// volume share 1 - alpha to its bubble (fixed point; the gas cells are counted apart),
+// and it clears the conversion flags of the cells it visits (the converted cells, whose
+// flags its neighbours read here, are cleared by the next pass).
 template <int D, int P>
 __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
   using R = typename Prec<P>::R;
@@ -286,23 +290,47 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
   const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
+  const bool fast = !*(volatile int32_t *)(d.cnt + C_TOPO);
   const int64_t total = (int64_t)nI + nNI + nL;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
        k += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-    const uint8_t cl = d.cflag[n];
-    if (k < nI && (cl & (CF_FILL | CF_EMPTY))) continue;
-    R acc = ((const R *)d.M)[n];
-    if (cl & CF_EXNB) {  // next to a converted cell
-      int x, y, z;
-      cell_xyz(p, n, x, y, z);
-      for (int i = 1; i < L::Q; ++i) {
-        const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
-        if (d.cflag[yy] & (CF_FILL | CF_EMPTY)) acc = acc + ((const R *)d.exc)[yy];
+    bool act = false;
+    int lab = 0;
+    Fx3 v = {0, 0, 0};
+    if (k < total) {
+      const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
+      const uint8_t cl = d.cflag[n];
+      if (!(k < nI && (cl & (CF_FILL | CF_EMPTY)))) {
+        R acc = ((const R *)d.M)[n];
+        if (cl & CF_EXNB) {  // next to a converted cell
+          int x, y, z;
+          cell_xyz(p, n, x, y, z);
+          for (int i = 1; i < L::Q; ++i) {
+            const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+            if (d.cflag[yy] & (CF_FILL | CF_EMPTY)) acc = acc + ((const R *)d.exc)[yy];
+          }
+        }
+        const R al = acc / ((const R *)d.rho)[n];
+        ((R *)d.M)[n] = acc;
+        ((R *)d.alpha)[n] = al;
+        d.cflag[n] = 0;
+        if (fast) {
+          lab = d.label[n];
+          if (lab > 0 && lab < p.cap) {
+            act = true;
+            v = fx3((double)(R(1) - al));
+          }
+        }
       }
     }
-    ((R *)d.M)[n] = acc;
-    ((R *)d.alpha)[n] = acc / ((const R *)d.rho)[n];
+    if (fast) wave_fx_add_runs(d.vacc, act, lab, v);
+  }
+}
+
+// the flags of the cells that filled or emptied
+__global__ __launch_bounds__(256) void k_conv_clear(DA d) {
+  SPREAD_LOOP(k, d.cnt + C_CONV) {
+    if (k < *(volatile int32_t *)(d.cnt + C_CONV)) d.cflag[d.clist[k]] = 0;
   }
 }
 
@@ -489,6 +517,7 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL((k_ni_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL(k_conv_clear, dim3(nb), dim3(256), 0, s, c.d);
 }
 
 #define MF_INST(D, P) template void Ops<D, P>::convert(Ctx &, hipStream_t);

@@ -457,39 +457,9 @@ void recount_gas(const Ctx &c, hipStream_t s) {
 // ------------------------------------------------------------------ fast path
 // Steps whose conversions cannot have changed any component (C_TOPO clear) keep every
 // id; each bubble then holds all of its gas, and only its volume and pressure change.
-// The sums are the same fixed-point sums as the full path's, so the results are
+// The volume is its gas-cell count plus the interface shares 1 - alpha summed by the
+// excess pass: the same fixed-point sums as the full path's, so the results are
 // identical to what the full labelling would give.
-// Also clears the conversion flags of this step's list cells, on every step.
-template <int P>
-__global__ __launch_bounds__(256) void k_vol_fast(KP p, DA d) {
-  using R = typename Prec<P>::R;
-  const bool fast = !*(volatile int32_t *)(d.cnt + C_TOPO);
-  // the interface cells after the conversions: old ones that stayed, new ones from gas
-  // and from liquid; the gas cells of each bubble are counted (bng)
-  const int nI = *(volatile int32_t *)(d.cnt + C_I);
-  const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
-  const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
-  const int64_t total = (int64_t)nI + nNI + nL;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
-       k += (int64_t)gridDim.x * blockDim.x) {
-    bool act = false;
-    int lab = 0;
-    Fx3 v = {0, 0, 0};
-    if (k < total) {
-      const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
-      d.cflag[n] = 0;
-      if (fast && (d.type[n] & TMASK) == TI) {
-        lab = d.label[n];
-        if (lab > 0 && lab < p.cap) {
-          act = true;
-          v = fx3((double)(R(1) - ((const R *)d.alpha)[n]));
-        }
-      }
-    }
-    if (fast) wave_fx_add_runs(d.vacc, act, lab, v);
-  }
-}
-
 // Several work-groups over the ids; the first also folds the atmosphere's terms and the
 // step's ledgers into the running totals.
 __global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
@@ -534,7 +504,6 @@ void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   // launches cheap, and their grid-stride loops cover the list when they do run
   const unsigned nf = nb < 1024 ? nb : 1024;
   if (!apply_flux) hipLaunchKernelGGL(k_force_full, dim3(1), dim3(1), 0, s, c.d);
-  hipLaunchKernelGGL((k_vol_fast<P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_bubble_fast, dim3((unsigned)((c.kp.cap + 255) / 256 < 64 ? (c.kp.cap + 255) / 256 : 64)), dim3(256), 0, s, c.kp, c.d);
   build_bubble_list(c, s);  // also starts the union-find: every listed cell its own root
   hipLaunchKernelGGL((k_ccl_hook<D>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
