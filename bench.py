@@ -14,6 +14,11 @@ A third measurement covers the batched ensemble (48 independent domains of 64^3 
 binary16 storage, learned curvature): MLUPS over all domains stepped one after another,
 and with the tuned bulk sweep and one graph launch per two steps of all domains.
 
+The roofline entry is the bulk sweep kernel: algorithmic bytes per launch over its
+average duration inside the timed steps, measured with events on its stream; there it
+shares the GPU with the previous step's labelling and geometry, which run on a second
+stream. ``roofline.isolated`` times the same kernel launched alone, back to back.
+
 Prints one JSON line. Options: --gpus N (only 1), --steps K, --warmup W,
 --workload NAME, --no-cpu-baseline, --mlp-train N, --mlp-epochs E, --no-ensemble,
 --ensemble-steps S.
@@ -145,6 +150,10 @@ def run_one(wl, steps, warmup, log, net=None):
     sim.profile(False)
     T1 = sim.read("type")
     bytes1, np1, _ = sweep_bytes(wl, T1, wl["precision"])
+    # the bulk kernel alone (back-to-back launches on the final state, nothing beside it):
+    # inside the step it shares the GPU with the previous step's labelling and geometry
+    _, tune_ms = sim.tune(20)
+    iso_ms = float(tune_ms[1 if wl["precision"] == "fp32" else 0])
     led = sim.ledgers()
     ncell = int(np.prod(sim.shape))
     wall = t2 - t1
@@ -161,6 +170,8 @@ def run_one(wl, steps, warmup, log, net=None):
         step_event_ms=step_ms / max(nst, 1),
         bulk_sweep_bytes=bytes_launch,
         bulk_sweep_gbs=bytes_launch / bulk_avg_s / 1e9,
+        bulk_isolated_ms=iso_ms,
+        bulk_isolated_gbs=bytes1 / (iso_ms / 1e3) / 1e9 if iso_ms > 0 else None,
         bytes_per_fluid_cell=per_cell,
         n_plain=0.5 * (np0 + np1),
         n_fluid=n_fluid,
@@ -335,6 +346,9 @@ def main():
             "traffic": measured_traffic("k_sweep_vec<3,4,4,256>"),
             "bytes_per_launch": r16["bulk_sweep_bytes"],
             "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
+            "isolated": {"achieved": round(r16["bulk_isolated_gbs"], 1),
+                         "frac": round(r16["bulk_isolated_gbs"] / HBM_PEAK_GBS, 4),
+                         "avg_launch_ms": round(r16["bulk_isolated_ms"], 4)},
         },
         "batched_ensemble": ens,
         "cpu_baseline": cpu,

@@ -164,7 +164,10 @@ int mf_nucleate(mf_ctx *ctx, int32_t n, const double *centers, const double *rad
 /* Advance nsteps time steps (enqueued on the context stream; returns without waiting).
  * Each step: stream / collide f and g, interface mass exchange, Henry's-law and
  * free-surface reconstruction, cell conversion with excess redistribution, bubble
- * labelling and gas bookkeeping, bubble pressures, curvature, disjoining pressure. */
+ * labelling and gas bookkeeping, bubble pressures, curvature, disjoining pressure.
+ * The labelling and geometry of a step run on a stream of the context's own, beside the
+ * next step's bulk sweep; all work is joined into the context stream before mf_step
+ * returns. */
 int mf_step(mf_ctx *ctx, int32_t nsteps);
 
 /* Wait for the context stream and report device status (MF_ENUMERIC / MF_ECAPACITY
@@ -255,8 +258,9 @@ int mf_attach_mlp(mf_ctx *ctx, const mf_mlp *m);
 /* Time spent in a kernel group over the steps since mf_profile_enable(ctx, 1), in
  * milliseconds (total) with the number of steps timed, measured with HIP events on the
  * context stream: group 0 = the bulk lattice sweep kernel (the whole sweep on domains
- * that use the per-cell kernel), 1 = whole step, 2 = the interface-cell sweep kernel
- * (zero on domains that use the per-cell kernel). At most 4096 steps are timed
+ * that use the per-cell kernel), 1 = whole step (from its list build to the end of its
+ * labelling and geometry, which overlap the next step), 2 = the interface-cell sweep
+ * kernel (zero on domains that use the per-cell kernel). At most 4096 steps are timed
  * per enable; a further mf_step returns MF_ESTATE until the next enable. */
 int mf_profile_enable(mf_ctx *ctx, int32_t on);
 int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launches);

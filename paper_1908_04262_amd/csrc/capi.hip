@@ -24,7 +24,7 @@ namespace {
 std::string &g_err = mf::g_thread_err;
 
 struct OpsTable {
-  void (*sweep)(Ctx &, hipStream_t, hipEvent_t);
+  void (*sweep)(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
   void (*convert)(Ctx &, hipStream_t);
   void (*label)(Ctx &, hipStream_t, int);
   void (*geometry)(Ctx &, hipStream_t);
@@ -98,15 +98,17 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   for (void **a : rarr) *a = cv.take<void>(Np * rb);
   d.label = cv.take<int32_t>(Np * 4);
   d.parent = cv.take<int32_t>(Np * 4);
-  d.ilist = cv.take<int32_t>(Np * 4);
+  d.ilist = cv.take<int32_t>(2 * Np * 4);  // two copies, alternating by step parity
   d.blist = cv.take<int32_t>(Np * 4);
   d.nilist = cv.take<int32_t>(Np * 4);
   d.l2ilist = cv.take<int32_t>(Np * 4);
   d.clist = cv.take<int32_t>(Np * 4);
   d.wmask = cv.take<uint32_t>(Np * 4);
   d.lcnt = cv.take<int32_t>((size_t)list_blocks_of(kp) * 4);
+  d.lcnt_b = cv.take<int32_t>((size_t)list_blocks_of(kp) * 4);
   d.sword = P.curvature == MF_CURV_MLP ? cv.take<uint32_t>(Np * 4) : nullptr;
-  d.cnt = cv.take<int32_t>(C_NCOUNT * 4);
+  d.cnt = cv.take<int32_t>(2 * C_NCOUNT * 4);  // two sets, alternating by step parity
+  d.nextid = cv.take<int32_t>(4);
   d.status = cv.take<int32_t>(4);
   const size_t cap = (size_t)kp.cap;
   d.bm = cv.take<double>(cap * 8);
@@ -221,7 +223,7 @@ KP make_kp(const mf_params &P) {
 
 __global__ void k_reset_counters(DA d) {
   const int t = threadIdx.x;
-  if (t < C_NEXTID) d.cnt[t] = 0;
+  if (t < C_NCOUNT) d.cnt[t] = 0;
 }
 
 __global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v) {
@@ -243,10 +245,17 @@ int device_status(Ctx *c) {
 
 void reset_counters(Ctx *c) { hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, c->d); }
 
+// the counter set and interface list of the current step parity
+void select_parity(Ctx *c) {
+  c->d.cnt = c->cnt_base + C_NCOUNT * c->parity;
+  c->d.ilist = c->ilist_base + (size_t)c->kp.Np * c->parity;
+}
+
 // per-step event pairs when profiling
+constexpr int kStepEvents = 6;
 struct Prof {
-  std::vector<hipEvent_t> ev;  // 5 per step: step start, sweep start, bulk sweep end,
-                               // interface sweep end, step end
+  std::vector<hipEvent_t> ev;  // per step: step start, sweep start, bulk sweep end,
+                               // interface sweep start, interface sweep end, step end
   size_t used = 0;
 };
 
@@ -256,6 +265,25 @@ struct mf_ctx : Ctx {
   OpsTable ops;
   Prof prof_ev;
 };
+
+static void destroy_side(mf_ctx *c) {
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->ev_conv) (void)hipEventDestroy(c->ev_conv);
+  if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  c->side = nullptr;
+  c->ev_conv = c->ev_side = nullptr;
+}
+
+// the context stream waits for the labelling and geometry the last step left running on
+// the side stream
+static void join_side(mf_ctx *c) {
+  if (!c->side_pending) return;
+  (void)hipStreamWaitEvent(c->stream, c->ev_side, 0);
+  c->side_pending = false;
+}
+
+static void join_side_cb(void *arg) { join_side((mf_ctx *)arg); }
 
 extern "C" {
 
@@ -310,6 +338,21 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
   char *base = (char *)(((uintptr_t)c->ws + 255) & ~(uintptr_t)255);
   Carve cv(base);
   layout(*p, c->kp, cv, c->d);
+  c->cnt_base = c->d.cnt;
+  c->ilist_base = c->d.ilist;
+  {
+    // default priority, not synchronising with the legacy default stream
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_conv, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      g_err = std::string("creating the side stream failed: ") + hipGetErrorString(e);
+      destroy_side(c);
+      if (c->own_ws) (void)hipFree(c->ws);
+      delete c;
+      return MF_EHIP;
+    }
+  }
   // zero everything, then the "empty" markers of the hash tables
   {
     size_t n = cv.off;
@@ -327,11 +370,12 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
     const int32_t next = 1;
     hipError_t e1 = hipMemcpyAsync(c->d.bp, &patm, 8, hipMemcpyHostToDevice, c->stream);
     hipError_t e2 = hipMemcpyAsync(c->d.balive, &one, 4, hipMemcpyHostToDevice, c->stream);
-    hipError_t e3 = hipMemcpyAsync(c->d.cnt + C_NEXTID, &next, 4, hipMemcpyHostToDevice, c->stream);
+    hipError_t e3 = hipMemcpyAsync(c->d.nextid, &next, 4, hipMemcpyHostToDevice, c->stream);
     hipError_t e4 = hipStreamSynchronize(c->stream);
     hipError_t e5 = hipGetLastError();
     if (e1 || e2 || e3 || e4 || e5) {
       g_err = std::string("initialisation failed: ") + hipGetErrorString(e4 ? e4 : (e5 ? e5 : e1));
+      destroy_side(c);
       if (c->own_ws) (void)hipFree(c->ws);
       delete c;
       return MF_EHIP;
@@ -348,6 +392,7 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
 int mf_destroy(mf_ctx *c) {
   if (!c) return MF_OK;
   (void)hipStreamSynchronize(c->stream);
+  destroy_side(c);
   for (hipEvent_t e : c->prof_ev.ev) (void)hipEventDestroy(e);
   if (c->mlp_buf) (void)hipFree(c->mlp_buf);
   if (c->own_ws) (void)hipFree(c->ws);
@@ -379,7 +424,7 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
   HIPCHK(c, hipMalloc(&p0d, sizeof(double) * (n > 0 ? n : 1)));
   HIPCHK(c, hipMemcpyAsync(c->d.balive, alive.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
   const int32_t next = n + 1;
-  HIPCHK(c, hipMemcpyAsync(c->d.cnt + C_NEXTID, &next, 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d.nextid, &next, 4, hipMemcpyHostToDevice, c->stream));
   if (n > 0) HIPCHK(c, hipMemcpyAsync(p0d, p0, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
@@ -394,19 +439,39 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 }
 
 // one time step, enqueued on the context stream (host work: launches only, so that it
-// can be captured into a graph); ev: five profiling events or NULL
-static void step_once(mf_ctx *c, hipEvent_t *ev) {
+// can be captured into a graph); ev: kStepEvents profiling events or NULL.
+// With overlap, the labelling and geometry of the step go to the side stream, where they
+// run beside the list build and bulk sweep of the next step. Those read only cell types,
+// populations and the wall mask, which labelling and geometry leave alone, and write the
+// populations and this step parity's counters and interface list; the interface sweep,
+// the first kernel that reads labels, bubble pressures and curvature, waits for the side
+// stream. The caller joins what the last step left running (join_side) before anything
+// else touches the state. Graph capture takes the plain order: there the domains already
+// run as parallel branches.
+static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
+  c->parity ^= 1;
+  select_parity(c);
   if (ev) (void)hipEventRecord(ev[0], c->stream);
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
   if (ev) (void)hipEventRecord(ev[1], c->stream);
-  c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr);
-  if (ev) (void)hipEventRecord(ev[3], c->stream);
+  c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, &join_side_cb, c);
+  if (ev) (void)hipEventRecord(ev[4], c->stream);
   c->cur ^= 1;
   c->ops.convert(*c, c->stream);
-  c->ops.label(*c, c->stream, 1);
-  c->ops.geometry(*c, c->stream);
-  if (ev) (void)hipEventRecord(ev[4], c->stream);
+  if (overlap) {
+    (void)hipEventRecord(c->ev_conv, c->stream);
+    (void)hipStreamWaitEvent(c->side, c->ev_conv, 0);
+    c->ops.label(*c, c->side, 1);
+    c->ops.geometry(*c, c->side);
+    if (ev) (void)hipEventRecord(ev[5], c->side);
+    (void)hipEventRecord(c->ev_side, c->side);
+    c->side_pending = true;
+  } else {
+    c->ops.label(*c, c->stream, 1);
+    c->ops.geometry(*c, c->stream);
+    if (ev) (void)hipEventRecord(ev[5], c->stream);
+  }
   c->step++;
 }
 
@@ -418,15 +483,17 @@ int mf_step(mf_ctx *c, int32_t nsteps) {
   for (int k = 0; k < nsteps; k++) {
     hipEvent_t *ev = nullptr;
     if (c->prof) {
-      if (c->prof_ev.used + 5 > c->prof_ev.ev.size()) {
+      if (c->prof_ev.used + kStepEvents > c->prof_ev.ev.size()) {
         c->err = "profiling event pool exhausted; call mf_profile_get";
+        join_side(c);
         return MF_ESTATE;
       }
       ev = &c->prof_ev.ev[c->prof_ev.used];
-      c->prof_ev.used += 5;
+      c->prof_ev.used += kStepEvents;
     }
-    step_once(c, ev);
+    step_once(c, ev, true);
   }
+  join_side(c);
   c->stepped = c->stepped || nsteps > 0;
   HIPCHK(c, hipGetLastError());
   return MF_OK;
@@ -559,11 +626,11 @@ int mf_set_bubble(mf_ctx *c, int32_t id, double gas_mass, double volume, double 
   c->gas_dirty = true;
   c->epoch++;
   int32_t next = 0;
-  HIPCHK(c, hipMemcpyAsync(&next, c->d.cnt + C_NEXTID, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&next, c->d.nextid, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (id + 1 > next) {
     next = id + 1;
-    HIPCHK(c, hipMemcpyAsync(c->d.cnt + C_NEXTID, &next, 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d.nextid, &next, 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return MF_OK;
@@ -612,18 +679,19 @@ int mf_read_bubbles(mf_ctx *c, mf_bubble *dst, int32_t capacity, int32_t *n_out)
 int mf_totals_get(mf_ctx *c, mf_totals *out) {
   if (!c || !out) return MF_EINVAL;
   __int128 led[3];
-  int32_t cnt[C_NCOUNT], st = 0;
+  int32_t cnt[C_NCOUNT], st = 0, next = 0;
   std::vector<int32_t> al(c->kp.cap);
   HIPCHK(c, hipMemcpyAsync(led, c->d.ledtot, sizeof led, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&st, c->d.status, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&next, c->d.nextid, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(al.data(), c->d.balive, 4 * c->kp.cap, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out->step = c->step;
   out->lost_liquid = (double)led[0] * 0x1p-64;
   out->atm_gas = (double)led[1] * 0x1p-64;
   out->collapsed_gas = (double)led[2] * 0x1p-64;
-  out->next_id = cnt[C_NEXTID];
+  out->next_id = next;
   int nb = 0;
   for (int i = 1; i < c->kp.cap; i++) nb += al[i] ? 1 : 0;
   out->n_bubbles = nb;
@@ -653,7 +721,7 @@ int mf_profile_enable(mf_ctx *c, int32_t on) {
   if (!c) return MF_EINVAL;
   c->prof = on != 0;
   if (c->prof && c->prof_ev.ev.empty()) {
-    c->prof_ev.ev.resize(5 * 4096);
+    c->prof_ev.ev.resize(kStepEvents * 4096);
     for (auto &e : c->prof_ev.ev) HIPCHK(c, hipEventCreate(&e));
   }
   c->prof_ev.used = 0;
@@ -666,8 +734,8 @@ int mf_profile_get(mf_ctx *c, int32_t group, double *ms_total, int64_t *launches
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double tot = 0.0;
   int64_t nl = 0;
-  static const int from[3] = {1, 0, 2}, to[3] = {2, 4, 3};
-  for (size_t k = 0; k + 5 <= c->prof_ev.used; k += 5) {
+  static const int from[3] = {1, 0, 3}, to[3] = {2, 5, 4};
+  for (size_t k = 0; k + kStepEvents <= c->prof_ev.used; k += kStepEvents) {
     float ms = 0.0f;
     hipEvent_t a = c->prof_ev.ev[k + from[group]];
     hipEvent_t b = c->prof_ev.ev[k + to[group]];
@@ -691,7 +759,7 @@ struct mf_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<uint64_t> epoch;          // context epochs and buffer parities at capture
-  std::vector<int> cur;
+  std::vector<int> cur, par;
 };
 
 static void batch_drop_graph(mf_batch *b) {
@@ -763,8 +831,8 @@ static hipError_t batch_capture(mf_batch *b) {
     (void)hipStreamWaitEvent(b->ss[i], b->ev_fork, 0);
     hipStream_t own = c->stream;
     c->stream = b->ss[i];
-    step_once(c, nullptr);
-    step_once(c, nullptr);
+    step_once(c, nullptr, false);
+    step_once(c, nullptr, false);
     c->stream = own;
     c->step -= 2;  // counted when the graph runs
     (void)hipEventRecord(b->ev_join[i], b->ss[i]);
@@ -784,9 +852,11 @@ static hipError_t batch_capture(mf_batch *b) {
   }
   b->epoch.resize(b->ctx.size());
   b->cur.resize(b->ctx.size());
+  b->par.resize(b->ctx.size());
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     b->epoch[i] = b->ctx[i]->epoch;
     b->cur[i] = b->ctx[i]->cur;
+    b->par[i] = b->ctx[i]->parity;
   }
   return hipSuccess;
 }
@@ -800,7 +870,7 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
   // a graph captured before a state change made outside the time step is rebuilt
   bool stale = b->exec == nullptr;
   for (size_t i = 0; i < b->ctx.size() && !stale; ++i)
-    stale = b->epoch[i] != b->ctx[i]->epoch || b->cur[i] != b->ctx[i]->cur;
+    stale = b->epoch[i] != b->ctx[i]->epoch || b->cur[i] != b->ctx[i]->cur || b->par[i] != b->ctx[i]->parity;
   if (stale && b->exec) batch_drop_graph(b);
   // the batch waits for the work already queued on the domains' own streams
   for (size_t i = 0; i < b->ctx.size(); ++i) {
@@ -825,7 +895,7 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
       hipStream_t own = c->stream;
       c->stream = b->sb;
       if (c->gas_dirty) c->ops.geometry(*c, c->stream);
-      step_once(c, nullptr);
+      step_once(c, nullptr, false);
       c->stream = own;
     }
   }

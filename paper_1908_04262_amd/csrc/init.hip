@@ -258,6 +258,10 @@ __device__ __forceinline__ int block_scan(int &si) {
   return tot;
 }
 
+// each list has its own chunk counts: the bubble list is built while the next step's
+// interface list may be under construction
+template <int WHICH> __device__ __forceinline__ int32_t *list_counts(const DA &d) { return WHICH == 0 ? d.lcnt : d.lcnt_b; }
+
 template <int WHICH> __device__ __forceinline__ bool list_skipped(const DA &d) {
   return WHICH == 1 && !*(volatile int32_t *)(d.cnt + C_TOPO);
 }
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(256) void k_list_count(KP p, DA d, int nchunks) {
     const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
     int si = __popcll(list_mask<WHICH>(p, d, c0));
     const int tot = block_scan(si);
-    if (threadIdx.x == 0) d.lcnt[ch] = tot;
+    if (threadIdx.x == 0) list_counts<WHICH>(d)[ch] = tot;
   }
 }
 
@@ -281,8 +285,9 @@ __global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int per = (nchunks + 1023) / 1024;
   const int b0 = threadIdx.x * per;
+  int32_t *lc = list_counts<WHICH>(d);
   int si = 0;
-  for (int k = 0; k < per && b0 + k < nchunks; ++k) si += d.lcnt[b0 + k];
+  for (int k = 0; k < per && b0 + k < nchunks; ++k) si += lc[b0 + k];
   const int ci = si;
   for (int o = 1; o < 64; o <<= 1) {
     const int a = __shfl_up(si, o);
@@ -296,8 +301,8 @@ __global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
     ti += s_w[k];
   }
   for (int k = 0; k < per && b0 + k < nchunks; ++k) {
-    const int a = d.lcnt[b0 + k];
-    d.lcnt[b0 + k] = oi;
+    const int a = lc[b0 + k];
+    lc[b0 + k] = oi;
     oi += a;
   }
   if (threadIdx.x == 0) d.cnt[WHICH == 0 ? C_I : C_B] = ti;
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
     const int ci = __popcll(mk);
     int si = ci;
     block_scan(si);
-    int o = d.lcnt[ch] + si - ci;
+    int o = list_counts<WHICH>(d)[ch] + si - ci;
     while (mk) {
       const int b = __ffsll((long long)mk) - 1;
       mk &= mk - 1;

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
   int ne = *(volatile int32_t *)(d.cnt + C_ENTRIES);
   if (ne > p.ecap) ne = p.ecap;
   // ids are never reused, so every id in use is below the id counter
-  int jmax = *(volatile int32_t *)(d.cnt + C_NEXTID);
+  int jmax = *(volatile int32_t *)d.nextid;
   if (jmax > cap) jmax = cap;
   if (tid == 0) {
     s_ncont = 0;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
       while (b >= 0 && d.rh_key[d.contested[b]] > d.rh_key[sv]) { d.contested[b + 1] = d.contested[b]; --b; }
       d.contested[b + 1] = sv;
     }
-    int next_id = d.cnt[C_NEXTID];
+    int next_id = *d.nextid;
     for (int a = 0; a < nc; ++a) {
       const int s = d.contested[a];
       const int32_t root = d.rh_key[s];
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
       write_bubble(p, d, id, m, vk);
       d.label[root] = id;
     }
-    d.cnt[C_NEXTID] = next_id;
+    *d.nextid = next_id;
     d.cnt[C_CONTESTED] = nc;
   }
   __syncthreads();
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
   if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
   const int tid = threadIdx.x;
   __shared__ long long s_atm[3];
-  int jmax = *(volatile int32_t *)(d.cnt + C_NEXTID);
+  int jmax = *(volatile int32_t *)d.nextid;
   if (jmax > p.cap) jmax = p.cap;
   if (blockIdx.x == 0 && tid < 64) {
     long long sa[3];

@@ -31,7 +31,8 @@ constexpr int ST_BADLABEL = 8;    // interface cell with an invalid bubble id
 
 // counters
 // C_TOPO: set when this step's conversions may have merged, split or removed a component
-enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_CONV, C_NEXTID, C_NCOUNT = 16 };
+// per-step counters (all cleared at the start of a step)
+enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_CONV, C_NCOUNT = 16 };
 // capacity of the list of filling cells whose neighbourhood the topology test examines
 constexpr int TCAND_CAP = 65536;
 
@@ -156,6 +157,8 @@ struct DA {
   int32_t *ilist, *blist, *nilist, *l2ilist;
   int32_t *clist;             // interface cells that fill or empty this step (sweep appends)
   int32_t *lcnt;              // per-chunk counts / offsets of the list builder [chunks]
+  int32_t *lcnt_b;            // the same for the bubble list (built on the side stream)
+  int32_t *nextid;            // next unused bubble id (persistent)
   int32_t *bng;               // gas cells of each bubble id [cap]
   uint32_t *wmask;            // static: bit i set when the source x - e_i of the cell is a wall
   int32_t *cnt;
@@ -373,9 +376,13 @@ __device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y,
 // every kernel family is a template over (D, P); the dispatcher picks one instance
 struct Ctx;
 template <int D, int P> struct Ops {
-  // the lattice sweep; with mid != NULL, the event is recorded between the bulk kernel
-  // and the interface / near-wall kernel
-  static void sweep(Ctx &c, hipStream_t s, hipEvent_t mid);
+  // the lattice sweep: the bulk kernel, then between(arg) (host code that may enqueue
+  // more work on s), then the interface / near-wall kernel, the first one that reads the
+  // labels and geometry; the events (each may be NULL) are recorded at the end of the bulk
+  // kernel and at the start of the interface kernel. Domains swept by the per-cell kernel
+  // run between(arg) first and record both events after that kernel.
+  static void sweep(Ctx &c, hipStream_t s, hipEvent_t bulk_end, hipEvent_t special_start,
+                    void (*between)(void *), void *arg);
   // one launch of the bulk sweep kernel in tuning variant v (see kSweepVariants); false
   // when the variant does not apply to this domain (nothing launched)
   static bool sweep_bulk(Ctx &c, hipStream_t s, int v);
@@ -408,6 +415,15 @@ struct Ctx {
   std::string err;
   bool prof = false;
   void *mlp_buf = nullptr;  // device copy of the attached network's weights
+  // Steps overlap: the labelling and geometry of step n run on the side stream while the
+  // main stream builds the lists and runs the bulk sweep of step n+1 (neither reads what
+  // the other writes); the interface sweep of step n+1 waits for ev_side. Counters and
+  // the interface list alternate between two copies by step parity.
+  int32_t *cnt_base = nullptr, *ilist_base = nullptr;
+  int parity = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_conv = nullptr, ev_side = nullptr;
+  bool side_pending = false;  // ev_side marks side-stream work the main stream has not joined
 };
 
 // every (dimension, precision) instance the library is built with

@@ -674,19 +674,24 @@ bool Ops<D, P>::sweep_bulk(Ctx &c, hipStream_t s, int variant) {
 }
 
 template <int D, int P>
-void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t mid) {
+void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t bulk_end, hipEvent_t special_start,
+                      void (*between)(void *), void *arg) {
   if constexpr (P != 0) {
     const int v = c.sweep_variant >= 0 ? c.sweep_variant : default_variant<P>();
     if (sweep_bulk(c, s, v) || (v != default_variant<P>() && sweep_bulk(c, s, default_variant<P>()))) {
-      if (mid) (void)hipEventRecord(mid, s);
+      if (bulk_end) (void)hipEventRecord(bulk_end, s);
+      if (between) between(arg);
+      if (special_start) (void)hipEventRecord(special_start, s);
       hipLaunchKernelGGL((k_sweep_special<D, P>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
       return;
     }
   }
   const int gx = (c.kp.nx + 63) / 64, gy = (c.kp.ny + 3) / 4;
   const int64_t nb = (int64_t)gx * gy * c.kp.nz;
+  if (between) between(arg);
   hipLaunchKernelGGL((k_sweep<D, P>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
-  if (mid) (void)hipEventRecord(mid, s);
+  if (bulk_end) (void)hipEventRecord(bulk_end, s);
+  if (special_start) (void)hipEventRecord(special_start, s);
 }
 
 }  // namespace mf
