@@ -22,7 +22,9 @@
  *   S3  stream g (Eq. diffusion) with the Henry's-law rebuild (Eqs. henryslaw,
  *       reconstructdiffusion) and the gas ledger that feeds the bubbles;
  *   S4  moments (Sec. 2), BGK collision (Eqs. collision, equilibrium) with tau from
- *       Eq. tau or the power-law limit of Eq. carreauTau; ADE collision (Eq. diffusion);
+ *       Eq. tau or the power-law limit of Eq. carreauTau, and the external force term of
+ *       Eq. collision in the scheme of Guo, Zheng and Shi (2002); ADE collision
+ *       (Eq. diffusion);
  *   S5-S7 cell-type conversion and excess-mass redistribution (Sec. 2.1, last paragraph);
  *   S8  bubble labelling by flood fill with merge/split bookkeeping (Sec. 3.5);
  *   S9  ideal-gas bubble pressure (Eq. idealgas);
@@ -60,6 +62,7 @@ typedef struct {
   int32_t max_ids;   /* capacity of the bubble table (ids 0..max_ids-1) */
   double tau, D, sigma, kH, RT, k_pi, d_max, p_atm, q, eps, S0;
   double pl_n, pl_nu_ref, pl_gdot_ref, tau_min, tau_max;
+  double accel[3]; /* body-force acceleration a (gravity); 0: no force term */
 } or_params;
 
 typedef struct {
@@ -70,6 +73,7 @@ typedef struct {
   int ex[19], ey[19], ez[19], opp[19];
   double w[19], wg[7];
   double kg;      /* 1/c_s^2 of the ADE lattice */
+  int force;      /* a != 0 */
   double omega_g; /* 1/tau_g */
   uint8_t *T;
   double *fc, *gc; /* post-collision populations [Q][N], [Qg][N] */
@@ -185,6 +189,21 @@ static double geq(const OS *s, int i, double c, double ux, double uy, double uz)
   return (s->wg[i] * c) * (1.0 + s->kg * eu);
 }
 
+/* Force term of Eq. collision for an acceleration a, written out in the form of Guo,
+ * Zheng and Shi (2002), the reading taken of the paper's garbled formula and sign:
+ * F_i = w_i rho [ (e_i - u) / c_s^2 + (e_i . u) e_i / c_s^4 ] . a, added after the BGK
+ * relaxation with the factor (1 - omega / 2), and u = (sum f e + rho a / 2) / rho.
+ * Moments: sum F_i = 0 and sum F_i e_i = rho a, so the momentum of a cell grows by
+ * exactly rho a per step whatever omega is (pinned on a periodic box), and a channel
+ * between walls reaches the parabolic (Newtonian) or power-law profile (pinned). */
+static double force_i(const OS *s, int i, double rho, double ux, double uy, double uz) {
+  const double *a = s->P.accel;
+  double ea = ((s->ex[i] * a[0] + s->ey[i] * a[1]) + s->ez[i] * a[2]);
+  double ua = ((ux * a[0] + uy * a[1]) + uz * a[2]);
+  double eu = ((s->ex[i] * ux + s->ey[i] * uy) + s->ez[i] * uz);
+  return (rho * s->w[i]) * (3.0 * (ea - ua) + (9.0 * eu) * ea);
+}
+
 /* moments of a population vector: rho = sum f_i, u = (sum f_i e_i) / rho (Sec. 2) */
 static void moments(const OS *s, const double *f, double *rho, double *ux, double *uy, double *uz) {
   double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -244,8 +263,15 @@ double or_powerlaw_tau_iter(const or_params *P, double rho, double pn, int iters
   return powerlaw_tau_iter(P, rho, pn, iters);
 }
 
-/* Frobenius norm of the non-equilibrium momentum flux Pi_neq = sum e e (f - feq) */
-static double pineq_norm(const OS *s, const double *ft, const double *fe) {
+/* Frobenius norm of the non-equilibrium momentum flux Pi_neq = sum e e (f - feq).
+ * With a body force F = rho a (Guo et al. 2002) the flux that measures the strain rate is
+ * Pi_neq + (u F + F u) / 2: in a uniformly accelerated box, where the strain rate is
+ * zero, the pre-collision populations carry Pi_neq = -(u F + F u) / 2 (the steady
+ * non-equilibrium part is minus half the force term). Pinned by that box (the power law
+ * then relaxes at its zero-shear clamp) and by body-force-driven power-law channel flow
+ * against its closed form. */
+static double pineq_norm(const OS *s, const double *ft, const double *fe, double rho, double ux, double uy,
+                         double uz) {
   double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
   int i;
   for (i = 0; i < s->Q; i++) {
@@ -256,6 +282,15 @@ static double pineq_norm(const OS *s, const double *ft, const double *fe) {
     pxy = pxy + (double)(s->ex[i] * s->ey[i]) * d;
     pxz = pxz + (double)(s->ex[i] * s->ez[i]) * d;
     pyz = pyz + (double)(s->ey[i] * s->ez[i]) * d;
+  }
+  if (s->force) {
+    double Fx = rho * s->P.accel[0], Fy = rho * s->P.accel[1], Fz = rho * s->P.accel[2];
+    pxx = pxx + ux * Fx;
+    pyy = pyy + uy * Fy;
+    pzz = pzz + uz * Fz;
+    pxy = pxy + 0.5 * (ux * Fy + uy * Fx);
+    pxz = pxz + 0.5 * (ux * Fz + uz * Fx);
+    pyz = pyz + 0.5 * (uy * Fz + uz * Fy);
   }
   double ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + 2.0 * ((pxy * pxy + pxz * pxz) + pyz * pyz);
   return sqrt(ss);
@@ -817,6 +852,8 @@ void *or_create(const or_params *P) {
   s->N = (int64_t)s->nx * s->ny * s->nz;
   set_lattice(s);
   s->omega_g = 1.0 / (0.5 + s->kg * P->D); /* D = c_s^2 (tau_g - 1/2), Eq. diffusionconst */
+  if (s->D == 2) s->P.accel[2] = 0.0; /* a plane flow has no third component */
+  s->force = s->P.accel[0] != 0.0 || s->P.accel[1] != 0.0 || s->P.accel[2] != 0.0;
   int64_t N = s->N;
   s->T = calloc(N, 1);
   s->fc = calloc(N * s->Q, sizeof(double));
@@ -1056,10 +1093,18 @@ static int step_once(OS *s) {
     /* S4 */
     double rho, ux, uy, uz;
     moments(s, ft, &rho, &ux, &uy, &uz);
+    if (s->force) {
+      /* velocity of the forced scheme: (sum f e + F / 2) / rho with F = rho a */
+      ux = ux + 0.5 * P->accel[0];
+      uy = uy + 0.5 * P->accel[1];
+      uz = uz + 0.5 * P->accel[2];
+    }
     for (i = 0; i < Q; i++) fe[i] = feq(s, i, rho, ux, uy, uz);
     double omega = omega_newton;
-    if (P->rheology == 1) omega = 1.0 / or_powerlaw_tau(P, rho, pineq_norm(s, ft, fe));
+    if (P->rheology == 1) omega = 1.0 / or_powerlaw_tau(P, rho, pineq_norm(s, ft, fe, rho, ux, uy, uz));
     for (i = 0; i < Q; i++) fn[(int64_t)i * N + n] = ft[i] - omega * (ft[i] - fe[i]);
+    if (s->force)
+      for (i = 0; i < Q; i++) fn[(int64_t)i * N + n] = fn[(int64_t)i * N + n] + (1.0 - 0.5 * omega) * force_i(s, i, rho, ux, uy, uz);
     double c = 0.0;
     for (i = 0; i < Qg; i++) c = c + gt[i];
     for (i = 0; i < Qg; i++)
