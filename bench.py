@@ -10,6 +10,9 @@ whole-step MLUPS of run (ii); run (i) and the ratio are reported beside it. The 
 of run (ii) is trained on the GPU by the library before the timed region (2M generated
 stencils by default), and its training time and validation error are reported.
 
+The same binary16 + learned-curvature run is repeated under gravity (a body force along
+-z, reported under ``body_force``; the metric's workload itself has none).
+
 A third measurement covers the batched ensemble (48 independent domains of 64^3 to 160^3,
 binary16 storage, learned curvature): MLUPS over all domains stepped one after another,
 and with the tuned bulk sweep and one graph launch per two steps of all domains.
@@ -300,6 +303,10 @@ def main():
     net, train_info = train_net(a.mlp_train, a.mlp_epochs, log)
     r16 = run_one(dict(wl, precision="f16s_g16", curvature="mlp"), a.steps, a.warmup, log, net=net)
     r16f = run_one(dict(wl, precision="f16s", curvature="mlp"), a.steps, a.warmup, log, net=net)
+    # the same foam under gravity (body-force term, forced kernel instances)
+    grav = (0.0, 0.0, -3e-5)
+    r16g = run_one(dict(wl, precision="f16s_g16", curvature="mlp", accel=grav), max(a.steps // 2, 1),
+                   a.warmup, log, net=net)
     ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
 
@@ -335,15 +342,16 @@ def main():
         "hbm_frac_step": round(r16["hbm_frac_step"], 4),
         "fp32_plain": brief(r32),
         "f16_f_only_mlp": brief(r16f),
+        "body_force": dict(brief(r16g), accel=list(grav), steps=max(a.steps // 2, 1)),
         "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep_vec<3,4,4,256> (bulk sweep, binary16 f and g)",
+            "kernel": "k_sweep_vec<3,4,4,256,false> (bulk sweep, binary16 f and g, no body force)",
             "achieved": round(r16["bulk_sweep_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(r16["bulk_sweep_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("k_sweep_vec<3,4,4,256>"),
+            "traffic": measured_traffic("k_sweep_vec<3,4,4,256,false>"),
             "bytes_per_launch": r16["bulk_sweep_bytes"],
             "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
             "isolated": {"achieved": round(r16["bulk_isolated_gbs"], 1),

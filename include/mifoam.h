@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MF_ABI_VERSION 1
+#define MF_ABI_VERSION 2
 
 enum mf_status {
   MF_OK = 0,
@@ -111,6 +111,13 @@ typedef struct mf_params {
   double S0;             /* initial supersaturation c0 / (kH p_atm) */
   double pl_n, pl_nu_ref, pl_gdot_ref; /* power law nu = nu_ref (gdot/gdot_ref)^(n-1) */
   double tau_min, tau_max;             /* clamp of the power-law relaxation time */
+  double accel[3];       /* body-force acceleration a (gravity), lattice units; all zero:
+                            no force term. Liquid and interface cells take the external
+                            force term of Eq. collision in the form of Guo, Zheng and Shi
+                            (2002): F = rho a, velocity (sum f e + F/2) / rho, and
+                            (1 - omega/2) w_i [(e_i - u)/c_s^2 + (e_i.u) e_i/c_s^4].F added
+                            after the relaxation; the power-law strain rate takes the
+                            force correction (u F + F u)/2. |a_k| <= 1e-2; a_z = 0 in 2D. */
 } mf_params;
 
 typedef struct mf_bubble {

@@ -161,6 +161,9 @@ int validate(const mf_params *p, std::string &why) {
   if (p->max_ids < 2 || p->max_ids > (1 << 24)) { why = "max_ids out of range"; return MF_EINVAL; }
   if (!(p->tau > 0.5) || !(p->D > 0.0) || !(p->RT > 0.0) || !(p->eps >= 0.0)) { why = "tau > 1/2, D > 0, RT > 0, eps >= 0 required"; return MF_EINVAL; }
   if (p->k_pi > 0.0 && !(p->d_max >= 1.0)) { why = "d_max >= 1 required with disjoining pressure"; return MF_EINVAL; }
+  for (int a = 0; a < 3; a++)
+    if (!(fabs(p->accel[a]) <= 1e-2)) { why = "body-force acceleration components must be finite with |a| <= 1e-2"; return MF_EINVAL; }
+  if (p->dim == 2 && p->accel[2] != 0.0) { why = "a plane (2D) domain takes no third acceleration component"; return MF_EINVAL; }
   if (p->rheology == MF_POWER_LAW && !(p->tau_min > 0.5 && p->tau_max >= p->tau_min && p->pl_nu_ref > 0 && p->pl_gdot_ref > 0)) {
     why = "power law needs 1/2 < tau_min <= tau_max, nu_ref > 0, gdot_ref > 0";
     return MF_EINVAL;
@@ -207,6 +210,13 @@ KP make_kp(const mf_params &P) {
   if (!(gs > 0.0)) gs = 1.0;
   k.gsc = (float)gs;
   k.ginv = (float)(1.0 / gs);
+  k.ax = P.accel[0];
+  k.ay = P.accel[1];
+  k.az = P.dim == 3 ? P.accel[2] : 0.0;
+  k.force = k.ax != 0.0 || k.ay != 0.0 || k.az != 0.0;
+  k.fax = (float)k.ax;
+  k.fay = (float)k.ay;
+  k.faz = (float)k.az;
   k.pl_l2nu3 = P.pl_nu_ref > 0.0 ? (float)log2(3.0 * P.pl_nu_ref) : 0.0f;
   k.pl_kg = P.pl_gdot_ref > 0.0 ? (float)(2.1213203435596424 / P.pl_gdot_ref) : 0.0f;
   return k;
@@ -270,9 +280,10 @@ static void destroy_side(mf_ctx *c) {
   if (c->side) (void)hipStreamSynchronize(c->side);
   if (c->ev_conv) (void)hipEventDestroy(c->ev_conv);
   if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+  if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
   if (c->side) (void)hipStreamDestroy(c->side);
   c->side = nullptr;
-  c->ev_conv = c->ev_side = nullptr;
+  c->ev_conv = c->ev_side = c->ev_norm = nullptr;
 }
 
 // the context stream waits for the labelling and geometry the last step left running on
@@ -345,6 +356,7 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
     hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_conv, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_norm, hipEventDisableTiming);
     if (e != hipSuccess) {
       g_err = std::string("creating the side stream failed: ") + hipGetErrorString(e);
       destroy_side(c);
@@ -445,9 +457,11 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 // populations and the wall mask, which labelling and geometry leave alone, and write the
 // populations and this step parity's counters and interface list; the interface sweep,
 // the first kernel that reads labels, bubble pressures and curvature, waits for the side
-// stream. The caller joins what the last step left running (join_side) before anything
-// else touches the state. Graph capture takes the plain order: there the domains already
-// run as parallel branches.
+// stream. The bulk sweep itself waits for the labelling and normals, so that the learned-
+// curvature kernel is dispatched beside it rather than into a GPU it already fills. The
+// caller joins what the last step left running (join_side) before anything else touches
+// the state. Graph capture takes the plain order: there the domains already run as
+// parallel branches.
 static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
   c->parity ^= 1;
   select_parity(c);
@@ -455,6 +469,7 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
   if (ev) (void)hipEventRecord(ev[1], c->stream);
+  if (c->side_pending) (void)hipStreamWaitEvent(c->stream, c->ev_norm, 0);
   c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, &join_side_cb, c);
   if (ev) (void)hipEventRecord(ev[4], c->stream);
   c->cur ^= 1;
@@ -463,7 +478,9 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
     (void)hipEventRecord(c->ev_conv, c->stream);
     (void)hipStreamWaitEvent(c->side, c->ev_conv, 0);
     c->ops.label(*c, c->side, 1);
+    c->ev_norm_rec = c->ev_norm;
     c->ops.geometry(*c, c->side);
+    c->ev_norm_rec = nullptr;
     if (ev) (void)hipEventRecord(ev[5], c->side);
     (void)hipEventRecord(c->ev_side, c->side);
     c->side_pending = true;

@@ -459,6 +459,7 @@ void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
     c.sword_dirty = false;
   }
   hipLaunchKernelGGL((k_normals<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, sword_all);
+  if (c.ev_norm_rec) (void)hipEventRecord(c.ev_norm_rec, s);
   if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
   hipLaunchKernelGGL((k_curvature<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   c.gas_dirty = false;

@@ -144,6 +144,9 @@ struct KP {
   float gsc, ginv;  // dissolved-gas storage scale s_g and 1/s_g (instance 4)
   float pl_l2nu3;   // log2(3 nu_ref) (power law, binary32 instances)
   float pl_kg;      // (3 / sqrt 2) / gdot_ref: shear rate = pl_kg |Pi_neq| / (rho tau) gdot_ref
+  int force;        // body-force acceleration a is non-zero
+  double ax, ay, az;
+  float fax, fay, faz;
 };
 
 struct DA {
@@ -418,11 +421,14 @@ struct Ctx {
   // Steps overlap: the labelling and geometry of step n run on the side stream while the
   // main stream builds the lists and runs the bulk sweep of step n+1 (neither reads what
   // the other writes); the interface sweep of step n+1 waits for ev_side. Counters and
-  // the interface list alternate between two copies by step parity.
+  // the interface list alternate between two copies by step parity. The bulk sweep starts
+  // once the labelling and normals are done (ev_norm): the learned-curvature kernel is
+  // then dispatched beside it instead of into a GPU the bulk sweep already fills.
+  // geometry() records ev_norm_rec, when set, after the normals.
   int32_t *cnt_base = nullptr, *ilist_base = nullptr;
   int parity = 0;
   hipStream_t side = nullptr;
-  hipEvent_t ev_conv = nullptr, ev_side = nullptr;
+  hipEvent_t ev_conv = nullptr, ev_side = nullptr, ev_norm = nullptr, ev_norm_rec = nullptr;
   bool side_pending = false;  // ev_side marks side-stream work the main stream has not joined
 };
 

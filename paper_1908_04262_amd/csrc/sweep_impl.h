@@ -61,6 +61,25 @@ __device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float
   return tau;
 }
 
+// Force correction of the strain-rate estimate under a body force F = rho a: the
+// non-equilibrium momentum flux that measures the strain rate is Pi_neq + (u F + F u)/2
+// (in a uniformly accelerated box the populations carry Pi_neq = -(u F + F u)/2 and no
+// strain).
+template <int D, class R>
+__device__ __forceinline__ void force_stress(R rho, R ux, R uy, R uz, R ax, R ay, R az, R &pxx, R &pyy, R &pzz,
+                                             R &pxy, R &pxz, R &pyz) {
+  const R Fx = rho * ax, Fy = rho * ay;
+  pxx = pxx + ux * Fx;
+  pyy = pyy + uy * Fy;
+  pxy = pxy + R(0.5) * (ux * Fy + uy * Fx);
+  if constexpr (D == 3) {
+    const R Fz = rho * az;
+    pzz = pzz + uz * Fz;
+    pxz = pxz + R(0.5) * (ux * Fz + uz * Fx);
+    pyz = pyz + R(0.5) * (uy * Fz + uz * Fy);
+  }
+}
+
 // BGK collision of one cell on offsets in binary32 (instances 1-4). Directions come in
 // opposite pairs (2k+1, 2k+2): the moments are taken from the pair sums s and
 // differences d (density from s, momentum from d, the momentum flux from s, whose
@@ -68,7 +87,9 @@ __device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float
 // equilibria are built per pair (even part w (drho + rho (4.5 (e.u)^2 - 1.5 u.u)), odd
 // part 3 w rho e.u).
 // c0 and q are the reference concentration and the source in the units gt is held in.
-template <int D>
+// FRC: the domain has a body force (a compile-time switch, so that the unforced sweep
+// keeps its register budget).
+template <int D, bool FRC>
 __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft, float *gt, float &rho, float &ux,
                                             float &uy, float &uz, float c0, float q) {
   using L = Lat<D>;
@@ -95,6 +116,13 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
   ux = jx * ir;
   uy = jy * ir;
   uz = D == 3 ? jz * ir : 0.0f;
+  // body force F = rho a (Guo et al.): the velocity is (sum f e + F/2) / rho
+  constexpr bool frc = FRC;
+  if constexpr (frc) {
+    ux = ux + 0.5f * p.fax;
+    uy = uy + 0.5f * p.fay;
+    if (D == 3) uz = uz + 0.5f * p.faz;
+  }
   const float uu = usq<D, float>(ux, uy, uz);
   float omega = (float)p.omega;
   if (p.rheology == MF_POWER_LAW) {
@@ -122,23 +150,48 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
       pxz = pxz - rho * ux * uz;
       pyz = pyz - rho * uy * uz;
     }
+    if constexpr (frc) force_stress<D, float>(rho, ux, uy, uz, p.fax, p.fay, p.faz, pxx, pyy, pzz, pxy, pxz, pyz);
     const float ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + 2.0f * ((pxy * pxy + pxz * pxz) + pyz * pyz);
     omega = __builtin_amdgcn_rcpf(powerlaw_tau_f32(p, ir, __builtin_amdgcn_sqrtf(ss)));
   }
   const float c15 = 1.5f * uu;
-  {
-    const float w0 = (float)L::w[0];
-    ft[0] = ft[0] - omega * (ft[0] - (w0 * drho - (w0 * rho) * c15));
-  }
+  if constexpr (!frc) {
+    {
+      const float w0 = (float)L::w[0];
+      ft[0] = ft[0] - omega * (ft[0] - (w0 * drho - (w0 * rho) * c15));
+    }
 #pragma unroll
-  for (int i = 1; i < Q; i += 2) {
-    const float eu = edot<D, float>(i, ux, uy, uz);
-    const float w = (float)L::w[i];
-    const float wr = w * rho;
-    const float ev = w * drho + wr * ((4.5f * eu) * eu - c15);
-    const float od = wr * (3.0f * eu);
-    ft[i] = ft[i] - omega * (ft[i] - (ev + od));
-    ft[i + 1] = ft[i + 1] - omega * (ft[i + 1] - (ev - od));
+    for (int i = 1; i < Q; i += 2) {
+      const float eu = edot<D, float>(i, ux, uy, uz);
+      const float w = (float)L::w[i];
+      const float wr = w * rho;
+      const float ev = w * drho + wr * ((4.5f * eu) * eu - c15);
+      const float od = wr * (3.0f * eu);
+      ft[i] = ft[i] - omega * (ft[i] - (ev + od));
+      ft[i + 1] = ft[i + 1] - omega * (ft[i + 1] - (ev - od));
+    }
+  } else {
+    // force term (1 - omega/2) F_i, F_i = w rho [3 (e - u).a + 9 (e.u)(e.a)]: per pair the
+    // even part w rho (9 (e.u)(e.a) - 3 u.a) and the odd part 3 w rho e.a
+    const float kf = 1.0f - 0.5f * omega;
+    const float ua = (ux * p.fax + uy * p.fay) + (D == 3 ? uz * p.faz : 0.0f);
+    {
+      const float w0 = (float)L::w[0];
+      ft[0] = (ft[0] - omega * (ft[0] - (w0 * drho - (w0 * rho) * c15))) + kf * ((w0 * rho) * (-3.0f * ua));
+    }
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const float eu = edot<D, float>(i, ux, uy, uz);
+      const float ea = edot<D, float>(i, p.fax, p.fay, p.faz);
+      const float w = (float)L::w[i];
+      const float wr = w * rho;
+      const float ev = w * drho + wr * ((4.5f * eu) * eu - c15);
+      const float od = wr * (3.0f * eu);
+      const float evf = kf * (wr * ((9.0f * eu) * ea - 3.0f * ua));
+      const float odf = kf * (wr * (3.0f * ea));
+      ft[i] = (ft[i] - omega * (ft[i] - (ev + od))) + (evf + odf);
+      ft[i + 1] = (ft[i + 1] - omega * (ft[i + 1] - (ev - od))) + (evf - odf);
+    }
   }
   float dc = gt[0];
 #pragma unroll
@@ -161,14 +214,14 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
 }
 
 // BGK collision of one cell in the register convention of instance P (fluid and ADE
-// lattices); ft and gt are replaced by their post-collision values.
-template <int D, int P>
+// lattices); ft and gt are replaced by their post-collision values. FRC: body force.
+template <int D, int P, bool FRC>
 __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename Prec<P>::R *ft,
                                              typename Prec<P>::R *gt, typename Prec<P>::R &rho,
                                              typename Prec<P>::R &ux, typename Prec<P>::R &uy,
                                              typename Prec<P>::R &uz) {
   if constexpr (P != 0) {
-    collide_f32<D>(p, d, ft, gt, rho, ux, uy, uz, (float)p.c0, (float)p.q);
+    collide_f32<D, FRC>(p, d, ft, gt, rho, ux, uy, uz, (float)p.c0, (float)p.q);
     return;
   }
   using L = Lat<D>;
@@ -178,6 +231,12 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
   R drho;
   A::mom(ft, rho, drho, ux, uy, uz);
   if (!(rho > R(0))) raise_status(d.status, ST_NONFINITE);
+  if constexpr (FRC) {
+    // body force F = rho a (Guo et al.): the velocity is (sum f e + F/2) / rho
+    ux = ux + R(0.5) * R(p.ax);
+    uy = uy + R(0.5) * R(p.ay);
+    if (D == 3) uz = uz + R(0.5) * R(p.az);
+  }
   const R uu = usq<D, R>(ux, uy, uz);
   R omega = R(p.omega);
   if (p.rheology == MF_POWER_LAW) {
@@ -208,6 +267,7 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
         pyz = pyz - rho * uy * uz;
       }
     }
+    if constexpr (FRC) force_stress<D, R>(rho, ux, uy, uz, R(p.ax), R(p.ay), R(p.az), pxx, pyy, pzz, pxy, pxz, pyz);
     const R ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + R(2) * ((pxy * pxy + pxz * pxz) + pyz * pyz);
     omega = R(1) / powerlaw_tau<R>(p, rho, sqrt(ss));
   }
@@ -215,6 +275,17 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
   for (int i = 0; i < Q; ++i) {
     const R fe = A::eq(i, rho, drho, ux, uy, uz, uu);
     ft[i] = ft[i] - omega * (ft[i] - fe);
+  }
+  if constexpr (FRC) {
+    const R kf = R(1) - R(0.5) * omega;
+    const R ax = R(p.ax), ay = R(p.ay), az = R(p.az);
+    const R ua = (ux * ax + uy * ay) + (D == 3 ? uz * az : R(0));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R eu = edot<D, R>(i, ux, uy, uz);
+      const R ea = edot<D, R>(i, ax, ay, az);
+      ft[i] = ft[i] + kf * ((rho * R(L::w[i])) * (R(3) * (ea - ua) + (R(9) * eu) * ea));
+    }
   }
   R dc;
   const R c = A::conc(gt, R(p.c0), dc);
@@ -333,7 +404,7 @@ __device__ __forceinline__ uint8_t store_interface(const KP &p, DA &d, int64_t n
 // The whole update of one cell (x, y, z) = n with type byte tb and bubble id lab; lanes
 // with fluid == false only take part in the wave-level gas-ledger sum. Called by the
 // whole wave.
-template <int D, int P>
+template <int D, int P, bool FRC>
 __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool fluid, int x, int y, int z, int64_t n,
                                            uint8_t tb, int32_t lab) {
   using L = Lat<D>;
@@ -369,7 +440,7 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
       special_terms<D, P>(p, d, cur, n, isI, lab, src, dst, ft, gt, Ms, hasG, hasF, phic, hasgas);
     }
     R rho, ux, uy, uz;
-    collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
+    collide_cell<D, P, FRC>(p, d, ft, gt, rho, ux, uy, uz);
 #pragma unroll
     for (int i = 0; i < Q; ++i) fout[(int64_t)i * Np + n] = FC::enc(ft[i], i);
 #pragma unroll
@@ -390,7 +461,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 }
 
 // ------------------------------------------------------------------ per-cell form
-template <int D, int P>
+template <int D, int P, bool FRC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep(KP p, DA d, int cur) {
   // tile of 64 x 4 cells
   const int gx = (p.nx + 63) >> 6, gy = (p.ny + 3) >> 2;
@@ -407,12 +478,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const uint8_t tb = in ? d.type[n] : TW;
   const int t = tb & TMASK;
   const int32_t lab = in && t == TI ? d.label[n] : NOLAB;
-  sweep_cell<D, P>(p, d, cur, in && (t == TL || t == TI), x, y, z, n, tb, lab);
+  sweep_cell<D, P, FRC>(p, d, cur, in && (t == TL || t == TI), x, y, z, n, tb, lab);
 }
 
 // ------------------------------------------------------------------ split form
 // interface cells (this step's interface list) through the per-cell update
-template <int D, int P>
+template <int D, int P, bool FRC>
 __global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
   LIST_LOOP(k, d.cnt + C_I) {
     int64_t n = 0;
@@ -427,7 +498,7 @@ __global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
       lab = d.label[n];
       cell_xyz(p, n, x, y, z);
     }
-    sweep_cell<D, P>(p, d, cur, fluid, x, y, z, n, tb, lab);
+    sweep_cell<D, P, FRC>(p, d, cur, fluid, x, y, z, n, tb, lab);
   }
 }
 
@@ -517,7 +588,7 @@ __device__ __forceinline__ void load_all(const KP &p, const typename Prec<P>::SF
 // Bulk kernel: VW consecutive cells n0 .. n0+VW-1 per thread (the grid is linear in the
 // cell index). Requires closed axes (no periodic wrap) and nx % VW == 0, so that every
 // group starts on a VW boundary and the pulls of a fluid cell are plain index offsets.
-template <int D, int P, int VW, int BS>
+template <int D, int P, int VW, int BS, bool FRC>
 __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
@@ -612,9 +683,9 @@ __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
       }
       R rho, ux, uy, uz;
       if constexpr (P == 4)
-        collide_f32<D>(p, d, ft, gt, rho, ux, uy, uz, (float)p.c0 * p.ginv, (float)p.q * p.ginv);
+        collide_f32<D, FRC>(p, d, ft, gt, rho, ux, uy, uz, (float)p.c0 * p.ginv, (float)p.q * p.ginv);
       else
-        collide_cell<D, P>(p, d, ft, gt, rho, ux, uy, uz);
+        collide_cell<D, P, FRC>(p, d, ft, gt, rho, ux, uy, uz);
 #pragma unroll
       for (int i = 0; i < Q; ++i) fv[i][e] = FC::enc(ft[i], i);
 #pragma unroll
@@ -654,7 +725,8 @@ template <int D, int P, int VW, int BS>
 bool launch_bulk(Ctx &c, hipStream_t s) {
   if (!vector_ok<D, P, VW>(c)) return false;
   const int64_t nb = (c.kp.N + (int64_t)BS * VW - 1) / ((int64_t)BS * VW);
-  hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
+  if (c.kp.force) hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS, true>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
+  else hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS, false>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
   return true;
 }
 
@@ -682,14 +754,16 @@ void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t bulk_end, hipEvent_t spe
       if (bulk_end) (void)hipEventRecord(bulk_end, s);
       if (between) between(arg);
       if (special_start) (void)hipEventRecord(special_start, s);
-      hipLaunchKernelGGL((k_sweep_special<D, P>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
+      if (c.kp.force) hipLaunchKernelGGL((k_sweep_special<D, P, true>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
+      else hipLaunchKernelGGL((k_sweep_special<D, P, false>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
       return;
     }
   }
   const int gx = (c.kp.nx + 63) / 64, gy = (c.kp.ny + 3) / 4;
   const int64_t nb = (int64_t)gx * gy * c.kp.nz;
   if (between) between(arg);
-  hipLaunchKernelGGL((k_sweep<D, P>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
+  if (c.kp.force) hipLaunchKernelGGL((k_sweep<D, P, true>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
+  else hipLaunchKernelGGL((k_sweep<D, P, false>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
   if (bulk_end) (void)hipEventRecord(bulk_end, s);
   if (special_start) (void)hipEventRecord(special_start, s);
 }

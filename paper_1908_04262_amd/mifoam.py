@@ -33,7 +33,7 @@ class MfParams(C.Structure):
         ("RT", C.c_double), ("k_pi", C.c_double), ("d_max", C.c_double),
         ("p_atm", C.c_double), ("q", C.c_double), ("eps", C.c_double), ("S0", C.c_double),
         ("pl_n", C.c_double), ("pl_nu_ref", C.c_double), ("pl_gdot_ref", C.c_double),
-        ("tau_min", C.c_double), ("tau_max", C.c_double),
+        ("tau_min", C.c_double), ("tau_max", C.c_double), ("accel", C.c_double * 3),
     ]
 
 
@@ -134,6 +134,8 @@ def make_params(wl: dict) -> MfParams:
     for k in ("tau", "D", "sigma", "kH", "RT", "k_pi", "d_max", "p_atm", "q", "eps", "S0",
               "pl_n", "pl_nu_ref", "pl_gdot_ref", "tau_min", "tau_max"):
         setattr(p, k, float(wl[k]))
+    for a, v in enumerate(wl.get("accel", (0.0, 0.0, 0.0))):
+        p.accel[a] = float(v)
     return p
 
 

@@ -26,7 +26,8 @@ def test_library_exports_every_symbol():
     lib = load_library()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.mf_abi_version() == 1
+    want = int(re.search(r"#define MF_ABI_VERSION (\d+)", open(os.path.join(ROOT, "include", "mifoam.h")).read()).group(1))
+    assert lib.mf_abi_version() == want
 
 
 def test_workspace_and_validation_on_host():
@@ -48,3 +49,14 @@ def test_workspace_and_validation_on_host():
     bad2 = make_params(workload("c3_foam_384"))
     bad2.struct_size = 8
     assert lib.mf_workspace_bytes(C.byref(bad2), C.byref(n)) == -1
+    # body force: bounded components, none out of the plane of a 2D domain
+    ok = make_params(workload("c3_foam_384", accel=(0.0, 0.0, -3e-5)))
+    assert lib.mf_workspace_bytes(C.byref(ok), C.byref(n)) == 0
+    big = make_params(workload("c3_foam_384", accel=(0.0, 0.02, 0.0)))
+    assert lib.mf_workspace_bytes(C.byref(big), C.byref(n)) == -1
+    assert b"acceleration" in lib.mf_last_error(None)
+    nan = make_params(workload("c3_foam_384", accel=(float("nan"), 0.0, 0.0)))
+    assert lib.mf_workspace_bytes(C.byref(nan), C.byref(n)) == -1
+    plane = make_params(workload("c1_2d_128", accel=(0.0, -1e-5, 1e-5)))
+    assert lib.mf_workspace_bytes(C.byref(plane), C.byref(n)) == -1
+    assert b"2D" in lib.mf_last_error(None)
