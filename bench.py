@@ -346,12 +346,12 @@ def main():
         "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep_vec<3,4,4,256,false> (bulk sweep, binary16 f and g, no body force)",
+            "kernel": "k_sweep_vec<3,4,4,256> (bulk sweep, binary16 f and g)",
             "achieved": round(r16["bulk_sweep_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(r16["bulk_sweep_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("k_sweep_vec<3,4,4,256,false>"),
+            "traffic": measured_traffic("k_sweep_vec<3,4,4,256>"),
             "bytes_per_launch": r16["bulk_sweep_bytes"],
             "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
             "isolated": {"achieved": round(r16["bulk_isolated_gbs"], 1),

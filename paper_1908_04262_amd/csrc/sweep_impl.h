@@ -589,7 +589,7 @@ __device__ __forceinline__ void load_all(const KP &p, const typename Prec<P>::SF
 // cell index). Requires closed axes (no periodic wrap) and nx % VW == 0, so that every
 // group starts on a VW boundary and the pulls of a fluid cell are plain index offsets.
 template <int D, int P, int VW, int BS, bool FRC>
-__global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
+__device__ __forceinline__ void sweep_vec_body(const KP &p, const DA &d, int cur) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
@@ -721,12 +721,23 @@ bool vector_ok(const Ctx &c) {
   return c.kp.nx % VW == 0 && c.kp.nx >= 2 * VW && c.kp.ny >= 3 && (D == 2 || c.kp.nz >= 3);
 }
 
+// the bulk kernel without and with the body-force term; the forced one is held to the
+// register budget of four waves per SIMD, which the memory-bound sweep needs
+template <int D, int P, int VW, int BS>
+__global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
+  sweep_vec_body<D, P, VW, BS, false>(p, d, cur);
+}
+template <int D, int P, int VW, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_vec_force(KP p, DA d, int cur) {
+  sweep_vec_body<D, P, VW, BS, true>(p, d, cur);
+}
+
 template <int D, int P, int VW, int BS>
 bool launch_bulk(Ctx &c, hipStream_t s) {
   if (!vector_ok<D, P, VW>(c)) return false;
   const int64_t nb = (c.kp.N + (int64_t)BS * VW - 1) / ((int64_t)BS * VW);
-  if (c.kp.force) hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS, true>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
-  else hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS, false>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
+  if (c.kp.force) hipLaunchKernelGGL((k_sweep_vec_force<D, P, VW, BS>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
+  else hipLaunchKernelGGL((k_sweep_vec<D, P, VW, BS>), dim3((unsigned)nb), dim3(BS), 0, s, c.kp, c.d, c.cur);
   return true;
 }
 
