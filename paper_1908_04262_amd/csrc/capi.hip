@@ -468,8 +468,8 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
   if (ev) (void)hipEventRecord(ev[0], c->stream);
   reset_counters(c);
   c->ops.build_lists(*c, c->stream);
-  if (ev) (void)hipEventRecord(ev[1], c->stream);
   if (c->side_pending) (void)hipStreamWaitEvent(c->stream, c->ev_norm, 0);
+  if (ev) (void)hipEventRecord(ev[1], c->stream);  // after the wait: times the bulk kernel alone
   c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, &join_side_cb, c);
   if (ev) (void)hipEventRecord(ev[4], c->stream);
   c->cur ^= 1;
