@@ -57,12 +57,13 @@ typedef struct {
   int32_t dim, nx, ny, nz;
   int32_t periodic[3];
   int32_t gas_from;  /* cells whose last coordinate is >= gas_from start as headspace gas; <0: none */
-  int32_t rheology;  /* 0 Newtonian BGK, 1 power law */
+  int32_t rheology;  /* 0 Newtonian BGK, 1 power law, 2 Carreau-Yasuda */
   int32_t cleanup;   /* 1: stranded interface cells are filled / emptied */
   int32_t max_ids;   /* capacity of the bubble table (ids 0..max_ids-1) */
   double tau, D, sigma, kH, RT, k_pi, d_max, p_atm, q, eps, S0;
   double pl_n, pl_nu_ref, pl_gdot_ref, tau_min, tau_max;
   double accel[3]; /* body-force acceleration a (gravity); 0: no force term */
+  double cy_tau0, cy_tau_inf, cy_lambda, cy_a, cy_n; /* Carreau-Yasuda (Eq. carreauTau) */
 } or_params;
 
 typedef struct {
@@ -259,6 +260,39 @@ static double powerlaw_tau_iter(const or_params *P, double rho, double pn, int i
   return tau;
 }
 double or_powerlaw_tau(const or_params *P, double rho, double pn) { return powerlaw_tau_iter(P, rho, pn, 4); }
+
+/* Carreau-Yasuda relaxation time, Eq. carreauTau in full:
+ * (tau - tau_inf) / (tau0 - tau_inf) = (1 + (lambda gdot)^a)^((n - 1) / a), with the shear rate
+ * gdot = K |Pi_neq| / (rho tau), K = 3/sqrt(2), taken at the cell's own tau as for the power law,
+ * so tau solves G(tau) = tau - h(tau) = 0 with h the right-hand side times (tau0 - tau_inf) plus
+ * tau_inf. For shear thinning (n <= 1, tau0 >= tau_inf, the use the paper names) h rises with tau
+ * and h' <= (tau0 - tau_inf)(1 - n) / tau, so with (tau0 - tau_inf)(1 - n) < tau_inf the root in
+ * [tau_inf, tau0] is unique; G(tau_inf) <= 0 <= G(tau0). It is found here by plain bisection
+ * down to adjacent doubles. Zero shear gives tau0. Pinned against a bracketing root solve, the
+ * Newtonian limits (lambda = 0, n = 1, tau0 = tau_inf) and body-force-driven channel flow against
+ * the profile integrated from the model's stress-shear relation. */
+double or_cy_tau(const or_params *P, double rho, double pn) {
+  double t0 = P->cy_tau0, ti = P->cy_tau_inf;
+  if (!(pn > 0.0) || P->cy_lambda == 0.0 || t0 == ti) return t0;
+  double g0 = (2.1213203435596424 * pn) / rho; /* gdot * tau */
+  double m = (P->cy_n - 1.0) / P->cy_a;
+  double lo = ti, hi = t0;
+  int it;
+  for (it = 0; it < 2000; it++) {
+    double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    double gd = g0 / mid;
+    double h = ti + (t0 - ti) * pow(1.0 + pow(P->cy_lambda * gd, P->cy_a), m);
+    if (mid - h < 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  /* the closer of the two adjacent end points */
+  double glo = lo - (ti + (t0 - ti) * pow(1.0 + pow(P->cy_lambda * g0 / lo, P->cy_a), m));
+  double ghi = hi - (ti + (t0 - ti) * pow(1.0 + pow(P->cy_lambda * g0 / hi, P->cy_a), m));
+  return fabs(glo) <= fabs(ghi) ? lo : hi;
+}
 double or_powerlaw_tau_iter(const or_params *P, double rho, double pn, int iters) {
   return powerlaw_tau_iter(P, rho, pn, iters);
 }
@@ -1102,6 +1136,7 @@ static int step_once(OS *s) {
     for (i = 0; i < Q; i++) fe[i] = feq(s, i, rho, ux, uy, uz);
     double omega = omega_newton;
     if (P->rheology == 1) omega = 1.0 / or_powerlaw_tau(P, rho, pineq_norm(s, ft, fe, rho, ux, uy, uz));
+    if (P->rheology == 2) omega = 1.0 / or_cy_tau(P, rho, pineq_norm(s, ft, fe, rho, ux, uy, uz));
     for (i = 0; i < Q; i++) fn[(int64_t)i * N + n] = ft[i] - omega * (ft[i] - fe[i]);
     if (s->force)
       for (i = 0; i < Q; i++) fn[(int64_t)i * N + n] = fn[(int64_t)i * N + n] + (1.0 - 0.5 * omega) * force_i(s, i, rho, ux, uy, uz);

@@ -25,6 +25,8 @@ class OrParams(C.Structure):
         ("p_atm", C.c_double), ("q", C.c_double), ("eps", C.c_double), ("S0", C.c_double),
         ("pl_n", C.c_double), ("pl_nu_ref", C.c_double), ("pl_gdot_ref", C.c_double),
         ("tau_min", C.c_double), ("tau_max", C.c_double), ("accel", C.c_double * 3),
+        ("cy_tau0", C.c_double), ("cy_tau_inf", C.c_double), ("cy_lambda", C.c_double),
+        ("cy_a", C.c_double), ("cy_n", C.c_double),
     ]
 
 
@@ -66,6 +68,8 @@ def load_library():
     lib.or_powerlaw_tau.restype = C.c_double
     lib.or_powerlaw_tau.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double]
     lib.or_lattice.argtypes = [vp, vp, vp, vp, vp]
+    lib.or_cy_tau.restype = C.c_double
+    lib.or_cy_tau.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double]
     lib.or_powerlaw_tau_iter.restype = C.c_double
     lib.or_powerlaw_tau_iter.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double, C.c_int]
     lib.or_relabel.argtypes = [vp]
@@ -82,7 +86,7 @@ def make_params(wl: dict) -> OrParams:
     for a in range(3):
         p.periodic[a] = int(wl["periodic"][a])
     p.gas_from = int(wl["gas_from"])
-    p.rheology = 1 if wl["rheology"] == "power_law" else 0
+    p.rheology = {"newtonian": 0, "power_law": 1, "carreau_yasuda": 2}[wl["rheology"]]
     p.cleanup = int(wl["cleanup"])
     p.max_ids = int(wl["max_ids"])
     for k in ("tau", "D", "sigma", "kH", "RT", "k_pi", "d_max", "p_atm", "q", "eps", "S0",
@@ -90,6 +94,8 @@ def make_params(wl: dict) -> OrParams:
         setattr(p, k, float(wl[k]))
     for a, v in enumerate(wl.get("accel", (0.0, 0.0, 0.0))):
         p.accel[a] = float(v)
+    for k, d in (("cy_tau0", 0.8), ("cy_tau_inf", 0.8), ("cy_lambda", 0.0), ("cy_a", 2.0), ("cy_n", 1.0)):
+        setattr(p, k, float(wl.get(k, d)))
     return p
 
 
@@ -229,6 +235,12 @@ def powerlaw_tau(wl, rho, pn, iters=None):
     if iters is None:
         return lib.or_powerlaw_tau(C.byref(p), rho, pn)
     return lib.or_powerlaw_tau_iter(C.byref(p), rho, pn, int(iters))
+
+
+def cy_tau(wl, rho, pn):
+    """Carreau-Yasuda relaxation time of the oracle (Eq. carreauTau)."""
+    lib = load_library()
+    return lib.or_cy_tau(C.byref(make_params(wl)), rho, pn)
 
 
 def traverse(dim, m, dmax):
