@@ -11,7 +11,8 @@ of run (ii) is trained on the GPU by the library before the timed region (2M gen
 stencils by default), and its training time and validation error are reported.
 
 The same binary16 + learned-curvature run is repeated under gravity (a body force along
--z, reported under ``body_force``; the metric's workload itself has none).
+-z, reported under ``body_force``) and with a Carreau-Yasuda liquid (``carreau_yasuda``); the
+metric's workload itself is a power-law liquid without body force.
 
 A third measurement covers the batched ensemble (48 independent domains of 64^3 to 160^3,
 binary16 storage, learned curvature): MLUPS over all domains stepped one after another,
@@ -307,6 +308,10 @@ def main():
     grav = (0.0, 0.0, -3e-5)
     r16g = run_one(dict(wl, precision="f16s_g16", curvature="mlp", accel=grav), max(a.steps // 2, 1),
                    a.warmup, log, net=net)
+    # the same foam with a Carreau-Yasuda liquid (shear thinning between tau_inf and tau0)
+    cy = dict(rheology="carreau_yasuda", cy_tau0=1.2, cy_tau_inf=0.6, cy_lambda=1000.0, cy_a=2.0, cy_n=0.4)
+    r16c = run_one(dict(wl, precision="f16s_g16", curvature="mlp", **cy), max(a.steps // 2, 1),
+                   a.warmup, log, net=net)
     ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
 
@@ -343,6 +348,8 @@ def main():
         "fp32_plain": brief(r32),
         "f16_f_only_mlp": brief(r16f),
         "body_force": dict(brief(r16g), accel=list(grav), steps=max(a.steps // 2, 1)),
+        "carreau_yasuda": dict(brief(r16c), params={k: v for k, v in cy.items() if k != "rheology"},
+                               steps=max(a.steps // 2, 1)),
         "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
         "roofline": {
             "bound": "hbm",

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MF_ABI_VERSION 2
+#define MF_ABI_VERSION 3
 
 enum mf_status {
   MF_OK = 0,
@@ -61,7 +61,7 @@ enum mf_precision {
                       when c0 = 0), arithmetic in binary32 */
 };
 
-enum mf_rheology { MF_NEWTONIAN = 0, MF_POWER_LAW = 1 };
+enum mf_rheology { MF_NEWTONIAN = 0, MF_POWER_LAW = 1, MF_CARREAU_YASUDA = 2 };
 enum mf_curvature { MF_CURV_PLAIN = 0, MF_CURV_MLP = 1 };
 
 /* cell types reported by MF_FIELD_TYPE */
@@ -118,6 +118,13 @@ typedef struct mf_params {
                             (1 - omega/2) w_i [(e_i - u)/c_s^2 + (e_i.u) e_i/c_s^4].F added
                             after the relaxation; the power-law strain rate takes the
                             force correction (u F + F u)/2. |a_k| <= 1e-2; a_z = 0 in 2D. */
+  double cy_tau0, cy_tau_inf, cy_lambda, cy_a, cy_n;
+                         /* Carreau-Yasuda (rheology MF_CARREAU_YASUDA, Eq. carreauTau):
+                            (tau - tau_inf)/(tau0 - tau_inf) = (1 + (lambda gdot)^a)^((n-1)/a),
+                            gdot = sqrt(2 S:S) from the non-equilibrium momentum flux at the
+                            cell's own tau (implicit, solved per cell). Shear thinning:
+                            1/2 < tau_inf <= tau0, 0 < n <= 1, a > 0, lambda >= 0, and
+                            (tau0 - tau_inf)(1 - n) < tau_inf, which makes tau unique. */
 } mf_params;
 
 typedef struct mf_bubble {

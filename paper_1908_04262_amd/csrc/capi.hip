@@ -154,7 +154,14 @@ int validate(const mf_params *p, std::string &why) {
   if (p->nx < 3 || p->ny < 3 || nz < 1 || (p->dim == 3 && nz < 3)) { why = "grid too small"; return MF_EINVAL; }
   if ((double)p->nx * p->ny * nz >= 2147483647.0) { why = "grid exceeds 2^31 cells"; return MF_EINVAL; }
   if (p->precision < 0 || p->precision > 4) { why = "unknown precision"; return MF_EINVAL; }
-  if (p->rheology != MF_NEWTONIAN && p->rheology != MF_POWER_LAW) { why = "unknown rheology"; return MF_EINVAL; }
+  if (p->rheology != MF_NEWTONIAN && p->rheology != MF_POWER_LAW && p->rheology != MF_CARREAU_YASUDA) { why = "unknown rheology"; return MF_EINVAL; }
+  if (p->rheology == MF_CARREAU_YASUDA &&
+      !(p->cy_tau_inf > 0.5 && p->cy_tau0 >= p->cy_tau_inf && p->cy_tau0 < 1e6 && p->cy_n > 0.0 && p->cy_n <= 1.0 &&
+        p->cy_a > 0.0 && p->cy_a < 1e3 && p->cy_lambda >= 0.0 && p->cy_lambda < 1e12 &&
+        (p->cy_tau0 - p->cy_tau_inf) * (1.0 - p->cy_n) < p->cy_tau_inf)) {
+    why = "Carreau-Yasuda needs 1/2 < tau_inf <= tau0, 0 < n <= 1, a > 0, lambda >= 0 and (tau0 - tau_inf)(1 - n) < tau_inf";
+    return MF_EINVAL;
+  }
   if (p->curvature != MF_CURV_PLAIN && p->curvature != MF_CURV_MLP) { why = "unknown curvature mode"; return MF_EINVAL; }
   if (p->curvature == MF_CURV_MLP && p->dim != 3) { why = "the learned curvature works on 5x5x5 stencils (3D only)"; return MF_EUNSUPPORTED; }
   if (p->curvature == MF_CURV_MLP && p->max_ids > 65534) { why = "the learned curvature supports at most 65534 bubble ids"; return MF_EINVAL; }
@@ -210,6 +217,13 @@ KP make_kp(const mf_params &P) {
   if (!(gs > 0.0)) gs = 1.0;
   k.gsc = (float)gs;
   k.ginv = (float)(1.0 / gs);
+  k.cy_tau0 = P.cy_tau0;
+  k.cy_tau_inf = P.cy_tau_inf;
+  k.cy_lambda = P.cy_lambda;
+  k.cy_a = P.cy_a;
+  k.cy_n = P.cy_n;
+  k.cy_lk = (float)(P.cy_lambda * 2.1213203435596424);
+  k.cy_m = (float)((P.cy_n - 1.0) / (P.cy_a > 0.0 ? P.cy_a : 1.0));
   k.ax = P.accel[0];
   k.ay = P.accel[1];
   k.az = P.dim == 3 ? P.accel[2] : 0.0;

@@ -161,4 +161,33 @@ __device__ __forceinline__ R powerlaw_tau(const KP &p, R rho, R pn) {
   return tau;
 }
 
+// Carreau-Yasuda relaxation time (Eq. carreauTau in full): the root in [tau_inf, tau0] of
+// G(tau) = tau - tau_inf - (tau0 - tau_inf)(1 + (lambda K pn / (rho tau))^a)^((n-1)/a),
+// K = 3/sqrt 2, unique under the parameter bounds the library enforces (h' < 1). Newton's
+// method from tau0 with the bracket kept up to date (closed: a converged iterate is one of
+// its ends) and a bisection step whenever Newton leaves it; binary64 iterates until the
+// step no longer changes tau (at most 60 steps).
+// h'(tau) = (tau0 - tau_inf)(1 - n) y (1 + y)^(m-1) / tau with y = x^a, m = (n-1)/a.
+__device__ __forceinline__ double cy_tau64(const KP &p, double rho, double pn) {
+  const double t0 = p.cy_tau0, ti = p.cy_tau_inf;
+  if (!(pn > 0.0) || p.cy_lambda == 0.0 || t0 == ti) return t0;
+  const double c = (p.cy_lambda * (2.1213203435596424 * pn)) / rho;  // lambda gdot tau
+  const double m = (p.cy_n - 1.0) / p.cy_a, w = (t0 - ti) * (1.0 - p.cy_n);
+  double lo = ti, hi = t0, t = t0;
+  for (int it = 0; it < 60; ++it) {
+    const double y = pow(c / t, p.cy_a);
+    const double s = pow(1.0 + y, m);
+    const double G = t - (ti + (t0 - ti) * s);
+    if (G < 0.0) lo = t;
+    else hi = t;
+    if (G == 0.0) break;
+    const double dh = (w * y) * s / ((1.0 + y) * t);
+    double tn = t - G / (1.0 - dh);
+    if (tn == t) break;  // converged (t is an end of the bracket then)
+    if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
+    t = tn;
+  }
+  return t;
+}
+
 }  // namespace mf

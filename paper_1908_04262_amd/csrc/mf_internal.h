@@ -144,6 +144,9 @@ struct KP {
   float gsc, ginv;  // dissolved-gas storage scale s_g and 1/s_g (instance 4)
   float pl_l2nu3;   // log2(3 nu_ref) (power law, binary32 instances)
   float pl_kg;      // (3 / sqrt 2) / gdot_ref: shear rate = pl_kg |Pi_neq| / (rho tau) gdot_ref
+  double cy_tau0, cy_tau_inf, cy_lambda, cy_a, cy_n;  // Carreau-Yasuda
+  float cy_lk;      // lambda (3 / sqrt 2): lambda gdot = cy_lk |Pi_neq| / (rho tau)
+  float cy_m;       // (n - 1) / a
   int force;        // body-force acceleration a is non-zero
   double ax, ay, az;
   float fax, fay, faz;

@@ -61,6 +61,35 @@ __device__ __forceinline__ float powerlaw_tau_f32(const KP &p, float rinv, float
   return tau;
 }
 
+// Carreau-Yasuda relaxation time in binary32 (the same root as cy_tau64): Newton's method
+// from tau0 inside the bracket [tau_inf, tau0], with the hardware base-2 exponential and
+// logarithm for the two powers and one reciprocal per step; a step that leaves the bracket
+// bisects instead. From tau0 the iteration is at binary64 precision after four steps for
+// lambda gdot tau from 1e-4 to 1e4 over the shear-thinning parameter range; five are taken.
+// rinv = 1 / rho, pn = |Pi_neq|.
+__device__ __forceinline__ float cy_tau_f32(const KP &p, float rinv, float pn) {
+  const float t0 = (float)p.cy_tau0, ti = (float)p.cy_tau_inf;
+  if (!(pn > 0.0f) || p.cy_lambda == 0.0 || t0 == ti) return t0;
+  const float c = (p.cy_lk * pn) * rinv;  // lambda gdot tau
+  const float a = (float)p.cy_a, m = p.cy_m, w = (t0 - ti) * (1.0f - (float)p.cy_n);
+  float lo = ti, hi = t0, t = t0;
+#pragma unroll
+  for (int it = 0; it < 5; ++it) {
+    const float it_ = __builtin_amdgcn_rcpf(t);
+    const float y = __builtin_amdgcn_exp2f(a * __builtin_amdgcn_logf(c * it_));
+    const float s1 = 1.0f + y;
+    const float sm = __builtin_amdgcn_exp2f(m * __builtin_amdgcn_logf(s1));
+    const float G = t - (ti + (t0 - ti) * sm);
+    lo = G < 0.0f ? t : lo;
+    hi = G < 0.0f ? hi : t;
+    const float dh = ((w * y) * sm) * (__builtin_amdgcn_rcpf(s1) * it_);
+    float tn = t - G * __builtin_amdgcn_rcpf(1.0f - dh);
+    tn = (tn >= lo && tn <= hi) ? tn : 0.5f * (lo + hi);  // closed: a converged iterate is an end
+    t = tn;
+  }
+  return t;
+}
+
 // Force correction of the strain-rate estimate under a body force F = rho a: the
 // non-equilibrium momentum flux that measures the strain rate is Pi_neq + (u F + F u)/2
 // (in a uniformly accelerated box the populations carry Pi_neq = -(u F + F u)/2 and no
@@ -125,7 +154,7 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
   }
   const float uu = usq<D, float>(ux, uy, uz);
   float omega = (float)p.omega;
-  if (p.rheology == MF_POWER_LAW) {
+  if (p.rheology != MF_NEWTONIAN) {
     // non-equilibrium momentum flux: sum e e (f - w) minus the equilibrium part
     // rho c_s^2 I + rho u u taken relative to the rest state (I/3)
     float pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
@@ -152,7 +181,8 @@ __device__ __forceinline__ void collide_f32(const KP &p, const DA &d, float *ft,
     }
     if constexpr (frc) force_stress<D, float>(rho, ux, uy, uz, p.fax, p.fay, p.faz, pxx, pyy, pzz, pxy, pxz, pyz);
     const float ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + 2.0f * ((pxy * pxy + pxz * pxz) + pyz * pyz);
-    omega = __builtin_amdgcn_rcpf(powerlaw_tau_f32(p, ir, __builtin_amdgcn_sqrtf(ss)));
+    const float pn = __builtin_amdgcn_sqrtf(ss);
+    omega = __builtin_amdgcn_rcpf(p.rheology == MF_POWER_LAW ? powerlaw_tau_f32(p, ir, pn) : cy_tau_f32(p, ir, pn));
   }
   const float c15 = 1.5f * uu;
   if constexpr (!frc) {
@@ -239,7 +269,7 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
   }
   const R uu = usq<D, R>(ux, uy, uz);
   R omega = R(p.omega);
-  if (p.rheology == MF_POWER_LAW) {
+  if (p.rheology != MF_NEWTONIAN) {
     R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -269,7 +299,8 @@ __device__ __forceinline__ void collide_cell(const KP &p, const DA &d, typename 
     }
     if constexpr (FRC) force_stress<D, R>(rho, ux, uy, uz, R(p.ax), R(p.ay), R(p.az), pxx, pyy, pzz, pxy, pxz, pyz);
     const R ss = ((pxx * pxx + pyy * pyy) + pzz * pzz) + R(2) * ((pxy * pxy + pxz * pxz) + pyz * pyz);
-    omega = R(1) / powerlaw_tau<R>(p, rho, sqrt(ss));
+    if constexpr (P == 0) omega = R(1) / (p.rheology == MF_POWER_LAW ? powerlaw_tau<R>(p, rho, sqrt(ss)) : cy_tau64(p, rho, sqrt(ss)));
+    else omega = R(1) / powerlaw_tau<R>(p, rho, sqrt(ss));
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {

@@ -34,6 +34,8 @@ class MfParams(C.Structure):
         ("p_atm", C.c_double), ("q", C.c_double), ("eps", C.c_double), ("S0", C.c_double),
         ("pl_n", C.c_double), ("pl_nu_ref", C.c_double), ("pl_gdot_ref", C.c_double),
         ("tau_min", C.c_double), ("tau_max", C.c_double), ("accel", C.c_double * 3),
+        ("cy_tau0", C.c_double), ("cy_tau_inf", C.c_double), ("cy_lambda", C.c_double),
+        ("cy_a", C.c_double), ("cy_n", C.c_double),
     ]
 
 
@@ -127,7 +129,7 @@ def make_params(wl: dict) -> MfParams:
         p.periodic[a] = int(wl["periodic"][a])
     p.gas_from = int(wl["gas_from"])
     p.precision = PRECISIONS[wl["precision"]]
-    p.rheology = 1 if wl["rheology"] == "power_law" else 0
+    p.rheology = {"newtonian": 0, "power_law": 1, "carreau_yasuda": 2}[wl["rheology"]]
     p.curvature = 1 if wl.get("curvature") == "mlp" else 0
     p.cleanup = int(wl["cleanup"])
     p.max_ids = int(wl["max_ids"])
@@ -136,6 +138,8 @@ def make_params(wl: dict) -> MfParams:
         setattr(p, k, float(wl[k]))
     for a, v in enumerate(wl.get("accel", (0.0, 0.0, 0.0))):
         p.accel[a] = float(v)
+    for k, d in (("cy_tau0", 0.8), ("cy_tau_inf", 0.8), ("cy_lambda", 0.0), ("cy_a", 2.0), ("cy_n", 1.0)):
+        setattr(p, k, float(wl.get(k, d)))
     return p
 
 

@@ -57,6 +57,15 @@ def test_workspace_and_validation_on_host():
     assert b"acceleration" in lib.mf_last_error(None)
     nan = make_params(workload("c3_foam_384", accel=(float("nan"), 0.0, 0.0)))
     assert lib.mf_workspace_bytes(C.byref(nan), C.byref(n)) == -1
+    # Carreau-Yasuda: shear thinning with a unique relaxation time
+    cy = dict(rheology="carreau_yasuda", cy_tau0=1.2, cy_tau_inf=0.6, cy_lambda=1000.0, cy_a=2.0, cy_n=0.4)
+    good = make_params(workload("c3_foam_384", **cy))
+    assert lib.mf_workspace_bytes(C.byref(good), C.byref(n)) == 0
+    for badkw in (dict(cy_tau_inf=0.5), dict(cy_tau0=0.55), dict(cy_n=1.5), dict(cy_a=0.0),
+                  dict(cy_lambda=-1.0), dict(cy_tau0=3.0, cy_n=0.1)):
+        b = make_params(workload("c3_foam_384", **dict(cy, **badkw)))
+        assert lib.mf_workspace_bytes(C.byref(b), C.byref(n)) == -1, badkw
+        assert b"Carreau" in lib.mf_last_error(None)
     plane = make_params(workload("c1_2d_128", accel=(0.0, -1e-5, 1e-5)))
     assert lib.mf_workspace_bytes(C.byref(plane), C.byref(n)) == -1
     assert b"2D" in lib.mf_last_error(None)
