@@ -175,6 +175,24 @@ int mf_destroy(mf_ctx *ctx);
  * (MF_ESTATE otherwise). MF_EINVAL if a nucleus is not inside the liquid. */
 int mf_nucleate(mf_ctx *ctx, int32_t n, const double *centers, const double *radii, const double *p0);
 
+/* Nucleation sites from a nucleation probability field by Poisson-disk sampling (Sec. 3.4;
+ * host code, no GPU work). The liquid region of the grid p describes (dim, nx, ny, nz,
+ * periodic, gas_from) is filled by the active-list method: sites are sphere centres with
+ * radii uniform in [r_min, r_max]; two sites keep |x_i - x_j| >= r_i + r_j + gap (the spheres
+ * never overlap and gap cells of liquid separate them; distances wrap on periodic axes); each
+ * sphere stays one cell clear of the wall layers and of the headspace; each site tries
+ * `attempts` candidates in the shell [d, 2d], d = r_i + r_new + gap, around it. The field prob
+ * (host, one value in [0, 1] per cell in cell order, x fastest; NULL: all ones) then thins the
+ * filled set: in placement order a site is kept with the probability of its nearest cell,
+ * until max_n are kept. centers (host, max_n x 3, z = 0 in 2D) and radii (host, max_n) receive
+ * the kept sites in order and *n_out their number; the result depends only on the arguments
+ * (SplitMix64 stream from seed, binary64 arithmetic without contraction). MF_EINVAL on a bad
+ * grid, r_min <= 0, r_max < r_min, gap < 0, attempts < 1, max_n < 0 or a field value outside
+ * [0, 1]. Feed the sites to mf_nucleate. */
+int mf_poisson_nuclei(const mf_params *p, const float *prob, int32_t max_n, double r_min, double r_max,
+                      double gap, int32_t attempts, uint64_t seed, double *centers, double *radii,
+                      int32_t *n_out);
+
 /* Advance nsteps time steps (enqueued on the context stream; returns without waiting).
  * Each step: stream / collide f and g, interface mass exchange, Henry's-law and
  * free-surface reconstruction, cell conversion with excess redistribution, bubble

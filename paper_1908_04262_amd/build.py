@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmifoam.so")
-SOURCES = ["capi.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "convert.hip", "label.hip", "geometry.hip", "init.hip", "mlp.hip"]
+SOURCES = ["capi.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_f16.hip", "convert.hip", "label.hip", "geometry.hip", "init.hip", "mlp.hip", "nucleate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -64,7 +64,7 @@ EXPORTS = ["mf_abi_version", "mf_last_error", "mf_workspace_bytes", "mf_create",
            "mf_mlp_destroy", "mf_mlp_train", "mf_mlp_get_params", "mf_mlp_set_params",
            "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_grad", "mf_attach_mlp", "mf_tune",
            "mf_set_sweep_variant", "mf_batch_create", "mf_batch_tune", "mf_batch_step",
-           "mf_batch_destroy"]
+           "mf_batch_destroy", "mf_poisson_nuclei"]
 SWEEP_VARIANTS = 4
 
 _LIB = None
@@ -110,6 +110,8 @@ def load_library():
     lib.mf_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp]
     lib.mf_attach_mlp.argtypes = [vp, vp]
     lib.mf_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), vp]
+    lib.mf_poisson_nuclei.argtypes = [C.POINTER(MfParams), vp, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                      C.c_int32, C.c_uint64, vp, vp, C.POINTER(C.c_int32)]
     lib.mf_set_sweep_variant.argtypes = [vp, C.c_int32]
     lib.mf_batch_create.argtypes = [C.c_int32, vp, C.POINTER(vp)]
     lib.mf_batch_tune.argtypes = [vp, C.c_int32, vp]
@@ -145,6 +147,32 @@ def make_params(wl: dict) -> MfParams:
 
 class MifoamError(RuntimeError):
     pass
+
+
+def poisson_nuclei(wl: dict, prob=None, max_n=1 << 20, r_min=2.0, r_max=4.0, gap=1.0, attempts=30, seed=0):
+    """Nucleation sites of the grid wl describes, by Poisson-disk sampling of the
+    probability field prob (host array of one value per cell, x fastest; None: all ones).
+    Returns (centres [n, 3], radii [n]) as float64 arrays; host code only."""
+    import numpy as np
+
+    lib = load_library()
+    p = make_params(wl)
+    pr = None
+    if prob is not None:
+        pr = np.ascontiguousarray(prob, dtype=np.float32).ravel()
+        ncell = int(p.nx) * int(p.ny) * (int(p.nz) if int(p.dim) == 3 else 1)
+        if pr.size != ncell:
+            raise ValueError(f"prob holds {pr.size} values, the grid {ncell} cells")
+    cap = int(max_n)
+    cen = np.zeros((max(cap, 1), 3), np.float64)
+    rad = np.zeros(max(cap, 1), np.float64)
+    n = C.c_int32()
+    rc = lib.mf_poisson_nuclei(C.byref(p), None if pr is None else pr.ctypes.data, cap, float(r_min), float(r_max),
+                               float(gap), int(attempts), int(seed) & ((1 << 64) - 1), cen.ctypes.data,
+                               rad.ctypes.data, C.byref(n))
+    if rc != 0:
+        raise MifoamError(f"mf_poisson_nuclei failed with status {rc}")
+    return cen[: n.value].copy(), rad[: n.value].copy()
 
 
 class Sim:
