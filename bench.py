@@ -122,6 +122,24 @@ def train_net(n_train, epochs, log):
                      val_rmse_kappa=round(rmse, 5))
 
 
+def time_field_nucleation(wl, log):
+    """Host time of the Poisson-disk nucleation sampler on the benchmark grid: the liquid
+    region filled with sites of radius U[2, 4] at least r_i + r_j + 1 apart, then thinned by a
+    field that rises linearly along x from 0.1 to 1, keeping up to 2000 sites."""
+    import numpy as np
+
+    from paper_1908_04262_amd import poisson_nuclei
+
+    nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
+    P = np.broadcast_to(np.linspace(0.1, 1.0, nx, dtype=np.float32), (nz, ny, nx))
+    t0 = time.perf_counter()
+    c, r = poisson_nuclei(wl, P, 2000, 2.0, 4.0, 1.0, 30, wl["seed"])
+    dt = time.perf_counter() - t0
+    log(f"[nucleation] {len(r)} sites from the field in {dt:.2f}s")
+    return {"sites": int(len(r)), "seconds": round(dt, 3), "grid": [nx, ny, nz], "r": [2.0, 4.0],
+            "field": "linear in x from 0.1 to 1", "host": True}
+
+
 def run_one(wl, steps, warmup, log, net=None):
     import numpy as np
     import torch
@@ -312,6 +330,7 @@ def main():
     cy = dict(rheology="carreau_yasuda", cy_tau0=1.2, cy_tau_inf=0.6, cy_lambda=1000.0, cy_a=2.0, cy_n=0.4)
     r16c = run_one(dict(wl, precision="f16s_g16", curvature="mlp", **cy), max(a.steps // 2, 1),
                    a.warmup, log, net=net)
+    nuc = time_field_nucleation(wl, log)
     ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
 
@@ -365,6 +384,7 @@ def main():
                          "frac": round(r16["bulk_isolated_gbs"] / HBM_PEAK_GBS, 4),
                          "avg_launch_ms": round(r16["bulk_isolated_ms"], 4)},
         },
+        "field_nucleation": nuc,
         "batched_ensemble": ens,
         "cpu_baseline": cpu,
     }
