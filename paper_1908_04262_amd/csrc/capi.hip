@@ -34,6 +34,8 @@ struct OpsTable {
   void (*read_field)(Ctx &, hipStream_t, int, double *);
   void (*write_field)(Ctx &, hipStream_t, int, const double *);
   bool (*sweep_bulk)(Ctx &, hipStream_t, int);
+  void (*geometry_normals)(Ctx &, hipStream_t, bool);
+  void (*geometry_curv)(Ctx &, hipStream_t);
 };
 
 template <int D, int P>
@@ -41,7 +43,7 @@ OpsTable make_ops() {
   return OpsTable{&Ops<D, P>::sweep,    &Ops<D, P>::convert,     &Ops<D, P>::label,
                   &Ops<D, P>::geometry, &Ops<D, P>::init_box,    &Ops<D, P>::nucleate,
                   &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field,
-                  &Ops<D, P>::sweep_bulk};
+                  &Ops<D, P>::sweep_bulk,  &Ops<D, P>::geometry_normals, &Ops<D, P>::geometry_curv};
 }
 
 OpsTable ops_for(int dim, int prec) {
@@ -292,6 +294,13 @@ struct mf_ctx : Ctx {
 
 static void destroy_side(mf_ctx *c) {
   if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->side2) (void)hipStreamSynchronize(c->side2);
+  if (c->side2) (void)hipStreamDestroy(c->side2);
+  if (c->ev_lab) (void)hipEventDestroy(c->ev_lab);
+  if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+  if (c->ev_list) (void)hipEventDestroy(c->ev_list);
+  c->side2 = nullptr;
+  c->ev_lab = c->ev_start = c->ev_list = nullptr;
   if (c->ev_conv) (void)hipEventDestroy(c->ev_conv);
   if (c->ev_side) (void)hipEventDestroy(c->ev_side);
   if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
@@ -303,6 +312,10 @@ static void destroy_side(mf_ctx *c) {
 // the context stream waits for the labelling and geometry the last step left running on
 // the side stream
 static void join_side(mf_ctx *c) {
+  if (c->list_pending) {
+    (void)hipStreamWaitEvent(c->stream, c->ev_list, 0);
+    c->list_pending = false;
+  }
   if (!c->side_pending) return;
   (void)hipStreamWaitEvent(c->stream, c->ev_side, 0);
   c->side_pending = false;
@@ -371,6 +384,10 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_conv, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_norm, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_lab, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_list, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking);
     if (e != hipSuccess) {
       g_err = std::string("creating the side stream failed: ") + hipGetErrorString(e);
       destroy_side(c);
@@ -471,8 +488,11 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 // populations and the wall mask, which labelling and geometry leave alone, and write the
 // populations and this step parity's counters and interface list; the interface sweep,
 // the first kernel that reads labels, bubble pressures and curvature, waits for the side
-// stream. The bulk sweep itself waits for the labelling and normals, so that the learned-
-// curvature kernel is dispatched beside it rather than into a GPU it already fills. The
+// stream. The normals read no ids and run beside the labelling on a third stream (the
+// excess pass has already written the stencil words). The bulk sweep itself waits for the
+// labelling and the normals, so that the learned-curvature kernel is dispatched beside it
+// rather than into a GPU it already fills. A step whose stencil words need the whole-grid
+// pass takes the plain order. The
 // caller joins what the last step left running (join_side) before anything else touches
 // the state. Graph capture takes the plain order: there the domains already run as
 // parallel branches.
@@ -480,21 +500,44 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
   c->parity ^= 1;
   select_parity(c);
   if (ev) (void)hipEventRecord(ev[0], c->stream);
-  reset_counters(c);
-  c->ops.build_lists(*c, c->stream);
-  if (c->side_pending) (void)hipStreamWaitEvent(c->stream, c->ev_norm, 0);
-  if (ev) (void)hipEventRecord(ev[1], c->stream);  // after the wait: times the bulk kernel alone
+  const bool lists_aside = overlap && !c->sword_dirty;
+  if (lists_aside) {
+    // the bulk sweep does not read the interface list: the third stream builds it (after
+    // the previous step's normals there), and the interface sweep waits for it
+    (void)hipEventRecord(c->ev_start, c->stream);
+    (void)hipStreamWaitEvent(c->side2, c->ev_start, 0);
+    hipStream_t own = c->stream;
+    c->stream = c->side2;
+    reset_counters(c);
+    c->ops.build_lists(*c, c->side2);
+    c->stream = own;
+    (void)hipEventRecord(c->ev_list, c->side2);
+  } else {
+    reset_counters(c);
+    c->ops.build_lists(*c, c->stream);
+  }
+  if (c->side_pending) {
+    (void)hipStreamWaitEvent(c->stream, c->ev_lab, 0);
+    (void)hipStreamWaitEvent(c->stream, c->ev_norm, 0);
+  }
+  if (ev) (void)hipEventRecord(ev[1], c->stream);  // after the waits: times the bulk kernel alone
+  c->list_pending = lists_aside;
   c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, &join_side_cb, c);
   if (ev) (void)hipEventRecord(ev[4], c->stream);
   c->cur ^= 1;
   c->ops.convert(*c, c->stream);
-  if (overlap) {
+  if (overlap && !c->sword_dirty) {
     (void)hipEventRecord(c->ev_conv, c->stream);
     (void)hipStreamWaitEvent(c->side, c->ev_conv, 0);
+    (void)hipStreamWaitEvent(c->side2, c->ev_conv, 0);
     c->ops.label(*c, c->side, 1);
+    (void)hipEventRecord(c->ev_lab, c->side);
+    // the normals read no ids: they run beside the labelling, on the third stream
     c->ev_norm_rec = c->ev_norm;
-    c->ops.geometry(*c, c->side);
+    c->ops.geometry_normals(*c, c->side2, !c->sword_fresh);
     c->ev_norm_rec = nullptr;
+    (void)hipStreamWaitEvent(c->side, c->ev_norm, 0);
+    c->ops.geometry_curv(*c, c->side);
     if (ev) (void)hipEventRecord(ev[5], c->side);
     (void)hipEventRecord(c->ev_side, c->side);
     c->side_pending = true;

@@ -278,7 +278,10 @@ __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
 }
 
 // Every interface cell of the new types gathers the shares of its converted neighbours in
-// ascending direction order; alpha = M / rho. On a step whose conversions leave every
+// ascending direction order; alpha = M / rho. With the learned curvature, the pass also
+// writes the stencil word of every list cell (converted ones included), whose type, fill
+// fraction or id may have changed this step; the labelling that follows changes ids only
+// when it relabels, and then rewrites the words of every gas and interface cell itself. On a step whose conversions leave every
 // bubble as it was (the topology test passed), the same pass adds each interface cell's
 // volume share 1 - alpha to its bubble (fixed point; the gas cells are counted apart),
 // and it clears the conversion flags of the cells it visits (the converted cells, whose
@@ -300,6 +303,8 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
     if (k < total) {
       const int64_t n = k < nI ? d.ilist[k] : (k < (int64_t)nI + nNI ? d.nilist[k - nI] : d.l2ilist[k - nI - nNI]);
       const uint8_t cl = d.cflag[n];
+      if (d.sword && k < nI && (cl & (CF_FILL | CF_EMPTY)))
+        d.sword[n] = stencil_word<R>(d.type[n], ((const R *)d.alpha)[n], d.label[n]);
       if (!(k < nI && (cl & (CF_FILL | CF_EMPTY)))) {
         R acc = ((const R *)d.M)[n];
         if (cl & CF_EXNB) {  // next to a converted cell
@@ -314,6 +319,7 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
         ((R *)d.M)[n] = acc;
         ((R *)d.alpha)[n] = al;
         d.cflag[n] = 0;
+        if (d.sword) d.sword[n] = stencil_word<R>(d.type[n], al, d.label[n]);
         if (fast) {
           lab = d.label[n];
           if (lab > 0 && lab < p.cap) {
@@ -518,6 +524,7 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_conv_clear, dim3(nb), dim3(256), 0, s, c.d);
+  c.sword_fresh = c.d.sword != nullptr;  // the excess pass wrote the list cells' stencil words
 }
 
 #define MF_INST(D, P) template void Ops<D, P>::convert(Ctx &, hipStream_t);

@@ -158,14 +158,15 @@ __device__ __forceinline__ R alpha_seen(const DA &d, int64_t y, R ac) {
            : (k < (int64_t)_nI + _nNI ? (int64_t)d.nilist[k - _nI] : (int64_t)d.l2ilist[k - _nI - _nNI]))
 
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_normals(KP p, DA d, int sword_all) {
+__global__ __launch_bounds__(256) void k_normals(KP p, DA d, int words) {
   using R = typename Prec<P>::R;
   NEWI_LOOP(k, n) {
     const int64_t n = NEWI_CELL(k);
     const uint8_t tb = d.type[n];
     // the cells of this step's lists are the ones whose type or fill fraction changed:
-    // their stencil words (learned curvature) follow here
-    if (d.sword && !sword_all) d.sword[n] = stencil_word<R>(tb, ((const R *)d.alpha)[n], d.label[n]);
+    // their stencil words (learned curvature) follow here, unless the excess pass of the
+    // time step or a whole-grid pass has written them
+    if (words) d.sword[n] = stencil_word<R>(tb, ((const R *)d.alpha)[n], d.label[n]);
     if ((tb & TMASK) != TI) continue;
     int x, y, z;
     cell_xyz(p, n, x, y, z);
@@ -447,25 +448,43 @@ __global__ __launch_bounds__(256) void k_sword_all(KP p, DA d) {
     d.sword[n] = stencil_word<R>(d.type[n], ((const R *)d.alpha)[n], d.label[n]);
 }
 
+// Normals (and the stencil words of the list cells when nothing else has written them);
+// they read fill fractions and types only, not ids, so they may run beside the labelling.
+template <int D, int P>
+void Ops<D, P>::geometry_normals(Ctx &c, hipStream_t s, bool words) {
+  hipLaunchKernelGGL((k_normals<D, P>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, words && c.d.sword ? 1 : 0);
+  if (c.ev_norm_rec) (void)hipEventRecord(c.ev_norm_rec, s);
+}
+
+// Curvature (learned, then the plain fit where the network gave nothing), disjoining
+// pressure and the gas side of the interface cells; after the labelling and the normals.
+template <int D, int P>
+void Ops<D, P>::geometry_curv(Ctx &c, hipStream_t s) {
+  if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
+  hipLaunchKernelGGL((k_curvature<D, P>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d);
+  c.gas_dirty = false;
+  c.sword_fresh = false;
+}
+
 template <int D, int P>
 void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
-  const unsigned nb = list_blocks(c);
   // stencil words: over the whole grid after a state change made outside the time step,
-  // else with the normals (this step's list cells) and the relabelling (bubble cells)
-  const int sword_all = c.d.sword && c.sword_dirty;
+  // else from the excess pass of the step or, outside a step, with the normals
+  const bool sword_all = c.d.sword && c.sword_dirty;
   if (sword_all) {
     const int64_t g = (c.kp.N + 255) / 256;
     hipLaunchKernelGGL((k_sword_all<P>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, c.kp, c.d);
     c.sword_dirty = false;
   }
-  hipLaunchKernelGGL((k_normals<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, sword_all);
-  if (c.ev_norm_rec) (void)hipEventRecord(c.ev_norm_rec, s);
-  if (c.kp.curvature == MF_CURV_MLP && c.d.mlp_w) launch_mlp_curv(c, s);
-  hipLaunchKernelGGL((k_curvature<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  c.gas_dirty = false;
+  geometry_normals(c, s, !sword_all && !c.sword_fresh);
+  geometry_curv(c, s);
 }
 
-#define MF_INST(D, P) template void Ops<D, P>::geometry(Ctx &, hipStream_t);
+#define MF_INST(D, P)                                                     \
+  template void Ops<D, P>::geometry(Ctx &, hipStream_t);                  \
+  template void Ops<D, P>::geometry_normals(Ctx &, hipStream_t, bool);    \
+  template void Ops<D, P>::geometry_curv(Ctx &, hipStream_t);
+
 MF_FOR_ALL(MF_INST)
 
 }  // namespace mf

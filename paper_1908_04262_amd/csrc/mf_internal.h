@@ -395,6 +395,10 @@ template <int D, int P> struct Ops {
   static void convert(Ctx &c, hipStream_t s);
   static void label(Ctx &c, hipStream_t s, int apply_flux);
   static void geometry(Ctx &c, hipStream_t s);
+  // the two halves of geometry(): normals (words: also the list cells' stencil words), and
+  // curvature + disjoining pressure + gas side
+  static void geometry_normals(Ctx &c, hipStream_t s, bool words);
+  static void geometry_curv(Ctx &c, hipStream_t s);
   static void init_box(Ctx &c, hipStream_t s);
   static void nucleate(Ctx &c, hipStream_t s, int n, const double *centers, const double *radii);
   static void build_lists(Ctx &c, hipStream_t s);
@@ -431,7 +435,11 @@ struct Ctx {
   int32_t *cnt_base = nullptr, *ilist_base = nullptr;
   int parity = 0;
   hipStream_t side = nullptr;
-  hipEvent_t ev_conv = nullptr, ev_side = nullptr, ev_norm = nullptr, ev_norm_rec = nullptr;
+  hipStream_t side2 = nullptr;  // the normals, beside the labelling on the side stream
+  hipEvent_t ev_conv = nullptr, ev_side = nullptr, ev_norm = nullptr, ev_norm_rec = nullptr, ev_lab = nullptr;
+  bool sword_fresh = false;     // the excess pass of this step wrote the list cells' stencil words
+  hipEvent_t ev_start = nullptr, ev_list = nullptr;  // step start (context stream), list built (third stream)
+  bool list_pending = false;    // the interface sweep must wait for ev_list
   bool side_pending = false;  // ev_side marks side-stream work the main stream has not joined
 };
 
