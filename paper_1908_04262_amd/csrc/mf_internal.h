@@ -425,13 +425,14 @@ struct Ctx {
   std::string err;
   bool prof = false;
   void *mlp_buf = nullptr;  // device copy of the attached network's weights
-  // Steps overlap: the labelling and geometry of step n run on the side stream while the
-  // main stream builds the lists and runs the bulk sweep of step n+1 (neither reads what
-  // the other writes); the interface sweep of step n+1 waits for ev_side. Counters and
-  // the interface list alternate between two copies by step parity. The bulk sweep starts
-  // once the labelling and normals are done (ev_norm): the learned-curvature kernel is
-  // then dispatched beside it instead of into a GPU the bulk sweep already fills.
-  // geometry() records ev_norm_rec, when set, after the normals.
+  // Steps overlap: the labelling and curvature of step n run on the side stream, its
+  // normals and then the counter reset and interface-list build of step n+1 on side2, while
+  // the main stream runs the bulk sweep of step n+1 (none of them reads what another
+  // writes). Counters and the interface list alternate between two copies by step parity.
+  // The bulk sweep starts once the labelling (ev_lab) and the normals (ev_norm) are done,
+  // so that the learned-curvature kernel is dispatched beside it instead of into a GPU the
+  // bulk sweep already fills; the interface sweep waits for the side stream (ev_side) and
+  // the list build (ev_list). geometry_normals() records ev_norm_rec, when set.
   int32_t *cnt_base = nullptr, *ilist_base = nullptr;
   int parity = 0;
   hipStream_t side = nullptr;
