@@ -24,7 +24,6 @@ namespace {
 std::string &g_err = mf::g_thread_err;
 
 struct OpsTable {
-  void (*sweep)(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
   void (*convert)(Ctx &, hipStream_t);
   void (*label)(Ctx &, hipStream_t, int);
   void (*geometry)(Ctx &, hipStream_t);
@@ -36,14 +35,18 @@ struct OpsTable {
   bool (*sweep_bulk)(Ctx &, hipStream_t, int);
   void (*geometry_normals)(Ctx &, hipStream_t, bool);
   void (*geometry_curv)(Ctx &, hipStream_t);
+  bool (*sweep_bulk_auto)(Ctx &, hipStream_t);
+  void (*sweep_interface)(Ctx &, hipStream_t);
+  void (*sweep_cells)(Ctx &, hipStream_t);
 };
 
 template <int D, int P>
 OpsTable make_ops() {
-  return OpsTable{&Ops<D, P>::sweep,    &Ops<D, P>::convert,     &Ops<D, P>::label,
+  return OpsTable{&Ops<D, P>::convert,     &Ops<D, P>::label,
                   &Ops<D, P>::geometry, &Ops<D, P>::init_box,    &Ops<D, P>::nucleate,
                   &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field,
-                  &Ops<D, P>::sweep_bulk,  &Ops<D, P>::geometry_normals, &Ops<D, P>::geometry_curv};
+                  &Ops<D, P>::sweep_bulk,  &Ops<D, P>::geometry_normals, &Ops<D, P>::geometry_curv,
+                  &Ops<D, P>::sweep_bulk_auto, &Ops<D, P>::sweep_interface, &Ops<D, P>::sweep_cells};
 }
 
 OpsTable ops_for(int dim, int prec) {
@@ -321,7 +324,6 @@ static void join_side(mf_ctx *c) {
   c->side_pending = false;
 }
 
-static void join_side_cb(void *arg) { join_side((mf_ctx *)arg); }
 
 extern "C" {
 
@@ -483,27 +485,24 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 
 // one time step, enqueued on the context stream (host work: launches only, so that it
 // can be captured into a graph); ev: kStepEvents profiling events or NULL.
-// With overlap, the labelling and geometry of the step go to the side stream, where they
-// run beside the list build and bulk sweep of the next step. Those read only cell types,
-// populations and the wall mask, which labelling and geometry leave alone, and write the
-// populations and this step parity's counters and interface list; the interface sweep,
-// the first kernel that reads labels, bubble pressures and curvature, waits for the side
-// stream. The normals read no ids and run beside the labelling on a third stream (the
-// excess pass has already written the stencil words). The bulk sweep itself waits for the
-// labelling and the normals, so that the learned-curvature kernel is dispatched beside it
-// rather than into a GPU it already fills. A step whose stencil words need the whole-grid
-// pass takes the plain order. The
-// caller joins what the last step left running (join_side) before anything else touches
-// the state. Graph capture takes the plain order: there the domains already run as
-// parallel branches.
+// With overlap, a step runs on three streams of the context. The context stream takes the
+// sweep and the conversions. After the conversions, the side stream takes the labelling
+// and the curvature, and the third stream the normals (they read no ids: the excess pass
+// has written the stencil words) and then the next step's counter reset and interface-list
+// build. The next bulk sweep reads only cell types, populations and the wall mask, so it
+// runs beside all of that; it waits for the labelling and the normals, so that the
+// learned-curvature kernel is dispatched beside it rather than into a GPU it already
+// fills. The interface sweep, the first kernel that reads ids, bubble pressures,
+// curvature and the new list, waits for both side streams. The caller joins what the last
+// step left running (join_side) before anything else touches the state. A step whose
+// stencil words need the whole-grid pass, and graph capture (where the domains already
+// run as parallel branches), take the plain order.
 static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
   c->parity ^= 1;
   select_parity(c);
   if (ev) (void)hipEventRecord(ev[0], c->stream);
-  const bool lists_aside = overlap && !c->sword_dirty;
-  if (lists_aside) {
-    // the bulk sweep does not read the interface list: the third stream builds it (after
-    // the previous step's normals there), and the interface sweep waits for it
+  const bool aside = overlap && !c->sword_dirty;
+  if (aside) {
     (void)hipEventRecord(c->ev_start, c->stream);
     (void)hipStreamWaitEvent(c->side2, c->ev_start, 0);
     hipStream_t own = c->stream;
@@ -512,6 +511,7 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
     c->ops.build_lists(*c, c->side2);
     c->stream = own;
     (void)hipEventRecord(c->ev_list, c->side2);
+    c->list_pending = true;
   } else {
     reset_counters(c);
     c->ops.build_lists(*c, c->stream);
@@ -521,18 +521,29 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
     (void)hipStreamWaitEvent(c->stream, c->ev_norm, 0);
   }
   if (ev) (void)hipEventRecord(ev[1], c->stream);  // after the waits: times the bulk kernel alone
-  c->list_pending = lists_aside;
-  c->ops.sweep(*c, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, &join_side_cb, c);
-  if (ev) (void)hipEventRecord(ev[4], c->stream);
+  if (c->ops.sweep_bulk_auto(*c, c->stream)) {
+    if (ev) (void)hipEventRecord(ev[2], c->stream);
+    join_side(c);
+    if (ev) (void)hipEventRecord(ev[3], c->stream);
+    c->ops.sweep_interface(*c, c->stream);
+    if (ev) (void)hipEventRecord(ev[4], c->stream);
+  } else {
+    join_side(c);
+    c->ops.sweep_cells(*c, c->stream);
+    if (ev) {
+      (void)hipEventRecord(ev[2], c->stream);
+      (void)hipEventRecord(ev[3], c->stream);
+      (void)hipEventRecord(ev[4], c->stream);
+    }
+  }
   c->cur ^= 1;
   c->ops.convert(*c, c->stream);
-  if (overlap && !c->sword_dirty) {
+  if (aside) {
     (void)hipEventRecord(c->ev_conv, c->stream);
     (void)hipStreamWaitEvent(c->side, c->ev_conv, 0);
     (void)hipStreamWaitEvent(c->side2, c->ev_conv, 0);
     c->ops.label(*c, c->side, 1);
     (void)hipEventRecord(c->ev_lab, c->side);
-    // the normals read no ids: they run beside the labelling, on the third stream
     c->ev_norm_rec = c->ev_norm;
     c->ops.geometry_normals(*c, c->side2, !c->sword_fresh);
     c->ev_norm_rec = nullptr;

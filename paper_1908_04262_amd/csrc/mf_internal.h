@@ -382,13 +382,13 @@ __device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y,
 // every kernel family is a template over (D, P); the dispatcher picks one instance
 struct Ctx;
 template <int D, int P> struct Ops {
-  // the lattice sweep: the bulk kernel, then between(arg) (host code that may enqueue
-  // more work on s), then the interface / near-wall kernel, the first one that reads the
-  // labels and geometry; the events (each may be NULL) are recorded at the end of the bulk
-  // kernel and at the start of the interface kernel. Domains swept by the per-cell kernel
-  // run between(arg) first and record both events after that kernel.
-  static void sweep(Ctx &c, hipStream_t s, hipEvent_t bulk_end, hipEvent_t special_start,
-                    void (*between)(void *), void *arg);
+  // the lattice sweep: the bulk kernel (liquid cells; false when the domain takes the
+  // per-cell kernel instead), the interface kernel (this step's interface list; after the
+  // bulk kernel, whose whole-group stores cover interface cells too), and the per-cell
+  // kernel over the whole grid
+  static bool sweep_bulk_auto(Ctx &c, hipStream_t s);
+  static void sweep_interface(Ctx &c, hipStream_t s);
+  static void sweep_cells(Ctx &c, hipStream_t s);
   // one launch of the bulk sweep kernel in tuning variant v (see kSweepVariants); false
   // when the variant does not apply to this domain (nothing launched)
   static bool sweep_bulk(Ctx &c, hipStream_t s, int v);

@@ -5,16 +5,28 @@
 #include "sweep_impl.h"
 
 namespace mf {
-template void Ops<2, 2>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<2, 2>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<2, 2>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<2, 2>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<2, 2>::sweep_bulk(Ctx &, hipStream_t, int);
-template void Ops<2, 3>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<2, 3>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<2, 3>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<2, 3>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<2, 3>::sweep_bulk(Ctx &, hipStream_t, int);
-template void Ops<2, 4>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<2, 4>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<2, 4>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<2, 4>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<2, 4>::sweep_bulk(Ctx &, hipStream_t, int);
-template void Ops<3, 2>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<3, 2>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<3, 2>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<3, 2>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<3, 2>::sweep_bulk(Ctx &, hipStream_t, int);
-template void Ops<3, 3>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<3, 3>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<3, 3>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<3, 3>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<3, 3>::sweep_bulk(Ctx &, hipStream_t, int);
-template void Ops<3, 4>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<3, 4>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<3, 4>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<3, 4>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<3, 4>::sweep_bulk(Ctx &, hipStream_t, int);
 }  // namespace mf

@@ -4,8 +4,12 @@
 #include "sweep_impl.h"
 
 namespace mf {
-template void Ops<2, 1>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<2, 1>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<2, 1>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<2, 1>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<2, 1>::sweep_bulk(Ctx &, hipStream_t, int);
-template void Ops<3, 1>::sweep(Ctx &, hipStream_t, hipEvent_t, hipEvent_t, void (*)(void *), void *);
+template bool Ops<3, 1>::sweep_bulk_auto(Ctx &, hipStream_t);
+template void Ops<3, 1>::sweep_interface(Ctx &, hipStream_t);
+template void Ops<3, 1>::sweep_cells(Ctx &, hipStream_t);
 template bool Ops<3, 1>::sweep_bulk(Ctx &, hipStream_t, int);
 }  // namespace mf

@@ -726,11 +726,13 @@ __device__ __forceinline__ void sweep_vec_body(const KP &p, const DA &d, int cur
 
   // Whole-group streaming (non-temporal) stores for every lane holding a liquid cell: the
   // populations are read again only in the next step, after gigabytes of other traffic,
-  // so they are kept out of the caches. The other cells of the group
-  // receive values that nothing reads: populations of wall and gas cells are never used
-  // (bounce-back and the gas-side rebuild take the receiving cell's own values, and a
-  // gas cell that turns interface is initialised afresh), and interface cells are
-  // rewritten by the interface kernel that follows.
+  // so they are kept out of the caches. The wall and gas cells of the group receive values
+  // that nothing reads (bounce-back and the gas-side rebuild take the receiving cell's own
+  // values, and a gas cell that turns interface is initialised afresh); interface cells
+  // are rewritten by the interface kernel, which runs after this one. (Storing the liquid
+  // cells of groups that hold an interface cell one by one would let the two kernels run
+  // together, but nearly every wave holds such a group, and the per-cell stores cost the
+  // bulk kernel a quarter of its rate.)
   SF *fout = (SF *)d.f[cur ^ 1];
   SG *gout = (SG *)d.g[cur ^ 1];
   if (anyliquid) {
@@ -787,27 +789,34 @@ bool Ops<D, P>::sweep_bulk(Ctx &c, hipStream_t s, int variant) {
   }
 }
 
+// the bulk kernel in the tuned launch shape (the default one when none was tuned or the
+// tuned one does not apply); false when the domain takes the per-cell kernel instead
 template <int D, int P>
-void Ops<D, P>::sweep(Ctx &c, hipStream_t s, hipEvent_t bulk_end, hipEvent_t special_start,
-                      void (*between)(void *), void *arg) {
-  if constexpr (P != 0) {
+bool Ops<D, P>::sweep_bulk_auto(Ctx &c, hipStream_t s) {
+  if constexpr (P == 0) {
+    return false;
+  } else {
     const int v = c.sweep_variant >= 0 ? c.sweep_variant : default_variant<P>();
-    if (sweep_bulk(c, s, v) || (v != default_variant<P>() && sweep_bulk(c, s, default_variant<P>()))) {
-      if (bulk_end) (void)hipEventRecord(bulk_end, s);
-      if (between) between(arg);
-      if (special_start) (void)hipEventRecord(special_start, s);
-      if (c.kp.force) hipLaunchKernelGGL((k_sweep_special<D, P, true>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
-      else hipLaunchKernelGGL((k_sweep_special<D, P, false>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
-      return;
-    }
+    return sweep_bulk(c, s, v) || (v != default_variant<P>() && sweep_bulk(c, s, default_variant<P>()));
   }
+}
+
+// the interface kernel (this step's interface list) of a domain swept by the bulk kernel;
+// it runs after the bulk kernel, whose whole-group stores also cover interface cells
+template <int D, int P>
+void Ops<D, P>::sweep_interface(Ctx &c, hipStream_t s) {
+  if constexpr (P == 0) return;  // binary64 domains take the per-cell kernel
+  if (c.kp.force) hipLaunchKernelGGL((k_sweep_special<D, P, true>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
+  else hipLaunchKernelGGL((k_sweep_special<D, P, false>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
+}
+
+// the per-cell kernel over the whole grid (binary64 and periodic domains)
+template <int D, int P>
+void Ops<D, P>::sweep_cells(Ctx &c, hipStream_t s) {
   const int gx = (c.kp.nx + 63) / 64, gy = (c.kp.ny + 3) / 4;
   const int64_t nb = (int64_t)gx * gy * c.kp.nz;
-  if (between) between(arg);
   if (c.kp.force) hipLaunchKernelGGL((k_sweep<D, P, true>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
   else hipLaunchKernelGGL((k_sweep<D, P, false>), dim3((unsigned)nb), dim3(256), 0, s, c.kp, c.d, c.cur);
-  if (bulk_end) (void)hipEventRecord(bulk_end, s);
-  if (special_start) (void)hipEventRecord(special_start, s);
 }
 
 }  // namespace mf
