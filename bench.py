@@ -307,8 +307,8 @@ def main():
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sweep shards by z-slabs; that path is not built).", file=sys.stderr)
+        print("bench.py runs on one GPU only: mifoam has no multi-GPU path "
+              "(a domain would shard by z-slabs; that path is not built).", file=sys.stderr)
         sys.exit(2)
 
     def log(msg):
