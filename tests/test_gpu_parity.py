@@ -280,3 +280,32 @@ def test_neck_fill_split_matches_oracle(neck_rows):
     nb = len(orc.bubbles()["id"])
     _say("  bubbles after 3 steps:", nb)
     assert nb == (2 if neck_rows == 1 else 1)
+
+
+def test_split_beyond_table_capacity_is_reported():
+    """The same one-row neck with a bubble table of two ids (the atmosphere and one bubble):
+    the split on the first step needs a third id. The labelling's own capacity check raises
+    the device status flag, and the next synchronisation reports MF_ECAPACITY with the
+    table message, on the step where the oracle stops with its capacity error."""
+    from paper_1908_04262_amd.mifoam import MifoamError
+    wl = _mk(name="neck_cap", dim=2, nx=16, ny=11, nz=1, gas_from=-1, nuclei=None, S0=1.2, tau=0.8,
+             sigma=1e-3, max_ids=2)
+    orc = Oracle(wl)
+    gpu = _sim(wl)
+    T, lab, al = _dumbbell(1)
+    for o in (orc, gpu):
+        o.write("type", T)
+        o.write("label", lab)
+        o.write("mass", al)
+        o.write("alpha", al)
+        o.write("rho", np.ones_like(al))
+        o.set_bubble(1, 0.2, 20.0, 1 / 3)
+    orc.geometry()
+    gpu.refresh(relabel=False)
+    _say("split beyond a two-id table")
+    with pytest.raises(RuntimeError, match="capacity exceeded"):
+        orc.step(1)
+    gpu.step(1)
+    with pytest.raises(MifoamError, match="MF_ECAPACITY.*capacity exceeded"):
+        gpu.sync()
+    gpu.close()
