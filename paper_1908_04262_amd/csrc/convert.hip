@@ -314,11 +314,11 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
             const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
             if (d.cflag[yy] & (CF_FILL | CF_EMPTY)) acc = acc + ((const R *)d.exc)[yy];
           }
+          ((R *)d.M)[n] = acc;
         }
         const R al = acc / ((const R *)d.rho)[n];
-        ((R *)d.M)[n] = acc;
         ((R *)d.alpha)[n] = al;
-        d.cflag[n] = 0;
+        if (cl) d.cflag[n] = 0;  // most list cells carry no flag: their lines stay clean
         if (d.sword) d.sword[n] = stencil_word<R>(d.type[n], al, d.label[n]);
         if (fast) {
           lab = d.label[n];
