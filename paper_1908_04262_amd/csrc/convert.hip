@@ -514,16 +514,20 @@ __global__ __launch_bounds__(256) void k_topo_window(KP p, DA d) {
 template <int D, int P>
 void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   const unsigned nb = list_blocks(c);
+  // the passes over the short lists (converted cells and their new neighbours) take at
+  // most four work-groups per CU: their entries are dealt one per wave, and a larger grid
+  // only costs dispatch time on the step's critical path
+  const unsigned ns = nb < 1024 ? nb : 1024;
   const int cur = c.cur;  // buffer holding this step's post-collision populations
-  hipLaunchKernelGGL((k_fill_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL((k_empty_scatter<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL((k_apply<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
-  hipLaunchKernelGGL((k_topo_check<D>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_fill_scatter<D>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_empty_scatter<D>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_apply<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_topo_check<D>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_topo_window<D>), dim3(256), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL((k_ni_init<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d, cur);
-  hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
+  hipLaunchKernelGGL((k_ni_init<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL(k_conv_clear, dim3(nb), dim3(256), 0, s, c.d);
+  hipLaunchKernelGGL(k_conv_clear, dim3(ns), dim3(256), 0, s, c.d);
   c.sword_fresh = c.d.sword != nullptr;  // the excess pass wrote the list cells' stencil words
 }
 
