@@ -8,6 +8,24 @@
 
 namespace mf {
 
+// slots for n entries of each lane, taken with one atomic per wave (called by the whole
+// wave); returns the lane's first slot
+__device__ __forceinline__ int wave_reserve(int32_t *counter, int n) {
+  const int lane = lane_id();
+  int incl = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int a = __shfl_up(incl, o);
+    if (lane >= o) incl += a;
+  }
+  const int tot = __shfl(incl, 63);
+  int base = 0;
+  if (tot > 0) {
+    if (lane == 63) base = atomicAdd(counter, tot);
+    base = __shfl(base, 63);
+  }
+  return base + incl - n;
+}
+
 // (a) every gas neighbour of a filled cell becomes a new interface cell; an emptied
 // neighbour of a filled cell stays an interface cell
 template <int D>
@@ -45,12 +63,13 @@ __global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
       if (ty[i] == TG) old[i] = flag_or(d.cflag, yy[i], CF_NEWI);
       else if (ty[i] == TI && (d.cflag[yy[i]] & CF_EMPTY)) flag_clear(d.cflag, yy[i], CF_EMPTY);
     }
+    int na = 0;
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      const bool add = !(old[i] & CF_NEWI);
-      const int slot = wave_append_slot(d.cnt + C_NI, add);
-      if (add) d.nilist[slot] = (int32_t)yy[i];
-    }
+    for (int i = 1; i < L::Q; ++i) na += (old[i] & CF_NEWI) ? 0 : 1;
+    int at = wave_reserve(d.cnt + C_NI, na);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i)
+      if (!(old[i] & CF_NEWI)) d.nilist[at++] = (int32_t)yy[i];
   }
 }
 
@@ -93,12 +112,13 @@ __global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
         old[i] = flag_or(d.cflag, yy[i], CF_L2I);
       }
     }
+    int na = 0;
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      const bool add = !(old[i] & CF_L2I);
-      const int slot = wave_append_slot(d.cnt + C_L2I, add);
-      if (add) d.l2ilist[slot] = (int32_t)yy[i];
-    }
+    for (int i = 1; i < L::Q; ++i) na += (old[i] & CF_L2I) ? 0 : 1;
+    int at = wave_reserve(d.cnt + C_L2I, na);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i)
+      if (!(old[i] & CF_L2I)) d.l2ilist[at++] = (int32_t)yy[i];
   }
 }
 
