@@ -8,7 +8,8 @@ open are filled from the parameter sets printed in the paper's figure captions
 diffusivity, supersaturation, power-law reference viscosity) are fixed below.  Randomness: SplitMix64 (Steele, Lea and Flood, 2014) as the integer
 stream and U(0,1) = (u >> 11) * 2**-53.
 
-Nucleus placement is dart throwing: per attempt draw r ~ U[r_min, r_max], then the
+Nucleus placement is a fixed list (``fixed``: (x, y, z, r) per nucleus), one nucleus at the
+grid centre with a seeded sub-cell offset (``center="jitter"``), or dart throwing: per attempt draw r ~ U[r_min, r_max], then the
 centre coordinates in axis order, each uniform over the liquid box that keeps the
 sphere ``r + 2`` cells away from walls and from the headspace; accept if the centre
 distance to every accepted nucleus is at least ``min_sep`` (or r_i + r_j + 4 when
@@ -151,10 +152,53 @@ def small_case(name: str, **overrides) -> dict:
             steps=60, seed=3,
             nuclei=dict(n=12, r_min=2.0, r_max=4.0, min_sep=None),
         ),
+        # Topology and lamella cases (3D, binary64): nuclei at given places. Bubbles a
+        # lamella of two cells apart in a 3 x 3 layer (disjoining pressure acts on the
+        # films between them; saturated liquid, so they neither grow nor shrink much).
+        "lamella3d": _mk(
+            name="lamella3d", dim=3, nx=53, ny=50, nz=31, precision="fp64", tau=0.7,
+            sigma=5e-4, S0=1.0, k_pi=5e-3, d_max=2.0, steps=100, seed=0,
+            nuclei=dict(n=9, fixed=_grid_layer(53, 50, 11.3, 3, 4.0, 2.0)),
+        ),
+        # two growing bubbles two cells apart: the film between them breaks (merge), the
+        # disjoining pressure opens the neck again (split into a new id), and they join
+        # once more
+        "neck3d": _mk(
+            name="neck3d", dim=3, nx=46, ny=34, nz=34, precision="fp64", tau=0.7,
+            sigma=5e-4, S0=1.5, k_pi=5e-3, d_max=2.0, steps=30, seed=0,
+            nuclei=dict(n=2, fixed=[(17.5, 16.3, 14.2, 4.0), (27.5, 16.6, 14.0, 4.0)]),
+        ),
+        # growth at supersaturation 2: two bubbles merge, a third one under the liquid
+        # surface grows into the headspace and bursts
+        "burst3d": _mk(
+            name="burst3d", dim=3, nx=46, ny=34, nz=34, precision="fp64", tau=0.7,
+            sigma=5e-4, S0=2.0, steps=100, seed=0,
+            nuclei=dict(n=3, fixed=[(12.3, 12.2, 10.4, 4.0), (22.1, 12.5, 10.2, 4.0),
+                                    (30.4, 23.6, 25 - 5.6, 3.0)]),
+        ),
+        # dissolution in undersaturated liquid: three small bubbles shrink and vanish
+        "dissolve3d": _mk(
+            name="dissolve3d", dim=3, nx=38, ny=30, nz=29, precision="fp64", tau=0.7,
+            sigma=2e-3, D=0.1, S0=0.2, steps=340, seed=0,
+            nuclei=dict(n=3, fixed=[(10.3, 10.2, 9.4, 2.0), (24.1, 17.5, 10.2, 2.6),
+                                    (14.4, 21.6, 12.1, 3.2)]),
+        ),
     }
     d = cases[name]
     d.update(overrides)
     return d
+
+
+def _grid_layer(nx, ny, z, n, r, gap):
+    """n x n nuclei of radius r in the plane at height z, centre spacing 2r + gap, with
+    small fixed sub-cell offsets so that no two spheres voxelise alike."""
+    sp = 2.0 * r + gap
+    out = []
+    for j in range(n):
+        for i in range(n):
+            out.append((nx / 2 + (i - (n - 1) / 2) * sp + 0.13 * j,
+                        ny / 2 + (j - (n - 1) / 2) * sp - 0.07 * i, z + 0.1 * i, r))
+    return out
 
 
 def _liquid_box(wl: dict, r: float):
@@ -180,7 +224,11 @@ def place_nuclei(wl: dict):
     rng = SplitMix64(wl["seed"])
     n = spec["n"]
     centers, radii = [], []
-    if spec.get("center") == "jitter":
+    if spec.get("fixed") is not None:
+        for (x, y, z, r) in spec["fixed"]:
+            centers.append([x, y, z if dim == 3 else 0.0])
+            radii.append(r)
+    elif spec.get("center") == "jitter":
         # one nucleus at the grid centre plus a seeded sub-cell offset in [-1/2, 1/2)
         r = spec["r_min"]
         c = [0.5 * (wl["nx"] - 1) + 0.5, 0.5 * (wl["ny"] - 1) + 0.5, 0.0]

@@ -22,8 +22,15 @@ def rel_maxdiff(a, b, mask):
     return float(np.abs(a - b).max() / scale)
 
 
-def compare_states(gpu, orc, tol_pop, tol_cell, exact_types=True):
-    """Compare a GPU Sim and an Oracle; returns a dict of the measured differences."""
+def compare_states(gpu, orc, tol_pop, tol_cell, exact_types=True, tol_geom=None):
+    """Compare a GPU Sim and an Oracle; returns a dict of the measured differences.
+
+    tol_geom bounds the curvature and the disjoining pressure of the interface cells
+    (default: tol_cell). In 3D binary64 they carry 1e-10: the least-squares fit amplifies
+    the last-bit differences of cbrt / acos in the PLIC inverse (libm on the host, the
+    device library on the GPU)."""
+    if tol_geom is None:
+        tol_geom = tol_cell
     Tg, To = gpu.read("type"), orc.read("type")
     out = {}
     out["type_mismatch"] = int((Tg != To).sum())
@@ -42,6 +49,8 @@ def compare_states(gpu, orc, tol_pop, tol_cell, exact_types=True):
     assert out["g"] <= tol_pop, out
     for name in ("mass", "alpha", "rho"):
         assert out[name] <= tol_cell, (name, out)
+    for name in ("kappa", "pi"):
+        assert out[name] <= tol_geom, (name, out)
     return out
 
 

@@ -202,3 +202,36 @@ def test_16bit_storage_with_learned_curvature(trained_net, prec):
         dm = abs(_liquid(gpu) - m0) / m0
         assert dm < 1e-6, dm
     assert compared >= 1
+
+
+@pytest.mark.timeout(900)
+def test_headline_form_against_fp64_oracle(trained_net):
+    """The benchmark's production form, binary16 f and g (precision 4) with the learned
+    curvature, against the FP64 oracle with the plain fit on config-2 physics: liquid mass
+    within 1e-6 relative and every bubble volume within 1% for 500 steps (the oracle's
+    first topology change comes later, near step 580)."""
+    from paper_1908_04262_amd import Sim
+    wl = small_case("c2_small", precision="f16s_g16", curvature="mlp")
+    wl64 = small_case("c2_small", precision="fp64")
+    _say("f16s_g16 + mlp c2_small vs fp64 oracle, 500 steps")
+    gpu = Sim(wl)
+    gpu.attach_mlp(trained_net)
+    orc = Oracle(wl64)
+    c, r, p0 = place_nuclei(wl)
+    gpu.nucleate(c, r, p0)
+    orc.nucleate(c, r, p0)
+    m0 = _liquid(gpu)
+    worst = 0.0
+    for k in range(10):
+        gpu.step(50)
+        orc.step(50)
+        bg, bo = gpu.bubbles(), orc.bubbles()
+        assert orc.ledgers()["next_id"] == len(r) + 1 and len(bo["id"]) == len(r)
+        assert list(bg["id"]) == list(bo["id"]), (bg["id"], bo["id"])
+        dv = np.abs(bg["V"] - bo["V"]) / bo["V"]
+        dm = abs(_liquid(gpu) - m0) / m0
+        worst = max(worst, dv.max())
+        _say(f"  step {50 * (k + 1)}: max volume deviation {dv.max():.2e}, mass drift {dm:.2e}")
+        assert dv.max() < 0.01, dv.max()
+        assert dm < 1e-6, dm
+    _say(f"worst volume deviation over 500 steps {worst:.2e}")

@@ -39,7 +39,7 @@ def test_field_nucleation_fp64_parity(dim):
     gpu = Sim(wl)
     orc.nucleate(c, r, p0)
     gpu.nucleate(c, r, p0)
-    compare_states(gpu, orc, tol_pop=1e-12, tol_cell=1e-12)
+    compare_states(gpu, orc, tol_pop=1e-12, tol_cell=1e-12, tol_geom=1e-10)
     compare_bubbles(gpu, orc, 1e-12)
     for k in range(2):
         orc.step(10)
