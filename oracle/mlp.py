@@ -109,8 +109,12 @@ def _inside_frac(cell, c, Rm, a):
     return float((F(sub) < 0).sum()) / 1000.0
 
 
-def generate(seed, first, n, noise=0.01):
-    """stencils [n, 125] (dz outer, dx inner, offsets -2..2) and exact curvature [n]"""
+def generate(seed, first, n, noise=0.01, geometry=None):
+    """stencils [n, 125] (dz outer, dx inner, offsets -2..2) and exact curvature [n];
+    with a list as geometry, each sample's body is appended to it as a dict (centre c
+    relative to the centre cell's centre, unit quaternion q = (w, x, y, z) of the body
+    frame, semi-axes a, gas_inside) so that tests can rebuild the stencil and its label
+    independently"""
     X = np.zeros((n, NFEAT))
     K = np.zeros(n)
     offs = np.arange(-2, 3)
@@ -149,6 +153,8 @@ def generate(seed, first, n, noise=0.01):
                     alpha[j] = min(1.0, max(0.0, alpha[j] + noise * st.normal()))
             X[k] = alpha
             K[k] = kap
+            if geometry is not None:
+                geometry.append(dict(c=c.copy(), q=qv.copy(), a=a.copy(), gas_inside=bool(gas_inside)))
             break
         else:
             raise RuntimeError(f"sample {sample}: no valid attempt")
