@@ -278,6 +278,16 @@ int mf_mlp_generate(uint64_t data_seed, int64_t first, int64_t n, double noise, 
 /* Curvature of n raw stencils [n][125] (host) through canonicalisation and the network. */
 int mf_mlp_eval(const mf_mlp *m, const float *stencils, int64_t n, float *kappa, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, serving
+ * loops, harnesses that forbid hipMalloc): the curvature of n raw stencils as
+ * mf_mlp_eval computes it, with stencils [n][125] and kappa [n] in device memory,
+ * enqueued on stream (hipStream_t, NULL = null stream) without waiting. The call
+ * allocates nothing: its intermediate arrays live in a static device array of 12.6 MB
+ * that every GPU the library runs on holds until the process ends, sized for at most
+ * 8192 stencils per call (MF_EINVAL beyond). All calls on one GPU share that array, so
+ * calls that overlap on one GPU (different streams, threads) race. */
+int mf_mlp_eval_noalloc(const mf_mlp *m, const float *stencils, int64_t n, float *kappa, void *stream);
+
 /* Loss and parameter gradient on one batch of raw stencils [B][125] with targets 8 kappa
  * (host buffers; grad has mf_mlp_param_count floats). For gradient checks. */
 int mf_mlp_grad(const mf_mlp *m, const float *stencils, const float *target8, int32_t B, float *grad,

@@ -8,6 +8,7 @@
 // binary32 master copy. The curvature enters the gas density of Eq. rhob.
 #include <math.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -379,11 +380,43 @@ static hipError_t ensure_batch(Net &n, int B) {
   return hipSuccess;
 }
 
-// forward pass of B canonical rows X (bfloat16-valued binary32 [B][128])
+// activations of a forward pass: pre-activations and bfloat16 GELU outputs of both
+// hidden layers [B][64], outputs [B]
+struct FwdBufs {
+  float *Z1, *H1, *Z2, *H2, *out;
+};
+
+// forward pass of B canonical rows X (bfloat16-valued binary32 [B][128]) with the
+// parameters theta into the buffers b
+static void forward_into(const float *theta, const FwdBufs &b, hipStream_t s, const float *X, int B) {
+  gemm(s, 1, X, NPD, 1, theta + OW1, NH, 1, b.Z1, NH, B, NH, NPD, theta + OB1, b.H1);
+  gemm(s, 1, b.H1, NH, 1, theta + OW2, NH, 1, b.Z2, NH, B, NH, NH, theta + OB2, b.H2);
+  hipLaunchKernelGGL(k_out_layer, dim3((B + 255) / 256), dim3(256), 0, s, b.H2, theta, B, b.out);
+}
+
 static void forward(Net &n, hipStream_t s, const float *X, int B) {
-  gemm(s, 1, X, NPD, 1, n.theta + OW1, NH, 1, n.Z1, NH, B, NH, NPD, n.theta + OB1, n.H1);
-  gemm(s, 1, n.H1, NH, 1, n.theta + OW2, NH, 1, n.Z2, NH, B, NH, NH, n.theta + OB2, n.H2);
-  hipLaunchKernelGGL(k_out_layer, dim3((B + 255) / 256), dim3(256), 0, s, n.H2, n.theta, B, n.out);
+  forward_into(n.theta, FwdBufs{n.Z1, n.H1, n.Z2, n.H2, n.out}, s, X, B);
+}
+
+// ------------------------------------------------- evaluation without allocation
+// Device memory of mf_mlp_eval_noalloc: canonical rows [kNoAllocMax][128], the four
+// hidden-layer arrays [kNoAllocMax][64] and the outputs [kNoAllocMax], 12.6 MB held by
+// every GPU the library runs on until the process ends. Host code never names it: its
+// address on the current device comes from hipGetSymbolAddress.
+constexpr int kNoAllocMax = 8192;
+constexpr size_t kScratchFloats = (size_t)kNoAllocMax * (NPD + 4 * NH + 1);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+// zero rows [n0, n1) of a [*][128] array (the padding rows of the last 64-row tile)
+__global__ void k_zero_rows(float *X, int n0, int n1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)(n1 - n0) * NPD) X[(int64_t)n0 * NPD + i] = 0.0f;
+}
+
+// kappa = out / 8
+__global__ void k_scale_out(const float *out, int n, float *kappa) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) kappa[i] = out[i] * 0.125f;
 }
 
 // loss and gradient of the mean squared error against Y (= 8 kappa), into n.g
@@ -689,6 +722,26 @@ int fail(const std::string &m, int rc) {
   mf::g_thread_err = m;
   return rc;
 }
+// address of scratch on the current device, looked up once per device (each GPU holds
+// its own copy of the array at its own address)
+static int scratch_address(float **out) {
+  static std::mutex mu;
+  static float *addr[256] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(std::string("hipGetDevice: ") + hipGetErrorString(e), MF_EHIP);
+  if (dev < 0 || dev >= 256) return fail("device ordinal out of range", MF_EINTERNAL);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e), MF_EHIP);
+    addr[dev] = (float *)p;
+  }
+  *out = addr[dev];
+  return MF_OK;
+}
+
 #define MLPCHK(expr)                                                                        \
   do {                                                                                      \
     hipError_t _e = (expr);                                                                 \
@@ -786,6 +839,31 @@ int mf_mlp_eval(const mf_mlp *mc, const float *stencils, int64_t n, float *kappa
   MLPCHK(hipStreamSynchronize(s));
   (void)hipFree(raw);
   for (int64_t i = 0; i < n; i++) kappa[i] = out[i] * 0.125f;
+  return MF_OK;
+}
+
+int mf_mlp_eval_noalloc(const mf_mlp *m, const float *stencils, int64_t n, float *kappa, void *stream) {
+  if (!m || n < 0 || (n > 0 && (!stencils || !kappa))) return fail("bad arguments", MF_EINVAL);
+  if (n > kNoAllocMax)
+    return fail("mf_mlp_eval_noalloc takes at most " + std::to_string(kNoAllocMax) + " stencils per call",
+                MF_EINVAL);
+  if (n == 0) return MF_OK;
+  float *scr = nullptr;
+  const int rc = scratch_address(&scr);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int nn = (int)n, npad = (nn + 63) / 64 * 64;
+  float *X = scr;
+  const FwdBufs b{X + (size_t)kNoAllocMax * NPD, X + (size_t)kNoAllocMax * (NPD + NH),
+                  X + (size_t)kNoAllocMax * (NPD + 2 * NH), X + (size_t)kNoAllocMax * (NPD + 3 * NH),
+                  X + (size_t)kNoAllocMax * (NPD + 4 * NH)};
+  hipLaunchKernelGGL(k_mlp_canon, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, stencils, (int64_t)nn, X);
+  // the rows up to the next multiple of 64 hold the previous call's values: clear them
+  if (npad > nn)
+    hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)(((npad - nn) * NPD + 255) / 256)), dim3(256), 0, s, X, nn, npad);
+  forward_into(m->theta, b, s, X, npad);
+  hipLaunchKernelGGL(k_scale_out, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, b.out, nn, kappa);
+  MLPCHK(hipGetLastError());
   return MF_OK;
 }
 

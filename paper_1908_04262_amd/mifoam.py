@@ -62,7 +62,7 @@ EXPORTS = ["mf_abi_version", "mf_last_error", "mf_workspace_bytes", "mf_create",
            "mf_set_bubble", "mf_refresh", "mf_read_bubbles", "mf_totals_get",
            "mf_profile_enable", "mf_profile_get", "mf_mlp_param_count", "mf_mlp_create",
            "mf_mlp_destroy", "mf_mlp_train", "mf_mlp_get_params", "mf_mlp_set_params",
-           "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_grad", "mf_attach_mlp", "mf_tune",
+           "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_eval_noalloc", "mf_mlp_grad", "mf_attach_mlp", "mf_tune",
            "mf_set_sweep_variant", "mf_batch_create", "mf_batch_tune", "mf_batch_step",
            "mf_batch_destroy", "mf_poisson_nuclei"]
 SWEEP_VARIANTS = 4
@@ -107,6 +107,7 @@ def load_library():
     lib.mf_mlp_set_params.argtypes = [vp, vp]
     lib.mf_mlp_generate.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_double, vp, vp, vp]
     lib.mf_mlp_eval.argtypes = [vp, vp, C.c_int64, vp, vp]
+    lib.mf_mlp_eval_noalloc.argtypes = [vp, vp, C.c_int64, vp, vp]
     lib.mf_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp]
     lib.mf_attach_mlp.argtypes = [vp, vp]
     lib.mf_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), vp]
@@ -401,6 +402,14 @@ class CurvatureNet:
         _check_plain(self.lib, self.lib.mf_mlp_eval(self.h, X.ctypes.data, X.shape[0], out.ctypes.data,
                                                     _stream_ptr()))
         return out
+
+    def eval_noalloc(self, stencils_dev, kappa_dev, n=None):
+        """curvature of device stencils (torch float32 [n, 125] on the GPU) into a device
+        tensor kappa_dev (float32 [n]) through the allocation-free entry point; enqueued
+        on the current stream"""
+        n = stencils_dev.shape[0] if n is None else int(n)
+        _check_plain(self.lib, self.lib.mf_mlp_eval_noalloc(self.h, C.c_void_p(stencils_dev.data_ptr()), n,
+                                                            C.c_void_p(kappa_dev.data_ptr()), _stream_ptr()))
 
     def grad(self, stencils, target8):
         X = np.ascontiguousarray(stencils, dtype=np.float32).reshape(-1, 125)
