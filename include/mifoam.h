@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MF_ABI_VERSION 3
+#define MF_ABI_VERSION 4
 
 enum mf_status {
   MF_OK = 0,
@@ -63,6 +63,18 @@ enum mf_precision {
 
 enum mf_rheology { MF_NEWTONIAN = 0, MF_POWER_LAW = 1, MF_CARREAU_YASUDA = 2 };
 enum mf_curvature { MF_CURV_PLAIN = 0, MF_CURV_MLP = 1 };
+
+/* Gas flux into the bubbles (Sec. 3.2, Eq. gascurrent).
+ * MF_FLUX_LEDGER: each interface cell books, per direction whose source is gas, the
+ *   dissolved gas it sent to the gas side minus what the Henry's-law rebuild returned;
+ *   cell conversions move the dissolved gas of emptied cells into their bubble and take
+ *   that of new interface cells out of it. Dissolved gas plus bubble, atmosphere and
+ *   collapsed gas is then conserved exactly.
+ * MF_FLUX_PAPER: the printed formula, with F read as the liquid and interface cells and
+ *   rho as 1: every interface cell x of bubble j books the populations its fluid
+ *   neighbours send towards it minus those it sends to them, less c(x)(alpha_new(x) -
+ *   alpha_old(x)); conversions move no gas. Gas is not conserved in this mode. */
+enum mf_flux_mode { MF_FLUX_LEDGER = 0, MF_FLUX_PAPER = 1 };
 
 /* cell types reported by MF_FIELD_TYPE */
 enum mf_cell_type { MF_GAS = 0, MF_INTERFACE = 1, MF_LIQUID = 2, MF_WALL = 3 };
@@ -125,14 +137,21 @@ typedef struct mf_params {
                             cell's own tau (implicit, solved per cell). Shear thinning:
                             1/2 < tau_inf <= tau0, 0 < n <= 1, a > 0, lambda >= 0, and
                             (tau0 - tau_inf)(1 - n) < tau_inf, which makes tau unique. */
+  int32_t flux_mode;     /* a value of mf_flux_mode: Sec. 3.2, Eq. gascurrent */
 } mf_params;
 
+/* One entry of the bubble table (Sec. 3.5: per-bubble volume, gas content and pressure). */
 typedef struct mf_bubble {
   int32_t id;
   int32_t alive;
-  double volume;   /* sum over the bubble's cells of (1 - alpha) */
-  double gas_mass; /* m_g */
-  double pressure; /* m_g RT / max(volume, 1/2) */
+  double volume;      /* sum over the bubble's cells of (1 - alpha) */
+  double gas_mass;    /* m_g */
+  double pressure;    /* m_g RT / max(volume, 1/2) (Eq. idealgas) */
+  int32_t n_cells;    /* gas and interface cells carrying the id */
+  int32_t reserved;
+  double centroid[3]; /* centre of the gas volume: sum (1 - alpha) x / sum (1 - alpha) over
+                         the bubble's cells (plain coordinates, no unwrapping across periodic
+                         axes; z = 0 in 2D) */
 } mf_bubble;
 
 typedef struct mf_totals {
@@ -144,28 +163,40 @@ typedef struct mf_totals {
   int32_t n_bubbles;    /* live bubbles, atmosphere excluded */
   int32_t n_interface;  /* interface cells entering the last step */
   int32_t status;       /* device status bits, 0 when healthy */
+  double liquid_mass;   /* sum of rho over liquid cells and of M over interface cells
+                           (Sec. 2.1: the mass that conversions and the excess split conserve) */
+  double dissolved_gas; /* sum of c = sum_i g_i over liquid and interface cells */
+  double bubble_gas;    /* sum of m_g over the live bubbles (atmosphere excluded) */
 } mf_totals;
 
-/* Library ABI version (MF_ABI_VERSION of the build). */
+/* Library ABI version (MF_ABI_VERSION of the build). Infrastructure of the boundary; it
+ * implements no passage of the paper. */
 int mf_abi_version(void);
 
-/* Message of the last failed call on ctx; with ctx == NULL, of the last failed
- * mf_create / mf_workspace_bytes on this thread. The pointer stays valid until the
- * next call on the same context. */
+/* Message of the last failed call on ctx; with ctx == NULL, of the last failed call
+ * without a context (mf_create, mf_workspace_bytes, networks, batches) on this thread.
+ * The pointer stays valid until the next call on the same context. Infrastructure; no
+ * passage of the paper. */
 const char *mf_last_error(const mf_ctx *ctx);
 
-/* Device bytes a context with these parameters needs (arrays sized for every cell:
- * populations in two buffers, cell fields, interface lists, labelling tables). */
+/* Device bytes a context with these parameters needs: the populations f and g of the
+ * lattice Boltzmann equation (Sec. 2, Eq. LBE; Sec. 3.1, Eq. diffusion) in two buffers
+ * each, the cell fields of the free-surface model (Sec. 2.1: type, mass M, fill
+ * fraction alpha), interface lists, labelling tables and the bubble table (Sec. 3.5).
+ * MF_EINVAL on invalid parameters (the rules of mf_create). */
 int mf_workspace_bytes(const mf_params *p, size_t *bytes);
 
-/* Create a context: validates p (MF_EINVAL), carves its arrays out of dev_workspace
- * (device memory of at least mf_workspace_bytes, owned by the caller and kept alive
- * until mf_destroy) or, when dev_workspace is NULL, allocates them itself. stream is a
- * hipStream_t (NULL: the null stream). Initialises a liquid at rest (f = w_i,
- * g = w_i c0 with c0 = S0 kH p_atm), walls on closed axes and the headspace. */
+/* Create a context (Sec. 2 set-up: a liquid at rest below the headspace, walls on closed
+ * axes): validates p (MF_EINVAL), carves its arrays out of dev_workspace (device memory of
+ * at least mf_workspace_bytes, owned by the caller and kept alive until mf_destroy; a
+ * smaller one gives MF_ENOMEM) or, when dev_workspace is NULL, allocates them itself
+ * (MF_ENOMEM on failure). stream is a hipStream_t (NULL: the null stream). Initialises the
+ * equilibrium at rest f = w_i (Eq. equilibrium) and g = w_i c0 with c0 = S0 kH p_atm
+ * (Sec. 3.1), and the atmosphere (id 0, pressure p_atm). */
 int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *stream, mf_ctx **out);
 
-/* Destroy; frees only memory the library allocated. NULL is accepted. */
+/* Destroy a context: waits for its stream, frees only memory the library allocated
+ * (never the caller's workspace). NULL is accepted. Infrastructure; no passage. */
 int mf_destroy(mf_ctx *ctx);
 
 /* Nucleation (Sec. 3.4): n spheres (disks in 2D) with centres [n][3] (z ignored in
@@ -193,44 +224,81 @@ int mf_poisson_nuclei(const mf_params *p, const float *prob, int32_t max_n, doub
                       double gap, int32_t attempts, uint64_t seed, double *centers, double *radii,
                       int32_t *n_out);
 
-/* Advance nsteps time steps (enqueued on the context stream; returns without waiting).
- * Each step: stream / collide f and g, interface mass exchange, Henry's-law and
- * free-surface reconstruction, cell conversion with excess redistribution, bubble
- * labelling and gas bookkeeping, bubble pressures, curvature, disjoining pressure.
- * The labelling and geometry of a step run on a stream of the context's own, beside the
- * next step's bulk sweep; all work is joined into the context stream before mf_step
- * returns. */
+/* Advance nsteps time steps (enqueued on the context stream; returns without waiting;
+ * nsteps < 0 gives MF_EINVAL, a learned-curvature context without a network MF_ESTATE).
+ * Each step is the paper's time step: stream and collide f (Sec. 2, Eqs. LBE,
+ * streamingstep, collisionstep, equilibrium, tau / carreauTau) and g (Sec. 3.1, Eqs.
+ * diffusion, diffusionconst), the interface mass exchange (Sec. 2.1, Eq. massexchange),
+ * the free-surface and Henry's-law rebuilds (Eqs. reconstruct, rhob,
+ * rhobplusdisjoining; Eqs. henryslaw, reconstructdiffusion), cell conversion with
+ * excess redistribution (Sec. 2.1), bubble labelling with the gas bookkeeping (Sec.
+ * 3.2 Eq. gascurrent, Sec. 3.5) and pressures (Eq. idealgas), curvature (Sec. 2.2) and
+ * disjoining pressure (Sec. 3.3, Appendix A Algorithm 1). The labelling and geometry of
+ * a step run on streams of the context's own, beside the next step's bulk sweep; all
+ * work is joined into the context stream before mf_step returns. Device-side failures
+ * surface at the next mf_sync. */
 int mf_step(mf_ctx *ctx, int32_t nsteps);
 
-/* Wait for the context stream and report device status (MF_ENUMERIC / MF_ECAPACITY
- * if the device flagged an invalid state or a full table). */
+/* Wait for the context stream and report the device status word that the kernels set
+ * themselves: MF_ENUMERIC for a non-positive or non-finite density in a collision (Sec.
+ * 2, Eq. collision), a liquid cell next to gas or an interface cell with an invalid
+ * bubble id (the invariants of Sec. 2.1); MF_ECAPACITY for a full bubble or labelling
+ * table (Sec. 3.5). The state is left in place for inspection. */
 int mf_sync(mf_ctx *ctx);
 
-/* Copy a field (mf_field) into dst (host memory, or device memory when dst_on_device
- * is 1). dst_bytes must hold the field (see mf_field for element types and counts).
- * Synchronises the context stream. */
+/* Copy a field (mf_field: the cell type and fill fraction of Sec. 2.1, populations of
+ * Sec. 2 and 3.1, curvature of Sec. 2.2, disjoining pressure of Sec. 3.3, bubble ids of
+ * Sec. 3.5) into dst (caller-owned host memory, or device memory when dst_on_device is
+ * 1), converted to the element type mf_field states, cell index x fastest. dst_bytes
+ * must hold the field (MF_EINVAL otherwise). Synchronises the context stream. */
 int mf_read_field(mf_ctx *ctx, int32_t field, void *dst, size_t dst_bytes, int32_t dst_on_device);
 
-/* Overwrite a field from host memory (hand-built test states); same layout as
- * mf_read_field. Allowed before the first mf_step. Call mf_refresh afterwards. A type
- * field must keep walls on the outer layer of every closed axis (MF_EINVAL otherwise). */
+/* Overwrite a field from host memory (hand-built states of the free-surface model of
+ * Sec. 2.1); same layout as mf_read_field. Allowed before the first mf_step (MF_ESTATE
+ * after). Call mf_refresh afterwards. A type field must keep walls on the outer layer of
+ * every closed axis (MF_EINVAL otherwise). */
 int mf_write_field(mf_ctx *ctx, int32_t field, const void *src, size_t src_bytes);
 
-/* Set one bubble-table entry (hand-built test states). The gas side of the interface
- * cells (rebuilt populations at the bubble pressure) follows before the next step. */
+/* Set one bubble-table entry (Sec. 3.5: gas mass, volume, pressure of Eq. idealgas) for
+ * hand-built states; MF_EINVAL for an id outside the table. The gas side of the
+ * interface cells (Eq. reconstruct at the bubble pressure) follows before the next step. */
 int mf_set_bubble(mf_ctx *ctx, int32_t id, double gas_mass, double volume, double pressure, int32_t alive);
 
-/* Recompute the derived state of a hand-written state: interface lists, curvature,
- * disjoining pressure and the gas side of the interface cells. relabel = 1 also runs
- * bubble labelling with no gas flux. */
+/* Recompute the derived state of a hand-written state: interface lists, curvature (Sec.
+ * 2.2), disjoining pressure (Sec. 3.3) and the gas side of the interface cells (Eqs.
+ * rhob, rhobplusdisjoining). relabel = 1 also runs the bubble labelling of Sec. 3.5 with
+ * no gas flux. Synchronises; reports the device status like mf_sync. */
 int mf_refresh(mf_ctx *ctx, int32_t relabel);
 
-/* Live bubbles (atmosphere excluded) in ascending id; *n_out = number of live bubbles
- * (may exceed capacity; then only capacity entries are written). Synchronises. */
+/* The bubble table of Sec. 3.5 (volume, gas content and Eq. idealgas pressure of every
+ * bubble; cell counts and gas-volume centroids from one pass over the grid): live
+ * bubbles (atmosphere excluded) in ascending id into dst (caller-owned host array of
+ * capacity entries; NULL only with capacity 0); *n_out = number of live bubbles (may
+ * exceed capacity; then only capacity entries are written). Synchronises. */
 int mf_read_bubbles(mf_ctx *ctx, mf_bubble *dst, int32_t capacity, int32_t *n_out);
 
-/* Ledgers and counters. Synchronises. */
+/* Conserved totals and ledgers: liquid mass (Sec. 2.1, conserved by the mass exchange,
+ * conversions and excess split), dissolved gas (Sec. 3.1) and bubble gas (Sec. 3.2), the
+ * atmosphere, collapsed and lost-liquid ledgers of Sec. 3.5, and counters. The liquid
+ * mass and dissolved gas are summed on the device in fixed point (independent of
+ * order). Synchronises. */
 int mf_totals_get(mf_ctx *ctx, mf_totals *out);
+
+/* Checkpoint (no passage of the paper: a production form). mf_save writes the whole
+ * state of ctx (device arena, step count, buffer parities, attached network weights)
+ * to the file path; mf_load reads such a file into a context created with the same
+ * parameters (MF_EINVAL otherwise, or for a file of another library version) and
+ * continues from it bit for bit. Both wait for the context stream; MF_EHIP on an I/O or
+ * copy failure (after a failed mf_load the state is undefined). */
+int mf_save(mf_ctx *ctx, const char *path);
+int mf_load(mf_ctx *ctx, const char *path);
+
+/* Fault injection for tests of the failure path (no passage of the paper): overwrite one
+ * element of a field in its storage form: MF_FIELD_F or MF_FIELD_G (comp = direction),
+ * MF_FIELD_RHO, MF_FIELD_ALPHA or MF_FIELD_MASS (comp = 0) at cell. No check of the
+ * value: a non-finite population is reported as MF_ENUMERIC by mf_sync after the next
+ * step. MF_EINVAL for other fields, cells or components. Synchronises. */
+int mf_debug_poke(mf_ctx *ctx, int32_t field, int64_t cell, int32_t comp, double value);
 
 /* ------------------------------------------------------------ learned curvature ---
  * A small network (125-64-64-1, GELU, bfloat16 weights and activations, binary32
@@ -270,6 +338,12 @@ int mf_mlp_train(mf_mlp *m, const mf_mlp_train_spec *spec, void *stream, double 
 int mf_mlp_get_params(const mf_mlp *m, float *dst);
 int mf_mlp_set_params(mf_mlp *m, const float *src);
 
+/* Write the network's binary32 parameters to the file path / create a network from such
+ * a file (*out owned by the caller, released with mf_mlp_destroy). MF_EINVAL for a file
+ * that is not a network file of this library, MF_EHIP on an I/O or copy failure. */
+int mf_mlp_save(const mf_mlp *m, const char *path);
+int mf_mlp_load(mf_mlp **out, const char *path);
+
 /* Generate n stencils (sample indices first..first+n-1 of the counter-based generator)
  * into host buffers: raw stencils [n][125] (dz outer, dx inner) and exact curvature [n]. */
 int mf_mlp_generate(uint64_t data_seed, int64_t first, int64_t n, double noise, float *stencils,
@@ -293,8 +367,9 @@ int mf_mlp_eval_noalloc(const mf_mlp *m, const float *stencils, int64_t n, float
 int mf_mlp_grad(const mf_mlp *m, const float *stencils, const float *target8, int32_t B, float *grad,
                 double *loss, void *stream);
 
-/* Use the network for the curvature of ctx (requires curvature = MF_CURV_MLP in the
- * parameters); the weights are copied, the network may be destroyed afterwards. */
+/* Use the network for the curvature of ctx (the curvature of Eq. rhob; requires
+ * curvature = MF_CURV_MLP in the parameters, MF_ESTATE otherwise); the weights are copied,
+ * the network may be destroyed afterwards. */
 int mf_attach_mlp(mf_ctx *ctx, const mf_mlp *m);
 
 /* Time spent in a kernel group over the steps since mf_profile_enable(ctx, 1), in
@@ -313,8 +388,9 @@ int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launch
  */
 
 /* Number of launch variants of the bulk lattice sweep (cells per thread x threads per
- * work-group: 0 = 4 x 256, 1 = 2 x 256, 2 = 4 x 128, 3 = 2 x 128). */
-#define MF_SWEEP_VARIANTS 4
+ * work-group: 0 = 4 x 256, 1 = 2 x 256, 2 = 4 x 128, 3 = 2 x 128, 4 = 8 x 256, 5 = 8 x 128,
+ * 6 = 8 x 64, 7 = 4 x 64). */
+#define MF_SWEEP_VARIANTS 8
 
 /* Time every applicable variant of the bulk sweep on the context's current state (reps
  * launches each; the kernel writes only the spare population buffer, so the state is not

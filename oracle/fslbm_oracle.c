@@ -20,7 +20,8 @@
  *       of Eq. rhob / rhobplusdisjoining;
  *   S2  interface mass exchange (Eq. massexchange with the weights Theta);
  *   S3  stream g (Eq. diffusion) with the Henry's-law rebuild (Eqs. henryslaw,
- *       reconstructdiffusion) and the gas ledger that feeds the bubbles;
+ *       reconstructdiffusion) and the gas ledger that feeds the bubbles (or, with
+ *       flux_mode 1, S3' the gas flux of Eq. gascurrent as printed);
  *   S4  moments (Sec. 2), BGK collision (Eqs. collision, equilibrium) with tau from
  *       Eq. tau or the power-law limit of Eq. carreauTau, and the external force term of
  *       Eq. collision in the scheme of Guo, Zheng and Shi (2002); ADE collision
@@ -64,6 +65,7 @@ typedef struct {
   double pl_n, pl_nu_ref, pl_gdot_ref, tau_min, tau_max;
   double accel[3]; /* body-force acceleration a (gravity); 0: no force term */
   double cy_tau0, cy_tau_inf, cy_lambda, cy_a, cy_n; /* Carreau-Yasuda (Eq. carreauTau) */
+  int32_t flux_mode; /* 0: gas ledger (S3, S6); 1: the printed Eq. gascurrent (S3') */
 } or_params;
 
 typedef struct {
@@ -1123,7 +1125,7 @@ static int step_once(OS *s) {
       } else
         gt[i] = G(s, i, src);
     }
-    if (hasgas) s->Phi[s->label[n]] += fx(phic);
+    if (hasgas && P->flux_mode == 0) s->Phi[s->label[n]] += fx(phic);
     /* S4 */
     double rho, ux, uy, uz;
     moments(s, ft, &rho, &ux, &uy, &uz);
@@ -1144,6 +1146,23 @@ static int step_once(OS *s) {
     for (i = 0; i < Qg; i++) c = c + gt[i];
     for (i = 0; i < Qg; i++)
       gn[(int64_t)i * N + n] = (gt[i] - s->omega_g * (gt[i] - geq(s, i, c, ux, uy, uz))) + s->wg[i] * P->q;
+    if (t == TI && P->flux_mode == 1) {
+      /* S3'. Eq. gascurrent as printed, with F read as the liquid and interface cells and
+       * rho as 1: for every interface cell of bubble j, the populations its fluid
+       * neighbours send towards it minus those it sends to them, less the advected part
+       * c (alpha_new - alpha_old), with c the streamed concentration and alpha_new the
+       * fill fraction after this step's mass exchange. Not conservative: the gas that
+       * conversions move (S6 d, e) is not booked in this mode. */
+      double pf = 0.0, cx = 0.0;
+      for (i = 0; i < Qg; i++) cx = cx + gt[i];
+      for (i = 1; i < Qg; i++) {
+        int64_t y = nbr(s, n, i);
+        if (y < 0) continue;
+        if (s->T[y] == TL || s->T[y] == TI) pf = pf + (G(s, s->opp[i], y) - G(s, i, n));
+      }
+      pf = pf - cx * (Ms[n] / rho - s->alpha[n]);
+      s->Phi[s->label[n]] += fx(pf);
+    }
     if (t == TI) {
       s->rho[n] = rho;
       s->ux[n] = ux;
@@ -1263,7 +1282,7 @@ static int step_once(OS *s) {
       G(s, i, n) = geq(s, i, cH, ubx, uby, ubz);
       sg = sg + G(s, i, n);
     }
-    s->Gam[lb] -= fx(sg);
+    if (P->flux_mode == 0) s->Gam[lb] -= fx(sg);
     s->rho[n] = rb;
     s->ux[n] = ubx;
     s->uy[n] = uby;
@@ -1275,7 +1294,7 @@ static int step_once(OS *s) {
     if (cls[n] != CE) continue;
     double sg = 0.0;
     for (i = 0; i < Qg; i++) sg = sg + G(s, i, n);
-    s->Gam[s->label[n]] += fx(sg);
+    if (P->flux_mode == 0) s->Gam[s->label[n]] += fx(sg);
   }
   /* S7: excess mass of converted cells, split equally over their interface
    * neighbours under the new types */

@@ -26,7 +26,7 @@ class OrParams(C.Structure):
         ("pl_n", C.c_double), ("pl_nu_ref", C.c_double), ("pl_gdot_ref", C.c_double),
         ("tau_min", C.c_double), ("tau_max", C.c_double), ("accel", C.c_double * 3),
         ("cy_tau0", C.c_double), ("cy_tau_inf", C.c_double), ("cy_lambda", C.c_double),
-        ("cy_a", C.c_double), ("cy_n", C.c_double),
+        ("cy_a", C.c_double), ("cy_n", C.c_double), ("flux_mode", C.c_int32),
     ]
 
 
@@ -96,6 +96,7 @@ def make_params(wl: dict) -> OrParams:
         p.accel[a] = float(v)
     for k, d in (("cy_tau0", 0.8), ("cy_tau_inf", 0.8), ("cy_lambda", 0.0), ("cy_a", 2.0), ("cy_n", 1.0)):
         setattr(p, k, float(wl.get(k, d)))
+    p.flux_mode = {"ledger": 0, "paper": 1}[wl.get("flux_mode", "ledger")]
     return p
 
 

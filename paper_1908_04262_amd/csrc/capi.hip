@@ -38,6 +38,9 @@ struct OpsTable {
   bool (*sweep_bulk_auto)(Ctx &, hipStream_t);
   void (*sweep_interface)(Ctx &, hipStream_t);
   void (*sweep_cells)(Ctx &, hipStream_t);
+  void (*totals)(Ctx &, hipStream_t);
+  void (*bubble_stats)(Ctx &, hipStream_t);
+  void (*poke)(Ctx &, hipStream_t, int, int64_t, int, double);
 };
 
 template <int D, int P>
@@ -46,7 +49,8 @@ OpsTable make_ops() {
                   &Ops<D, P>::geometry, &Ops<D, P>::init_box,    &Ops<D, P>::nucleate,
                   &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field,
                   &Ops<D, P>::sweep_bulk,  &Ops<D, P>::geometry_normals, &Ops<D, P>::geometry_curv,
-                  &Ops<D, P>::sweep_bulk_auto, &Ops<D, P>::sweep_interface, &Ops<D, P>::sweep_cells};
+                  &Ops<D, P>::sweep_bulk_auto, &Ops<D, P>::sweep_interface, &Ops<D, P>::sweep_cells,
+                  &Ops<D, P>::totals, &Ops<D, P>::bubble_stats, &Ops<D, P>::poke};
 }
 
 OpsTable ops_for(int dim, int prec) {
@@ -149,6 +153,8 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.contested = cv.take<int32_t>((size_t)kp.ecap * 4);
   d.rused = cv.take<int32_t>((size_t)kp.ecap * 4);
   d.scratch_d = cv.take<double>(cap * 8);
+  d.tacc = cv.take<long long>(6 * 8);
+  d.bstat = cv.take<long long>(cap * 13 * 8);
 }
 
 int validate(const mf_params *p, std::string &why) {
@@ -168,6 +174,7 @@ int validate(const mf_params *p, std::string &why) {
     return MF_EINVAL;
   }
   if (p->curvature != MF_CURV_PLAIN && p->curvature != MF_CURV_MLP) { why = "unknown curvature mode"; return MF_EINVAL; }
+  if (p->flux_mode != MF_FLUX_LEDGER && p->flux_mode != MF_FLUX_PAPER) { why = "unknown gas-flux mode"; return MF_EINVAL; }
   if (p->curvature == MF_CURV_MLP && p->dim != 3) { why = "the learned curvature works on 5x5x5 stencils (3D only)"; return MF_EUNSUPPORTED; }
   if (p->curvature == MF_CURV_MLP && p->max_ids > 65534) { why = "the learned curvature supports at most 65534 bubble ids"; return MF_EINVAL; }
   if (p->max_ids < 2 || p->max_ids > (1 << 24)) { why = "max_ids out of range"; return MF_EINVAL; }
@@ -233,6 +240,7 @@ KP make_kp(const mf_params &P) {
   k.ay = P.accel[1];
   k.az = P.dim == 3 ? P.accel[2] : 0.0;
   k.force = k.ax != 0.0 || k.ay != 0.0 || k.az != 0.0;
+  k.flux_paper = P.flux_mode == MF_FLUX_PAPER ? 1 : 0;
   k.fax = (float)k.ax;
   k.fay = (float)k.ay;
   k.faz = (float)k.az;
@@ -737,23 +745,38 @@ int mf_refresh(mf_ctx *c, int32_t relabel) {
 
 int mf_read_bubbles(mf_ctx *c, mf_bubble *dst, int32_t capacity, int32_t *n_out) {
   if (!c) return MF_EINVAL;
+  if (capacity < 0 || (capacity > 0 && !dst)) { c->err = "dst is NULL"; return MF_EINVAL; }
   const int cap = c->kp.cap;
   std::vector<double> m(cap), V(cap), p(cap);
   std::vector<int32_t> al(cap);
+  std::vector<long long> st;
   HIPCHK(c, hipMemcpyAsync(m.data(), c->d.bm, 8 * cap, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(V.data(), c->d.bV, 8 * cap, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(p.data(), c->d.bp, 8 * cap, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(al.data(), c->d.balive, 4 * cap, hipMemcpyDeviceToHost, c->stream));
+  if (capacity > 0) {
+    // cell counts and gas-volume centroids: one pass over the grid
+    st.resize((size_t)cap * 13);
+    c->ops.bubble_stats(*c, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(st.data(), c->d.bstat, 8 * st.size(), hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   int k = 0;
   for (int i = 1; i < cap; i++) {
     if (!al[i]) continue;
-    if (dst && k < capacity) {
+    if (k < capacity) {
+      const long long *b = &st[(size_t)i * 13];
       dst[k].id = i;
       dst[k].alive = 1;
       dst[k].volume = V[i];
       dst[k].gas_mass = m[i];
       dst[k].pressure = p[i];
+      dst[k].n_cells = (int32_t)b[0];
+      const double w = fx_to_double(fx3_join(b[1], b[2], b[3]));
+      for (int a = 0; a < 3; a++)
+        dst[k].centroid[a] = w > 0.0 ? fx_to_double(fx3_join(b[4 + 3 * a], b[5 + 3 * a], b[6 + 3 * a])) / w : 0.0;
+      if (c->kp.dim == 2) dst[k].centroid[2] = 0.0;
     }
     k++;
   }
@@ -771,8 +794,20 @@ int mf_totals_get(mf_ctx *c, mf_totals *out) {
   HIPCHK(c, hipMemcpyAsync(&st, c->d.status, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&next, c->d.nextid, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(al.data(), c->d.balive, 4 * c->kp.cap, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> bm(c->kp.cap);
+  HIPCHK(c, hipMemcpyAsync(bm.data(), c->d.bm, 8 * c->kp.cap, hipMemcpyDeviceToHost, c->stream));
+  long long tacc[6];
+  c->ops.totals(*c, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(tacc, c->d.tacc, sizeof tacc, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out->step = c->step;
+  out->liquid_mass = fx_to_double(fx3_join(tacc[0], tacc[1], tacc[2]));
+  out->dissolved_gas = fx_to_double(fx3_join(tacc[3], tacc[4], tacc[5]));
+  double bg = 0.0;
+  for (int i = 1; i < c->kp.cap; i++)
+    if (al[i]) bg += bm[i];
+  out->bubble_gas = bg;
   out->lost_liquid = (double)led[0] * 0x1p-64;
   out->atm_gas = (double)led[1] * 0x1p-64;
   out->collapsed_gas = (double)led[2] * 0x1p-64;
@@ -785,13 +820,176 @@ int mf_totals_get(mf_ctx *c, mf_totals *out) {
   return MF_OK;
 }
 
+int mf_debug_poke(mf_ctx *c, int32_t field, int64_t cell, int32_t comp, double value) {
+  if (!c) return MF_EINVAL;
+  const int Q = c->kp.dim == 2 ? 9 : 19, Qg = c->kp.dim == 2 ? 5 : 7;
+  if (cell < 0 || cell >= c->kp.N) { c->err = "cell out of range"; return MF_EINVAL; }
+  int ncomp = 0;
+  switch (field) {
+    case MF_FIELD_F: ncomp = Q; break;
+    case MF_FIELD_G: ncomp = Qg; break;
+    case MF_FIELD_RHO: case MF_FIELD_ALPHA: case MF_FIELD_MASS: ncomp = 1; break;
+    default: c->err = "mf_debug_poke writes F, G, RHO, ALPHA or MASS"; return MF_EINVAL;
+  }
+  if (comp < 0 || comp >= ncomp) { c->err = "component out of range"; return MF_EINVAL; }
+  join_side(c);
+  c->ops.poke(*c, c->stream, field, cell, comp, value);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return MF_OK;
+}
+
+// ---------------------------------------------------------------- checkpoints
+// File: a header (magic, ABI version, the creation parameters, the arena size and the
+// host-side state of the step sequence), the whole device arena, and the attached
+// network's weights when there are any. The arena holds only data (no addresses), so a
+// context created with the same parameters continues from it bit for bit.
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int32_t abi, has_mlp;
+  uint64_t params_bytes, arena_bytes, mlp_bytes;
+  mf_params params;
+  int64_t step;
+  int32_t cur, parity, nucleated, stepped, sword_dirty, sword_fresh, gas_dirty, sweep_variant;
+};
+const char kCkptMagic[8] = {'M', 'I', 'F', 'O', 'A', 'M', 'C', 'K'};
+constexpr size_t kMlpWBytes = (2 * (128 * 64 + 64 * 64 + 64) + 255) & ~(size_t)255;
+constexpr size_t kMlpBBytes = (4 * (2 * 64 + 1) + 255) & ~(size_t)255;
+constexpr size_t kCkptChunk = (size_t)64 << 20;
+
+// every field of two parameter sets (padding bytes are not compared)
+bool params_equal(const mf_params &a, const mf_params &b) {
+  bool eq = a.struct_size == b.struct_size && a.dim == b.dim && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz &&
+            a.gas_from == b.gas_from && a.precision == b.precision && a.rheology == b.rheology &&
+            a.curvature == b.curvature && a.cleanup == b.cleanup && a.max_ids == b.max_ids &&
+            a.flux_mode == b.flux_mode;
+  for (int k = 0; k < 3; k++) eq = eq && a.periodic[k] == b.periodic[k];
+  const double da[] = {a.tau, a.D, a.sigma, a.kH, a.RT, a.k_pi, a.d_max, a.p_atm, a.q, a.eps, a.S0, a.pl_n,
+                       a.pl_nu_ref, a.pl_gdot_ref, a.tau_min, a.tau_max, a.accel[0], a.accel[1], a.accel[2],
+                       a.cy_tau0, a.cy_tau_inf, a.cy_lambda, a.cy_a, a.cy_n};
+  const double db[] = {b.tau, b.D, b.sigma, b.kH, b.RT, b.k_pi, b.d_max, b.p_atm, b.q, b.eps, b.S0, b.pl_n,
+                       b.pl_nu_ref, b.pl_gdot_ref, b.tau_min, b.tau_max, b.accel[0], b.accel[1], b.accel[2],
+                       b.cy_tau0, b.cy_tau_inf, b.cy_lambda, b.cy_a, b.cy_n};
+  for (size_t k = 0; k < sizeof da / sizeof da[0]; k++) eq = eq && memcmp(&da[k], &db[k], 8) == 0;
+  return eq;
+}
+
+size_t arena_bytes(const mf_ctx *c) {
+  size_t need = 0;
+  mf_workspace_bytes(&c->P, &need);
+  return need - 256;
+}
+char *arena_base(const mf_ctx *c) { return (char *)(((uintptr_t)c->ws + 255) & ~(uintptr_t)255); }
+}  // namespace
+
+int mf_save(mf_ctx *c, const char *path) {
+  if (!c || !path) return MF_EINVAL;
+  join_side(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  CkptHeader h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, kCkptMagic, 8);
+  h.abi = MF_ABI_VERSION;
+  h.has_mlp = c->d.mlp_w ? 1 : 0;
+  h.params_bytes = sizeof(mf_params);
+  h.arena_bytes = arena_bytes(c);
+  h.mlp_bytes = h.has_mlp ? kMlpWBytes + kMlpBBytes : 0;
+  h.params = c->P;
+  h.step = c->step;
+  h.cur = c->cur;
+  h.parity = c->parity;
+  h.nucleated = c->nucleated;
+  h.stepped = c->stepped;
+  h.sword_dirty = c->sword_dirty;
+  h.sword_fresh = c->sword_fresh;
+  h.gas_dirty = c->gas_dirty;
+  h.sweep_variant = c->sweep_variant;
+  FILE *fp = fopen(path, "wb");
+  if (!fp) { c->err = std::string("cannot open ") + path + " for writing"; return MF_EINVAL; }
+  std::vector<char> buf(kCkptChunk);
+  bool ok = fwrite(&h, sizeof h, 1, fp) == 1;
+  const char *base = arena_base(c);
+  for (size_t off = 0; ok && off < h.arena_bytes; off += kCkptChunk) {
+    const size_t n = h.arena_bytes - off < kCkptChunk ? h.arena_bytes - off : kCkptChunk;
+    if (hipMemcpy(buf.data(), base + off, n, hipMemcpyDeviceToHost) != hipSuccess) { ok = false; break; }
+    ok = fwrite(buf.data(), 1, n, fp) == n;
+  }
+  if (ok && h.has_mlp) {
+    if (hipMemcpy(buf.data(), c->mlp_buf, h.mlp_bytes, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+    else ok = fwrite(buf.data(), 1, h.mlp_bytes, fp) == h.mlp_bytes;
+  }
+  if (fclose(fp) != 0) ok = false;
+  if (!ok) { c->err = std::string("writing the checkpoint ") + path + " failed"; return MF_EHIP; }
+  return MF_OK;
+}
+
+int mf_load(mf_ctx *c, const char *path) {
+  if (!c || !path) return MF_EINVAL;
+  join_side(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  FILE *fp = fopen(path, "rb");
+  if (!fp) { c->err = std::string("cannot open ") + path; return MF_EINVAL; }
+  CkptHeader h;
+  if (fread(&h, sizeof h, 1, fp) != 1 || memcmp(h.magic, kCkptMagic, 8) != 0 || h.abi != MF_ABI_VERSION ||
+      h.params_bytes != sizeof(mf_params)) {
+    fclose(fp);
+    c->err = "not a checkpoint of this library version";
+    return MF_EINVAL;
+  }
+  if (!params_equal(h.params, c->P) || h.arena_bytes != arena_bytes(c)) {
+    fclose(fp);
+    c->err = "the checkpoint was written by a context with other parameters";
+    return MF_EINVAL;
+  }
+  if (h.has_mlp && (c->kp.curvature != MF_CURV_MLP || h.mlp_bytes != kMlpWBytes + kMlpBBytes)) {
+    fclose(fp);
+    c->err = "the checkpoint holds a network the context cannot take";
+    return MF_EINVAL;
+  }
+  if (h.has_mlp && !c->mlp_buf) {
+    if (hipMalloc(&c->mlp_buf, kMlpWBytes + kMlpBBytes) != hipSuccess) {
+      fclose(fp);
+      c->err = "allocating the network weights failed";
+      return MF_ENOMEM;
+    }
+  }
+  std::vector<char> buf(kCkptChunk);
+  bool ok = true;
+  char *base = arena_base(c);
+  for (size_t off = 0; ok && off < h.arena_bytes; off += kCkptChunk) {
+    const size_t n = h.arena_bytes - off < kCkptChunk ? h.arena_bytes - off : kCkptChunk;
+    ok = fread(buf.data(), 1, n, fp) == n && hipMemcpy(base + off, buf.data(), n, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (ok && h.has_mlp)
+    ok = fread(buf.data(), 1, h.mlp_bytes, fp) == h.mlp_bytes &&
+         hipMemcpy(c->mlp_buf, buf.data(), h.mlp_bytes, hipMemcpyHostToDevice) == hipSuccess;
+  fclose(fp);
+  if (!ok) { c->err = std::string("reading the checkpoint ") + path + " failed (the state is undefined)"; return MF_EHIP; }
+  if (h.has_mlp) {
+    c->d.mlp_w = (const uint16_t *)c->mlp_buf;
+    c->d.mlp_b = (const float *)((char *)c->mlp_buf + kMlpWBytes);
+  }
+  c->step = h.step;
+  c->cur = h.cur;
+  c->parity = h.parity;
+  select_parity(c);
+  c->nucleated = h.nucleated != 0;
+  c->stepped = h.stepped != 0;
+  c->sword_dirty = h.sword_dirty != 0;
+  c->sword_fresh = h.sword_fresh != 0;
+  c->gas_dirty = h.gas_dirty != 0;
+  c->sweep_variant = h.sweep_variant;
+  c->epoch++;
+  return MF_OK;
+}
+
 int mf_attach_mlp(mf_ctx *c, const mf_mlp *m) {
   if (!c || !m) return MF_EINVAL;
   c->epoch++;
   if (c->kp.curvature != MF_CURV_MLP) { c->err = "the context was created for the plain curvature"; return MF_ESTATE; }
   // weights (bfloat16) and biases (binary32), 256-byte aligned
-  const size_t wbytes = (2 * (128 * 64 + 64 * 64 + 64) + 255) & ~(size_t)255;
-  const size_t bbytes = (4 * (2 * 64 + 1) + 255) & ~(size_t)255;
+  const size_t wbytes = kMlpWBytes, bbytes = kMlpBBytes;
   if (!c->mlp_buf) HIPCHK(c, hipMalloc(&c->mlp_buf, wbytes + bbytes));
   uint16_t *w = (uint16_t *)c->mlp_buf;
   float *b = (float *)((char *)c->mlp_buf + wbytes);

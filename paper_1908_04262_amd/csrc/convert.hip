@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
         ((R *)d.M)[n] = r;
       }
     }
-    wave_fx_add_runs(d.gam, emptied && lab >= 0 && lab < p.cap, lab, fx3((double)sg), d.gam0);
+    wave_fx_add_runs(d.gam, emptied && !p.flux_paper && lab >= 0 && lab < p.cap, lab, fx3((double)sg), d.gam0);
     wave_count_add(d.bng, emptied && lab > 0 && lab < p.cap, lab, 1);  // one more gas cell
   }
 }
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
       if (D == 3) ((R *)d.uz)[n] = ubz;
       ((R *)d.M)[n] = R(0);
     }
-    wave_fx_add_runs(d.gam, act && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg), d.gam0);
+    wave_fx_add_runs(d.gam, act && !p.flux_paper && lab >= 0 && lab < p.cap, lab, fx3(-(double)sg), d.gam0);
     wave_count_add(d.bng, act && lab > 0 && lab < p.cap, lab, -1);  // one gas cell fewer
   }
 }

@@ -431,6 +431,109 @@ __global__ __launch_bounds__(256) void k_write(KP p, DA d, int cur, int field, c
   }
 }
 
+// add the three chunks of a lane's fixed-point partial sums over the wave, one atomic
+// per chunk from lane 0 (integer sums: the result does not depend on the order)
+__device__ __forceinline__ void wave_chunks_add(long long *dst, long long l, long long m, long long h) {
+  for (int off = 32; off > 0; off >>= 1) {
+    l += __shfl_xor(l, off);
+    m += __shfl_xor(m, off);
+    h += __shfl_xor(h, off);
+  }
+  if (lane_id() == 0) {
+    atomicAdd((unsigned long long *)&dst[0], (unsigned long long)l);
+    atomicAdd((unsigned long long *)&dst[1], (unsigned long long)m);
+    atomicAdd((unsigned long long *)&dst[2], (unsigned long long)h);
+  }
+}
+
+__global__ void k_zero_ll(long long *a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+
+// Liquid mass (density of liquid cells, mass M of interface cells) and dissolved gas
+// (concentration of liquid and interface cells) summed over the grid, each cell's value
+// rounded to the fixed point of Fx3: a grid stride of at most 2^20 threads keeps every
+// lane's chunk sums far from overflow.
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_totals(KP p, DA d, int cur) {
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  using SG = typename Prec<P>::SG;
+  using L = Lat<D>;
+  const SF *f = (const SF *)d.f[cur];
+  const SG *g = (const SG *)d.g[cur];
+  long long ml = 0, mm = 0, mh = 0, cl = 0, cm = 0, ch = 0;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x) {
+    const int t = d.type[n] & TMASK;
+    if (t != TL && t != TI) continue;
+    double m;
+    if (t == TI) {
+      m = (double)((const R *)d.M)[n];
+    } else {
+      m = 0.0;
+      for (int i = 0; i < L::Q; ++i) m += FCodec<P, D>::full(f[(int64_t)i * p.Np + n], i);
+    }
+    double c = 0.0;
+    for (int i = 0; i < L::Qg; ++i)
+      c += (double)GCodec<P>::dec(g[(int64_t)i * p.Np + n], p) + (P != 0 ? L::wg[i] * p.c0 : 0.0);
+    const Fx3 a = fx3(m), b = fx3(c);
+    ml += a.l; mm += a.m; mh += a.h;
+    cl += b.l; cm += b.m; ch += b.h;
+  }
+  wave_chunks_add(d.tacc, ml, mm, mh);
+  wave_chunks_add(d.tacc + 3, cl, cm, ch);
+}
+
+// Per bubble id: the number of its gas and interface cells and the fixed-point sums of
+// w = 1 - alpha (its gas volume) and of w x, w y, w z (first moments of that volume).
+template <int P>
+__global__ __launch_bounds__(256) void k_bubble_stats(KP p, DA d) {
+  using R = typename Prec<P>::R;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t n0 = start - (start & 63); n0 < p.N; n0 += stride) {
+    const int64_t n = n0 + lane_id();
+    bool on = false;
+    int lab = 0;
+    double w = 0.0;
+    int x = 0, y = 0, z = 0;
+    if (n < p.N) {
+      const int t = d.type[n] & TMASK;
+      lab = d.label[n];
+      on = (t == TG || t == TI) && lab > 0 && lab < p.cap;
+      if (on) {
+        w = t == TG ? 1.0 : 1.0 - (double)((const R *)d.alpha)[n];
+        cell_xyz(p, n, x, y, z);
+      }
+    }
+    wave_count_add_ll(d.bstat, on, lab);
+    wave_fx_add(d.bstat + 1, on, lab, fx3(w), nullptr, 13);
+    wave_fx_add(d.bstat + 4, on, lab, fx3(w * x), nullptr, 13);
+    wave_fx_add(d.bstat + 7, on, lab, fx3(w * y), nullptr, 13);
+    wave_fx_add(d.bstat + 10, on, lab, fx3(w * z), nullptr, 13);
+  }
+}
+
+// one element of a field in its storage form (fault-injection tests)
+template <int D, int P>
+__global__ void k_poke(KP p, DA d, int cur, int field, int64_t n, int comp, double v) {
+  using R = typename Prec<P>::R;
+  using SF = typename Prec<P>::SF;
+  using SG = typename Prec<P>::SG;
+  using L = Lat<D>;
+  switch (field) {
+    case MF_FIELD_F: ((SF *)d.f[cur])[(int64_t)comp * p.Np + n] = FCodec<P, D>::from_full(v, comp); break;
+    case MF_FIELD_G:
+      ((SG *)d.g[cur])[(int64_t)comp * p.Np + n] = GCodec<P>::enc((R)(v - (P != 0 ? L::wg[comp] * p.c0 : 0.0)), p);
+      break;
+    case MF_FIELD_RHO: ((R *)d.rho)[n] = (R)v; break;
+    case MF_FIELD_ALPHA: ((R *)d.alpha)[n] = (R)v; break;
+    case MF_FIELD_MASS: ((R *)d.M)[n] = (R)v; break;
+    default: break;
+  }
+}
+
 static unsigned grid_blocks(const Ctx &c) {
   int64_t b = (c.kp.N + 255) / 256;
   if (b > 65536) b = 65536;
@@ -485,12 +588,36 @@ void Ops<D, P>::write_field(Ctx &c, hipStream_t s, int field, const double *src_
   }
 }
 
+template <int D, int P>
+void Ops<D, P>::totals(Ctx &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ll, dim3(1), dim3(64), 0, s, c.d.tacc, (int64_t)6);
+  int64_t b = (c.kp.N + 255) / 256;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL((k_totals<D, P>), dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, c.kp, c.d, c.cur);
+}
+
+template <int D, int P>
+void Ops<D, P>::bubble_stats(Ctx &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ll, dim3(64), dim3(256), 0, s, c.d.bstat, (int64_t)c.kp.cap * 13);
+  int64_t b = (c.kp.N + 255) / 256;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL((k_bubble_stats<P>), dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, c.kp, c.d);
+}
+
+template <int D, int P>
+void Ops<D, P>::poke(Ctx &c, hipStream_t s, int field, int64_t cell, int comp, double value) {
+  hipLaunchKernelGGL((k_poke<D, P>), dim3(1), dim3(1), 0, s, c.kp, c.d, c.cur, field, cell, comp, value);
+}
+
 #define MF_INST(D, P)                                                                  \
   template void Ops<D, P>::init_box(Ctx &, hipStream_t);                               \
   template void Ops<D, P>::nucleate(Ctx &, hipStream_t, int, const double *, const double *); \
   template void Ops<D, P>::build_lists(Ctx &, hipStream_t);                            \
   template void Ops<D, P>::read_field(Ctx &, hipStream_t, int, double *);              \
-  template void Ops<D, P>::write_field(Ctx &, hipStream_t, int, const double *);
+  template void Ops<D, P>::write_field(Ctx &, hipStream_t, int, const double *);       \
+  template void Ops<D, P>::totals(Ctx &, hipStream_t);                                 \
+  template void Ops<D, P>::bubble_stats(Ctx &, hipStream_t);                           \
+  template void Ops<D, P>::poke(Ctx &, hipStream_t, int, int64_t, int, double);
 MF_FOR_ALL(MF_INST)
 
 }  // namespace mf

@@ -148,6 +148,7 @@ struct KP {
   float cy_lk;      // lambda (3 / sqrt 2): lambda gdot = cy_lk |Pi_neq| / (rho tau)
   float cy_m;       // (n - 1) / a
   int force;        // body-force acceleration a is non-zero
+  int flux_paper;   // gas flux of Eq. gascurrent as printed instead of the ledger
   double ax, ay, az;
   float fax, fay, faz;
 };
@@ -194,6 +195,9 @@ struct DA {
   int32_t *rused;             // used root-hash slots [ecap]
   int32_t *contested;         // [ecap]
   double *scratch_d;          // [cap] spare
+  long long *tacc;            // liquid mass and dissolved gas, fixed point [2][3]
+  long long *bstat;           // per id: cell count, then Fx3 sums of w, w x, w y, w z
+                              // (w = 1 - alpha) [cap][13]
   // learned curvature (NULL unless a network is attached)
   const uint16_t *mlp_w;      // bfloat16 W1 [128][64], W2 [64][64], W3 [64]
   const float *mlp_b;         // b1 [64], b2 [64], b3
@@ -242,7 +246,7 @@ constexpr int NSPREAD = 64;
 // add a fixed-point value to acc[key*3 .. +2] for every lane with pred; lanes that share
 // a key are summed inside the wave first. Called by the whole wave.
 __device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, Fx3 v,
-                                            long long *spread0 = nullptr) {
+                                            long long *spread0 = nullptr, int stride = 3) {
   unsigned long long act = __ballot(pred);
   int lane = lane_id();
   while (act) {
@@ -257,7 +261,7 @@ __device__ __forceinline__ void wave_fx_add(long long *acc, bool pred, int key, 
       sh += __shfl_xor(sh, off);
     }
     if (lane == leader) {
-      long long *dst = k == 0 && spread0 ? spread0 + 3 * (blockIdx.x & (NSPREAD - 1)) : acc + 3 * k;
+      long long *dst = k == 0 && spread0 ? spread0 + 3 * (blockIdx.x & (NSPREAD - 1)) : acc + (int64_t)stride * k;
       atomicAdd((unsigned long long *)&dst[0], (unsigned long long)sl);
       atomicAdd((unsigned long long *)&dst[1], (unsigned long long)sm);
       atomicAdd((unsigned long long *)&dst[2], (unsigned long long)sh);
@@ -306,6 +310,20 @@ __device__ __forceinline__ void wave_count_add(int32_t *acc, bool pred, int key,
     const int k = __shfl(key, leader);
     const unsigned long long mm = __ballot(pred && key == k);
     if (lane_id() == leader) atomicAdd(&acc[k], v * (int)__popcll(mm));
+    act &= ~mm;
+    pred = pred && key != k;
+  }
+}
+
+// add one to acc[13 * key] (64-bit) for every lane with pred, one atomic per key and
+// wave. Called by the whole wave.
+__device__ __forceinline__ void wave_count_add_ll(long long *acc, bool pred, int key) {
+  unsigned long long act = __ballot(pred);
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int k = __shfl(key, leader);
+    const unsigned long long mm = __ballot(pred && key == k);
+    if (lane_id() == leader) atomicAdd((unsigned long long *)&acc[13 * (int64_t)k], (unsigned long long)__popcll(mm));
     act &= ~mm;
     pred = pred && key != k;
   }
@@ -404,6 +422,12 @@ template <int D, int P> struct Ops {
   static void build_lists(Ctx &c, hipStream_t s);
   static void read_field(Ctx &c, hipStream_t s, int field, double *dst_dev);
   static void write_field(Ctx &c, hipStream_t s, int field, const double *src_dev);
+  // liquid mass and dissolved gas over the grid into d.tacc (fixed point, cleared first)
+  static void totals(Ctx &c, hipStream_t s);
+  // per-id cell counts and gas-volume moments into d.bstat (cleared first)
+  static void bubble_stats(Ctx &c, hipStream_t s);
+  // overwrite one element of a field in its storage form
+  static void poke(Ctx &c, hipStream_t s, int field, int64_t cell, int comp, double value);
 };
 
 struct Ctx {
@@ -452,8 +476,8 @@ extern thread_local std::string g_thread_err;
 
 // bulk-sweep variants the tuner chooses from: cells per thread x threads per work-group
 struct SweepVariant { int vw, bs; };
-constexpr SweepVariant kSweepVariants[] = {{4, 256}, {2, 256}, {4, 128}, {2, 128}};
-constexpr int kNumSweepVariants = 4;
+constexpr SweepVariant kSweepVariants[] = {{4, 256}, {2, 256}, {4, 128}, {2, 128}, {8, 256}, {8, 128}, {8, 64}, {4, 64}};
+constexpr int kNumSweepVariants = 8;
 
 // work-groups of the list builder (one per chunk of cells)
 int list_blocks_of(const KP &kp);

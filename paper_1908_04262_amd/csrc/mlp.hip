@@ -7,6 +7,8 @@
 // activations are rounded to bfloat16 before each product; weights are rounded from the
 // binary32 master copy. The curvature enters the gas density of Eq. rhob.
 #include <math.h>
+#include <stdio.h>
+#include <string.h>
 
 #include <mutex>
 #include <string>
@@ -783,6 +785,46 @@ int mf_mlp_destroy(mf_mlp *m) {
     if (b) (void)hipFree(b);
   if (m->loss) (void)hipFree(m->loss);
   delete m;
+  return MF_OK;
+}
+
+// network file: magic, parameter count, the binary32 master parameters
+static const char kMlpMagic[8] = {'M', 'I', 'F', 'O', 'A', 'M', 'N', 'N'};
+
+int mf_mlp_save(const mf_mlp *m, const char *path) {
+  if (!m || !path) return fail("NULL argument", MF_EINVAL);
+  std::vector<float> th(NPARAM);
+  MLPCHK(hipMemcpy(th.data(), m->theta, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+  FILE *fp = fopen(path, "wb");
+  if (!fp) return fail(std::string("cannot open ") + path + " for writing", MF_EINVAL);
+  const int32_t np = NPARAM;
+  bool ok = fwrite(kMlpMagic, 1, 8, fp) == 8 && fwrite(&np, 4, 1, fp) == 1 &&
+            fwrite(th.data(), sizeof(float), NPARAM, fp) == (size_t)NPARAM;
+  if (fclose(fp) != 0) ok = false;
+  return ok ? MF_OK : fail(std::string("writing ") + path + " failed", MF_EHIP);
+}
+
+int mf_mlp_load(mf_mlp **out, const char *path) {
+  if (!out || !path) return fail("NULL argument", MF_EINVAL);
+  *out = nullptr;
+  FILE *fp = fopen(path, "rb");
+  if (!fp) return fail(std::string("cannot open ") + path, MF_EINVAL);
+  char magic[8];
+  int32_t np = 0;
+  std::vector<float> th(NPARAM);
+  const bool ok = fread(magic, 1, 8, fp) == 8 && memcmp(magic, kMlpMagic, 8) == 0 && fread(&np, 4, 1, fp) == 1 &&
+                  np == NPARAM && fread(th.data(), sizeof(float), NPARAM, fp) == (size_t)NPARAM;
+  fclose(fp);
+  if (!ok) return fail(std::string(path) + " is not a network file of this library", MF_EINVAL);
+  mf_mlp *m = nullptr;
+  const int rc = mf_mlp_create(0, &m);
+  if (rc) return rc;
+  const hipError_t e = hipMemcpy(m->theta, th.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    mf_mlp_destroy(m);
+    return fail(std::string("hipMemcpy: ") + hipGetErrorString(e), MF_EHIP);
+  }
+  *out = m;
   return MF_OK;
 }
 

@@ -334,7 +334,8 @@ template <int D, int P, class Src, class Dst>
 __device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64_t n, bool isI, int32_t lab,
                                               Src src, Dst dst, typename Prec<P>::R *ft, typename Prec<P>::R *gt,
                                               typename Prec<P>::R &Ms, bool &hasG, bool &hasF,
-                                              typename Prec<P>::R &phic, bool &hasgas) {
+                                              typename Prec<P>::R &phic, bool &hasgas,
+                                              typename Prec<P>::R &pf, typename Prec<P>::R &aold) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
@@ -408,6 +409,18 @@ __device__ __forceinline__ void special_terms(const KP &p, DA &d, int cur, int64
       }
     }
     Ms = Mo + dm;
+    if (p.flux_paper) {
+      // Eq. gascurrent as printed: what the liquid and interface neighbours y = x + e_i
+      // send towards the cell minus what it sends to them
+      R s = R(0);
+#pragma unroll
+      for (int i = 1; i < Qg; ++i) {
+        const int tn = tsrc[opp(i)];
+        if (tn == TL || tn == TI) s = s + (gt[opp(i)] - gown[i]);
+      }
+      pf = s;
+      aold = ax;
+    }
   }
 }
 
@@ -463,15 +476,26 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
       ft[i] = FC::dec(fin[(int64_t)i * Np + s], i);
       if (i < Qg) gt[i] = GC::dec(gin[(int64_t)i * Np + s], p);
     }
-    R Ms = R(0);
+    R Ms = R(0), pf = R(0), aold = R(0), cx = R(0);
     bool hasG = false, hasF = false;
     if (isI || (tb & NEARWALL)) {
       auto src = [&](int i) { return nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]); };
       auto dst = [&](int i) { return nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]); };
-      special_terms<D, P>(p, d, cur, n, isI, lab, src, dst, ft, gt, Ms, hasG, hasF, phic, hasgas);
+      special_terms<D, P>(p, d, cur, n, isI, lab, src, dst, ft, gt, Ms, hasG, hasF, phic, hasgas, pf, aold);
+    }
+    if (isI && p.flux_paper) {
+      // streamed concentration (the offset form holds c - c0)
+      cx = P != 0 ? R(p.c0) : R(0);
+#pragma unroll
+      for (int i = 0; i < Qg; ++i) cx = cx + gt[i];
     }
     R rho, ux, uy, uz;
     collide_cell<D, P, FRC>(p, d, ft, gt, rho, ux, uy, uz);
+    if (isI && p.flux_paper) {
+      // less the advected part c (alpha_new - alpha_old); every interface cell books it
+      phic = pf - cx * (Ms / rho - aold);
+      hasgas = true;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) fout[(int64_t)i * Np + n] = FC::enc(ft[i], i);
 #pragma unroll
@@ -784,6 +808,10 @@ bool Ops<D, P>::sweep_bulk(Ctx &c, hipStream_t s, int variant) {
       case 1: return launch_bulk<D, P, 2, 256>(c, s);
       case 2: return launch_bulk<D, P, 4, 128>(c, s);
       case 3: return launch_bulk<D, P, 2, 128>(c, s);
+      case 4: return launch_bulk<D, P, 8, 256>(c, s);
+      case 5: return launch_bulk<D, P, 8, 128>(c, s);
+      case 6: return launch_bulk<D, P, 8, 64>(c, s);
+      case 7: return launch_bulk<D, P, 4, 64>(c, s);
       default: return false;
     }
   }

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmifoam.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "f16s": 2, "bf16s": 3, "f16s_g16": 4}
+FLUX_MODES = {"ledger": 0, "paper": 1}
 FIELDS = dict(type=0, label=1, rho=2, ux=3, uy=4, uz=5, alpha=6, mass=7, conc=8,
               kappa=9, pi=10, f=11, g=12)
 STATUS = {0: "MF_OK", -1: "MF_EINVAL", -2: "MF_ENOMEM", -3: "MF_EHIP", -4: "MF_ECAPACITY",
@@ -35,19 +36,21 @@ class MfParams(C.Structure):
         ("pl_n", C.c_double), ("pl_nu_ref", C.c_double), ("pl_gdot_ref", C.c_double),
         ("tau_min", C.c_double), ("tau_max", C.c_double), ("accel", C.c_double * 3),
         ("cy_tau0", C.c_double), ("cy_tau_inf", C.c_double), ("cy_lambda", C.c_double),
-        ("cy_a", C.c_double), ("cy_n", C.c_double),
+        ("cy_a", C.c_double), ("cy_n", C.c_double), ("flux_mode", C.c_int32),
     ]
 
 
 class MfBubble(C.Structure):
     _fields_ = [("id", C.c_int32), ("alive", C.c_int32), ("volume", C.c_double),
-                ("gas_mass", C.c_double), ("pressure", C.c_double)]
+                ("gas_mass", C.c_double), ("pressure", C.c_double), ("n_cells", C.c_int32),
+                ("reserved", C.c_int32), ("centroid", C.c_double * 3)]
 
 
 class MfTotals(C.Structure):
     _fields_ = [("step", C.c_int64), ("lost_liquid", C.c_double), ("atm_gas", C.c_double),
                 ("collapsed_gas", C.c_double), ("next_id", C.c_int32),
-                ("n_bubbles", C.c_int32), ("n_interface", C.c_int32), ("status", C.c_int32)]
+                ("n_bubbles", C.c_int32), ("n_interface", C.c_int32), ("status", C.c_int32),
+                ("liquid_mass", C.c_double), ("dissolved_gas", C.c_double), ("bubble_gas", C.c_double)]
 
 
 class MfMlpTrainSpec(C.Structure):
@@ -64,8 +67,9 @@ EXPORTS = ["mf_abi_version", "mf_last_error", "mf_workspace_bytes", "mf_create",
            "mf_mlp_destroy", "mf_mlp_train", "mf_mlp_get_params", "mf_mlp_set_params",
            "mf_mlp_generate", "mf_mlp_eval", "mf_mlp_eval_noalloc", "mf_mlp_grad", "mf_attach_mlp", "mf_tune",
            "mf_set_sweep_variant", "mf_batch_create", "mf_batch_tune", "mf_batch_step",
-           "mf_batch_destroy", "mf_poisson_nuclei"]
-SWEEP_VARIANTS = 4
+           "mf_batch_destroy", "mf_poisson_nuclei", "mf_save", "mf_load", "mf_debug_poke",
+           "mf_mlp_save", "mf_mlp_load"]
+SWEEP_VARIANTS = 8
 
 _LIB = None
 
@@ -118,6 +122,11 @@ def load_library():
     lib.mf_batch_tune.argtypes = [vp, C.c_int32, vp]
     lib.mf_batch_step.argtypes = [vp, C.c_int32]
     lib.mf_batch_destroy.argtypes = [vp]
+    lib.mf_save.argtypes = [vp, C.c_char_p]
+    lib.mf_load.argtypes = [vp, C.c_char_p]
+    lib.mf_debug_poke.argtypes = [vp, C.c_int32, C.c_int64, C.c_int32, C.c_double]
+    lib.mf_mlp_save.argtypes = [vp, C.c_char_p]
+    lib.mf_mlp_load.argtypes = [C.POINTER(vp), C.c_char_p]
     _LIB = lib
     return lib
 
@@ -143,6 +152,7 @@ def make_params(wl: dict) -> MfParams:
         p.accel[a] = float(v)
     for k, d in (("cy_tau0", 0.8), ("cy_tau_inf", 0.8), ("cy_lambda", 0.0), ("cy_a", 2.0), ("cy_n", 1.0)):
         setattr(p, k, float(wl.get(k, d)))
+    p.flux_mode = FLUX_MODES[wl.get("flux_mode", "ledger")]
     return p
 
 
@@ -268,14 +278,27 @@ class Sim:
         return dict(id=np.array([arr[i].id for i in range(k)], np.int32),
                     m=np.array([arr[i].gas_mass for i in range(k)]),
                     V=np.array([arr[i].volume for i in range(k)]),
-                    p=np.array([arr[i].pressure for i in range(k)]))
+                    p=np.array([arr[i].pressure for i in range(k)]),
+                    n_cells=np.array([arr[i].n_cells for i in range(k)], np.int32),
+                    centroid=np.array([list(arr[i].centroid) for i in range(k)]).reshape(k, 3))
 
     def ledgers(self):
         t = MfTotals()
         self._check(self.lib.mf_totals_get(self.h, C.byref(t)))
         return dict(lost_liquid=t.lost_liquid, atm_gas=t.atm_gas, collapsed_gas=t.collapsed_gas,
                     next_id=t.next_id, step=t.step, n_bubbles=t.n_bubbles,
-                    n_interface=t.n_interface, status=t.status)
+                    n_interface=t.n_interface, status=t.status, liquid=t.liquid_mass,
+                    dissolved=t.dissolved_gas, bubble_gas=t.bubble_gas)
+
+    def save(self, path):
+        self._check(self.lib.mf_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._check(self.lib.mf_load(self.h, os.fsencode(path)))
+
+    def poke(self, name, cell, comp, value):
+        """overwrite one element of a field in its storage form (fault-injection tests)"""
+        self._check(self.lib.mf_debug_poke(self.h, FIELDS[name], int(cell), int(comp), float(value)))
 
     def attach_mlp(self, net):
         self._check(self.lib.mf_attach_mlp(self.h, net.h))
@@ -302,16 +325,8 @@ class Sim:
 
     def totals(self):
         """Liquid mass (rho over liquid cells plus M over interface cells), dissolved and
-        bubble gas, and the ledgers."""
-        T = self.read("type")
-        f = self.read("f")
-        M = self.read("mass")
-        liquid = f.sum(axis=0)[T == 2].sum() + M[T == 1].sum()
-        conc = self.read("conc")
-        dissolved = conc[(T == 2) | (T == 1)].sum()
-        b = self.bubbles()
-        led = self.ledgers()
-        return dict(liquid=liquid, dissolved=dissolved, bubble_gas=b["m"].sum(), **led)
+        bubble gas (summed by the library on the device), and the ledgers."""
+        return self.ledgers()
 
 
 class Batch:
@@ -395,6 +410,20 @@ class CurvatureNet:
         rmse = C.c_double()
         _check_plain(self.lib, self.lib.mf_mlp_train(self.h, C.byref(spec), _stream_ptr(), C.byref(rmse)))
         return rmse.value
+
+    def save(self, path):
+        _check_plain(self.lib, self.lib.mf_mlp_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        """a network read from a file written by save()"""
+        net = cls.__new__(cls)
+        net.lib = load_library()
+        net.nparam = net.lib.mf_mlp_param_count()
+        h = C.c_void_p()
+        _check_plain(net.lib, net.lib.mf_mlp_load(C.byref(h), os.fsencode(path)))
+        net.h = h
+        return net
 
     def eval(self, stencils):
         X = np.ascontiguousarray(stencils, dtype=np.float32).reshape(-1, 125)
