@@ -21,11 +21,19 @@ and with the tuned bulk sweep and one graph launch per two steps of all domains.
 The roofline entry is the bulk sweep kernel: algorithmic bytes per launch over its
 average duration inside the timed steps, measured with events on its stream; there it
 shares the GPU with the previous step's labelling and geometry, which run on a second
-stream. ``roofline.isolated`` times the same kernel launched alone, back to back.
+stream. ``roofline.isolated`` times the same kernel launched alone, back to back. Before
+each timed window the library's tuner picks the bulk kernel's launch shape on the live
+state (untimed).
+
+After its timed window the reported run advances to step 2000 and times the same number
+of steps there (``late_state``: the bubbles have grown, more cells are interface and gas).
+``accuracy_vs_oracle`` compares the production form with the FP64 oracle on a 96^3 crop of
+the same recipe (liquid-mass drift, bubble-volume error). ``cpu_baseline`` runs the
+single-threaded oracle on that crop, once alone and as one copy per host core.
 
 Prints one JSON line. Options: --gpus N (only 1), --steps K, --warmup W,
 --workload NAME, --no-cpu-baseline, --mlp-train N, --mlp-epochs E, --no-ensemble,
---ensemble-steps S.
+--ensemble-steps S, --late-steps L, --accuracy-steps A.
 """
 import argparse
 import hashlib
@@ -67,6 +75,8 @@ def measured_traffic(kernel):
     m = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": (\d+)", text)
     return int(m.group(1)) if m else None
 METRIC = "MLUPS & %HBM peak, 384^3 foam; FP16-store+MLP-curvature vs FP32 plain"
+# launch shapes of the bulk sweep (cells per thread, threads per work-group), by variant
+VARIANTS = [(4, 256), (2, 256), (4, 128), (2, 128), (8, 256), (8, 128), (8, 64), (4, 64)]
 
 
 BYTES_F = {"fp64": 8, "fp32": 4, "f16s": 2, "bf16s": 2, "f16s_g16": 2}
@@ -140,7 +150,45 @@ def time_field_nucleation(wl, log):
             "field": "linear in x from 0.1 to 1", "host": True}
 
 
-def run_one(wl, steps, warmup, log, net=None):
+def late_window(sim, wl, until, steps, log):
+    """Advance the foam to step `until` and time `steps` more steps there: the bubbles have
+    grown, so more cells are interface and gas than in the first window."""
+    import numpy as np
+    import torch
+
+    done = sim.ledgers()["step"]
+    t0 = time.perf_counter()
+    while done < until:
+        n = min(500, until - done)
+        sim.step(n)
+        sim.sync()
+        done += n
+        log(f"[{wl['precision']}] late state: step {done}")
+    adv = time.perf_counter() - t0
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    sim.sync()
+    bulk_ms, nsw = sim.profile_get(0)
+    spec_ms, _ = sim.profile_get(2)
+    sim.profile(False)
+    T = sim.read("type")
+    led = sim.ledgers()
+    ncell = int(np.prod(sim.shape))
+    out = dict(step=int(done), steps=steps, mlups=round(ncell * steps / wall / 1e6, 2),
+               ms_per_step=round(wall * 1e3 / steps, 4), bulk_sweep_ms=round(bulk_ms / max(nsw, 1), 4),
+               special_sweep_ms=round(spec_ms / max(nsw, 1), 4),
+               interface_fraction=round(float(np.count_nonzero(T == 1)) / ncell, 5),
+               gas_fraction=round(float(np.count_nonzero(T == 0)) / ncell, 5),
+               n_bubbles=led["n_bubbles"], advance_seconds=round(adv, 2))
+    log(f"[{wl['precision']}] late state {json.dumps(out)}")
+    return out
+
+
+def run_one(wl, steps, warmup, log, net=None, late_steps=0):
     import numpy as np
     import torch
 
@@ -156,7 +204,10 @@ def run_one(wl, steps, warmup, log, net=None):
     log(f"[{wl['precision']}] created + nucleated {len(r)} nuclei in {time.time() - t0:.1f}s")
     sim.step(warmup)
     sim.sync()
-    log(f"[{wl['precision']}] warmup {warmup} steps done")
+    # the project's tuner picks the bulk-sweep launch shape on the live state (untimed)
+    variant, tune_ms = sim.tune(5)
+    log(f"[{wl['precision']}] warmup {warmup} steps done; tuned bulk-sweep shape {variant} "
+        f"({[round(float(x), 3) for x in tune_ms]} ms)")
     T0 = sim.read("type")
     bytes0, np0, per_cell = sweep_bytes(wl, T0, wl["precision"])
     sim.profile(True)
@@ -175,7 +226,8 @@ def run_one(wl, steps, warmup, log, net=None):
     # the bulk kernel alone (back-to-back launches on the final state, nothing beside it):
     # inside the step it shares the GPU with the previous step's labelling and geometry
     _, tune_ms = sim.tune(20)
-    iso_ms = float(tune_ms[1 if wl["precision"] == "fp32" else 0])
+    sim.set_sweep_variant(variant)
+    iso_ms = float(tune_ms[variant])
     led = sim.ledgers()
     ncell = int(np.prod(sim.shape))
     wall = t2 - t1
@@ -205,6 +257,9 @@ def run_one(wl, steps, warmup, log, net=None):
     # over the wall time of a step
     step_bytes = n_fluid * per_cell + (ncell - n_fluid)
     res["hbm_frac_step"] = step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS
+    res["bulk_variant"] = int(variant)
+    if late_steps > 0:
+        res["late_state"] = late_window(sim, wl, late_steps, steps, log)
     log(f"[{wl['precision']}/{wl['curvature']}] {json.dumps(res)}")
     sim.close()
     del sim
@@ -263,34 +318,107 @@ def run_ensemble(net, steps, log):
             "tuned_variants": [int(v) for v in variants]}
 
 
-def cpu_baseline(log, budget_s=20.0):
-    """The FP64 oracle on the host: the same recipe (power-law foam, supersaturation
-    1.5, r ~ U[2,4]) on a 96^3 crop with the bubble density of the 384^3 case, timed over
-    a few steps."""
-    import numpy as np
+def crop_workload(n=96):
+    """the 384^3 recipe (power-law foam, supersaturation 1.5, r ~ U[2,4]) on an n^3 crop
+    with the same bubble density"""
+    from synth import workload
 
-    from oracle import Oracle
-    from synth import place_nuclei, workload
-
-    n = 96
     frac = (n / 384.0) ** 3
     wl = workload("c3_foam_384", nx=n, ny=n, nz=n, precision="fp64", max_ids=4096)
     wl["gas_from"] = int(0.75 * n)
     wl["nuclei"] = dict(wl["nuclei"], n=max(1, int(round(2000 * frac))))
+    return wl
+
+
+def _oracle_crop_rate(args):
+    """one process: the oracle on the crop for `steps` steps; returns seconds"""
+    n, steps = args
+    from oracle import Oracle
+    from synth import place_nuclei
+
+    wl = crop_workload(n)
     o = Oracle(wl)
     o.nucleate(*place_nuclei(wl))
     t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < budget_s and steps < 50:
-        o.step(1)
-        steps += 1
-    dt = time.perf_counter() - t0
+    o.step(steps)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(log, budget_s=10.0):
+    """The FP64 oracle on the host on a 96^3 crop of the benchmark recipe: first one
+    process (the oracle is single-threaded), then one independent copy per host core (at
+    most 16, the machine's CPU share), each on the same crop; the aggregate rate of the copies
+    is the value."""
+    import multiprocessing as mp
+
+    n = 96
     ncell = n ** 3
-    v = ncell * steps / dt / 1e6
-    log(f"cpu baseline: {steps} steps of {n}^3 in {dt:.1f}s -> {v:.3f} MLUPS")
-    return dict(value=v, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{steps} steps of the FP64 oracle on a {n}^3 crop of the 384^3 recipe "
-                       f"({wl['nuclei']['n']} nuclei), single thread")
+    t1 = _oracle_crop_rate((n, 4))
+    steps = max(2, min(50, int(budget_s / max(t1 / 4, 1e-3))))
+    single = ncell * 4 / t1 / 1e6
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        secs = pool.map(_oracle_crop_rate, [(n, steps)] * cores)
+    wall = time.perf_counter() - t0
+    agg = cores * ncell * steps / max(secs) / 1e6
+    log(f"cpu baseline: 1 process {single:.3f} MLUPS; {cores} processes x {steps} steps of {n}^3 "
+        f"in {wall:.1f}s -> {agg:.3f} MLUPS ({cpu_model()})")
+    return dict(value=agg, unit="MLUPS", cores=cores, kind="oracle",
+                single_thread_value=single, cpu_model=cpu_model(),
+                sample=f"{cores} independent single-threaded FP64 oracle processes, {steps} steps each of a "
+                       f"{n}^3 crop of the 384^3 recipe ({crop_workload(n)['nuclei']['n']} nuclei); the "
+                       f"oracle itself is single-threaded")
+
+
+def crop_accuracy(net, steps, log):
+    """Error of the production form (binary16 f and g, learned curvature) against the FP64
+    oracle on the 96^3 crop: relative liquid-mass drift and the largest relative bubble
+    volume deviation, over `steps` steps (compared only while the oracle's bubble ids are
+    unchanged)."""
+    import numpy as np
+
+    from oracle import Oracle
+    from paper_1908_04262_amd import Sim
+    from synth import place_nuclei
+
+    wl64 = crop_workload(96)
+    wl = dict(wl64, precision="f16s_g16", curvature="mlp")
+    gpu = Sim(wl)
+    gpu.attach_mlp(net)
+    orc = Oracle(wl64)
+    c, r, p0 = place_nuclei(wl64)
+    gpu.nucleate(c, r, p0)
+    orc.nucleate(c, r, p0)
+    t0 = gpu.totals()
+    m0 = t0["liquid"] + t0["lost_liquid"]
+    worst_v, worst_m, compared, done = 0.0, 0.0, 0, 0
+    chunk = max(1, steps // 5)
+    while done < steps:
+        gpu.step(chunk)
+        orc.step(chunk)
+        done += chunk
+        t = gpu.totals()
+        worst_m = max(worst_m, abs(t["liquid"] + t["lost_liquid"] - m0) / m0)
+        bg, bo = gpu.bubbles(), orc.bubbles()
+        if list(bg["id"]) == list(bo["id"]) and bo["id"].size:
+            worst_v = max(worst_v, float((np.abs(bg["V"] - bo["V"]) / bo["V"]).max()))
+            compared += 1
+    gpu.close()
+    out = dict(steps=done, mass_drift=worst_m, max_volume_error=worst_v, comparisons=compared,
+               crop="96^3 crop of the 384^3 recipe", reference="FP64 oracle, plain curvature")
+    log(f"[accuracy] {json.dumps(out)}")
+    return out
 
 
 def main():
@@ -301,7 +429,9 @@ def main():
     ap.add_argument("--workload", default="c3_foam_384")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mlp-train", type=int, default=1966080)
-    ap.add_argument("--mlp-epochs", type=int, default=4)
+    ap.add_argument("--mlp-epochs", type=int, default=8)
+    ap.add_argument("--late-steps", type=int, default=2000)
+    ap.add_argument("--accuracy-steps", type=int, default=25)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--quiet", action="store_true")
@@ -320,7 +450,8 @@ def main():
     wl = workload(a.workload)
     r32 = run_one(dict(wl, precision="fp32", curvature="plain"), a.steps, a.warmup, log)
     net, train_info = train_net(a.mlp_train, a.mlp_epochs, log)
-    r16 = run_one(dict(wl, precision="f16s_g16", curvature="mlp"), a.steps, a.warmup, log, net=net)
+    r16 = run_one(dict(wl, precision="f16s_g16", curvature="mlp"), a.steps, a.warmup, log, net=net,
+                  late_steps=a.late_steps)
     r16f = run_one(dict(wl, precision="f16s", curvature="mlp"), a.steps, a.warmup, log, net=net)
     # the same foam under gravity (body-force term, forced kernel instances)
     grav = (0.0, 0.0, -3e-5)
@@ -333,13 +464,15 @@ def main():
     nuc = time_field_nucleation(wl, log)
     ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
+    acc = None if a.accuracy_steps <= 0 else crop_accuracy(net, a.accuracy_steps, log)
 
     def brief(r):
         return {"mlups": round(r["mlups"], 2), "ms_per_step": round(r["ms_per_step"], 4),
                 "hbm_frac_step": round(r["hbm_frac_step"], 4),
                 "bulk_sweep_gbs": round(r["bulk_sweep_gbs"], 1),
                 "bulk_sweep_ms": round(r["bulk_sweep_ms"], 4),
-                "special_sweep_ms": round(r["special_sweep_ms"], 4)}
+                "special_sweep_ms": round(r["special_sweep_ms"], 4),
+                "bulk_variant": r["bulk_variant"]}
 
     out = {
         "metric": METRIC,
@@ -370,14 +503,18 @@ def main():
         "carreau_yasuda": dict(brief(r16c), params={k: v for k, v in cy.items() if k != "rheology"},
                                steps=max(a.steps // 2, 1)),
         "speedup_vs_fp32_plain": round(r16["mlups"] / r32["mlups"], 3),
+        "late_state": r16.get("late_state"),
+        "accuracy_vs_oracle": acc,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep_vec<3,4,4,256> (bulk sweep, binary16 f and g)",
+            "kernel": f"k_sweep_vec<3,4,{VARIANTS[r16['bulk_variant']][0]},{VARIANTS[r16['bulk_variant']][1]}> "
+                      "(bulk sweep, binary16 f and g)",
             "achieved": round(r16["bulk_sweep_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(r16["bulk_sweep_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("k_sweep_vec<3,4,4,256>"),
+            "traffic": measured_traffic(f"k_sweep_vec<3,4,{VARIANTS[r16['bulk_variant']][0]},"
+                                        f"{VARIANTS[r16['bulk_variant']][1]}>"),
             "bytes_per_launch": r16["bulk_sweep_bytes"],
             "avg_launch_ms": round(r16["bulk_sweep_ms"], 4),
             "isolated": {"achieved": round(r16["bulk_isolated_gbs"], 1),

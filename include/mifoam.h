@@ -405,24 +405,31 @@ int mf_tune(mf_ctx *ctx, int32_t reps, int32_t *best_variant, float *ms_per_vari
 int mf_set_sweep_variant(mf_ctx *ctx, int32_t variant);
 
 /* A batch of n distinct contexts (created, nucleated and, for the learned curvature,
- * with a network attached) advanced together. The batch owns a stream of its own and one
- * per domain; the contexts stay owned by the caller and must outlive the batch. Errors
- * are reported through mf_last_error(NULL). */
+ * with a network attached) advanced together (the time step of mf_step; a production form
+ * beyond the paper). The batch owns a stream of its own; the contexts stay owned by the
+ * caller and must outlive the batch. Errors are reported through mf_last_error(NULL). */
 typedef struct mf_batch mf_batch;
 int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out);
 
-/* Tune the bulk sweep once per distinct domain shape and storage form (reps launches per
- * variant) and apply the choice to every domain of that shape; variants (n ints,
- * nullable) receives each domain's variant. */
+/* The batch's autotuner: for every group of domains that share their kernels and every
+ * domain shape in it, time the batched bulk-sweep launch over the domains of that shape in
+ * every launch shape that fits them (reps launches each; the bulk kernel writes only the
+ * spare population buffer, so the state is not changed) and keep the fastest for those
+ * domains; variants (n ints, nullable) receives each domain's launch shape (-1: per-cell
+ * sweep). Synchronises. */
 int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants);
 
-/* Advance every domain by nsteps. Pairs of steps run as one launch of a graph that holds
- * two steps of all domains (each domain's kernels on its own branch, so independent
- * domains run side by side); the graph is captured on first use and again after any
- * state change made outside the time step (nucleation, field writes, refresh, network
- * attachment, tuning) or after an odd step count. Results are identical to mf_step on
- * each context. Work already queued on the contexts' streams runs first, and later work
- * queued there waits for the batch. Profiling must be off. */
+/* Advance every domain by nsteps. The domains are grouped by the kernels they use
+ * (dimension, storage, bulk or per-cell sweep, body force, learned curvature; at most 64
+ * per group), and every kernel of a step runs as one launch for all domains of a group:
+ * each domain takes its range of the launch's work-groups, and each work-group finds its
+ * domain by a binary search over the ranges passed with the launch. Pairs of steps run as
+ * one launch of a graph that holds two steps of all groups (a branch per group); the
+ * graph is captured on first use and again after any state change made outside the time
+ * step (nucleation, field writes, refresh, network attachment, tuning) or after an odd
+ * step count, which runs outside the graph. Results are those of mf_step on each context,
+ * bit for bit. Work already queued on the contexts' streams runs first, and later work
+ * queued there waits for the batch. Profiling must be off (MF_ESTATE). */
 int mf_batch_step(mf_batch *b, int32_t nsteps);
 
 /* Wait for the batch stream and free the batch (not the contexts). */

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,6 +42,11 @@ struct OpsTable {
   void (*totals)(Ctx &, hipStream_t);
   void (*bubble_stats)(Ctx &, hipStream_t);
   void (*poke)(Ctx &, hipStream_t, int, int64_t, int, double);
+  void (*sweep_multi)(const MStep &, unsigned, bool, bool, hipStream_t);
+  void (*convert_multi)(const MStep &, hipStream_t);
+  void (*label_multi)(const MStep &, hipStream_t);
+  void (*geometry_multi)(const MStep &, bool, hipStream_t);
+  void (*bulk_multi)(const MStep &, int, bool, hipStream_t);
 };
 
 template <int D, int P>
@@ -50,7 +56,9 @@ OpsTable make_ops() {
                   &Ops<D, P>::build_lists, &Ops<D, P>::read_field, &Ops<D, P>::write_field,
                   &Ops<D, P>::sweep_bulk,  &Ops<D, P>::geometry_normals, &Ops<D, P>::geometry_curv,
                   &Ops<D, P>::sweep_bulk_auto, &Ops<D, P>::sweep_interface, &Ops<D, P>::sweep_cells,
-                  &Ops<D, P>::totals, &Ops<D, P>::bubble_stats, &Ops<D, P>::poke};
+                  &Ops<D, P>::totals, &Ops<D, P>::bubble_stats, &Ops<D, P>::poke,
+                  &Ops<D, P>::sweep_multi, &Ops<D, P>::convert_multi, &Ops<D, P>::label_multi,
+                  &Ops<D, P>::geometry_multi, &Ops<D, P>::bulk_multi};
 }
 
 OpsTable ops_for(int dim, int prec) {
@@ -258,10 +266,26 @@ KP make_kp(const mf_params &P) {
     }                                                                                 \
   } while (0)
 
-__global__ void k_reset_counters(DA d) {
+__device__ __forceinline__ void b_reset_counters(const GridPos &gp, DA d) {
   const int t = threadIdx.x;
   if (t < C_NCOUNT) d.cnt[t] = 0;
 }
+__global__ void k_reset_counters(DA d) {
+  b_reset_counters(GridPos::hw(), d);
+}
+
+__global__ void km_reset_counters(MLaunch ml) {
+  MF_MULTI(MK_ONE)
+  b_reset_counters(gp, m.d);
+}
+
+}  // namespace
+
+void mf::reset_multi(const MStep &ms, hipStream_t s) {
+  hipLaunchKernelGGL(km_reset_counters, dim3(ms.grid[MK_ONE]), dim3(64), 0, s, ms.at(MK_ONE));
+}
+
+namespace {
 
 __global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
@@ -1033,15 +1057,35 @@ int mf_profile_get(mf_ctx *c, int32_t group, double *ms_total, int64_t *launches
 
 
 // ---------------------------------------------------------------- batched domains
+// The domains of a batch are grouped by what selects their kernels (dimension, storage,
+// per-cell or bulk sweep, body force, learned curvature). Every kernel of a step runs as
+// one launch for all domains of a group: each domain takes the work-groups it would take
+// alone, and each work-group finds its domain from a table of per-domain parameters and
+// arrays (MDom) and a prefix sum of work-group counts per launch kind. Two steps of all
+// groups are captured into one graph (a branch per group); the results are those of
+// mf_step on each context, bit for bit.
+struct BatchGroup {
+  std::vector<int> idx;  // domains of the batch in this group
+  OpsTable ops;
+  int precision = 0;
+  bool cells = false, frc = false, mlp = false;
+  unsigned vmask = 0;        // bulk launch shapes used by the group's domains
+  int grid[MK_COUNT] = {};   // work-groups of each launch kind over the group
+  std::vector<int> pre;      // [MK_COUNT][nd + 1] work-group prefix sums
+  MDom *dom_dev[2] = {nullptr, nullptr};  // the two steps of a captured pair
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_join = nullptr;
+};
+
 struct mf_batch {
   std::vector<mf_ctx *> ctx;
-  hipStream_t sb = nullptr;             // the batch stream (graph launches)
-  std::vector<hipStream_t> ss;          // one stream per domain inside the graph
-  std::vector<hipEvent_t> ev_in, ev_join;
+  hipStream_t sb = nullptr;  // the batch stream (graph launches)
   hipEvent_t ev_fork = nullptr, ev_out = nullptr;
+  std::vector<hipEvent_t> ev_in;
+  std::vector<BatchGroup> groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<uint64_t> epoch;          // context epochs and buffer parities at capture
+  std::vector<uint64_t> epoch;  // context epochs and buffer parities at capture
   std::vector<int> cur, par;
 };
 
@@ -1050,11 +1094,144 @@ static void batch_drop_graph(mf_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+  for (BatchGroup &g : b->groups) {
+    for (int j = 0; j < 2; ++j) {
+      if (g.dom_dev[j]) (void)hipFree(g.dom_dev[j]);
+      g.dom_dev[j] = nullptr;
+    }
+  }
+}
+
+static void batch_free_groups(mf_batch *b) {
+  for (BatchGroup &g : b->groups) {
+    if (g.stream) (void)hipStreamDestroy(g.stream);
+    if (g.ev_join) (void)hipEventDestroy(g.ev_join);
+  }
+  b->groups.clear();
 }
 
 static int batch_fail(const char *msg, hipError_t e) {
   g_thread_err = std::string(msg) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
   return e != hipSuccess ? MF_EHIP : MF_ESTATE;
+}
+
+#define HIPCHK_B(expr)                                                          \
+  do {                                                                          \
+    const hipError_t _e = (expr);                                               \
+    if (_e != hipSuccess) return batch_fail(#expr, _e);                         \
+  } while (0)
+
+// Work-groups a domain takes in a batched launch of kind k. The passes over the whole grid
+// (list builder, sweep) take the grid of the domain's own launchers; the passes over its
+// lists take a grid sized to the domain (their grid-stride loops cover whatever does not
+// fit, and no result depends on the number of work-groups), so that a batch of small
+// domains does not start thousands of work-groups that find nothing to do.
+static int kind_blocks(const mf_ctx *c, int kind, int variant) {
+  const int64_t N = c->kp.N;
+  auto clampi = [](int64_t v, int64_t lo, int64_t hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); };
+  const int nb = (int)list_blocks(*c);
+  const int nch = list_blocks_of(c->kp);
+  switch (kind) {
+    case MK_ONE: return 1;
+    case MK_LISTGRID: return nch < 1024 ? nch : 1024;
+    case MK_LIST: return clampi(N / 8192, 1, nb);
+    case MK_SHORT: return clampi(N / 65536, 1, 1024);
+    case MK_TOPOW: return clampi(N / 65536, 1, 256);
+    case MK_BFAST: return (c->kp.cap + 255) / 256 < 64 ? (c->kp.cap + 255) / 256 : 64;
+    case MK_MLP: return clampi(N / 16384, 1, 768);
+    case MK_CELLS:
+      return variant < 0 ? (int)((int64_t)((c->kp.nx + 63) / 64) * ((c->kp.ny + 3) / 4) * c->kp.nz) : 0;
+    default: {
+      const int v = kind - MK_BULK0;
+      if (v != variant) return 0;
+      const int64_t per = (int64_t)kSweepVariants[v].bs * kSweepVariants[v].vw;
+      return (int)((N + per - 1) / per);
+    }
+  }
+}
+
+// sort the domains into groups by the kernels they use
+static hipError_t batch_group(mf_batch *b) {
+  batch_free_groups(b);
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    const mf_ctx *c = b->ctx[i];
+    const int v = effective_sweep_variant(c->kp, c->P.precision, c->sweep_variant);
+    const bool cells = v < 0, frc = c->kp.force != 0, mlp = c->kp.curvature == MF_CURV_MLP;
+    BatchGroup *g = nullptr;
+    for (BatchGroup &h : b->groups) {
+      const mf_ctx *o = b->ctx[h.idx[0]];
+      if (o->kp.dim == c->kp.dim && h.precision == c->P.precision && h.cells == cells && h.frc == frc && h.mlp == mlp &&
+          (int)h.idx.size() < kMaxBatchDomains) {
+        g = &h;
+        break;
+      }
+    }
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->ops = c->ops;
+      g->precision = c->P.precision;
+      g->cells = cells;
+      g->frc = frc;
+      g->mlp = mlp;
+      hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    g->idx.push_back((int)i);
+    if (!cells) g->vmask |= 1u << v;
+  }
+  return hipSuccess;
+}
+
+// the per-domain tables of each group for the two steps of a pair, from the contexts'
+// current buffer parities
+static hipError_t batch_tables(mf_batch *b) {
+  for (BatchGroup &g : b->groups) {
+    const int nd = (int)g.idx.size();
+    std::vector<int> &pre = g.pre;
+    pre.assign((size_t)MK_COUNT * (nd + 1), 0);
+    for (int k = 0; k < MK_COUNT; ++k) {
+      for (int i = 0; i < nd; ++i) {
+        const mf_ctx *c = b->ctx[g.idx[i]];
+        const int v = effective_sweep_variant(c->kp, c->P.precision, c->sweep_variant);
+        pre[(size_t)k * (nd + 1) + i + 1] = pre[(size_t)k * (nd + 1) + i] + kind_blocks(c, k, v);
+      }
+      g.grid[k] = pre[(size_t)k * (nd + 1) + nd];
+    }
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < 2; ++j) {
+      std::vector<MDom> t(nd);
+      for (int i = 0; i < nd; ++i) {
+        const mf_ctx *c = b->ctx[g.idx[i]];
+        const int parity = c->parity ^ (j == 0 ? 1 : 0);  // step_once flips it first
+        t[i].kp = c->kp;
+        t[i].d = c->d;
+        t[i].d.cnt = c->cnt_base + C_NCOUNT * parity;
+        t[i].d.ilist = c->ilist_base + (size_t)c->kp.Np * parity;
+        t[i].cur = c->cur ^ j;
+      }
+      e = hipMalloc(&g.dom_dev[j], sizeof(MDom) * nd);
+      if (e == hipSuccess) e = hipMemcpy(g.dom_dev[j], t.data(), sizeof(MDom) * nd, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// one time step of every domain of a group, as batched launches on stream s
+static void group_step(const BatchGroup &g, int j, hipStream_t s) {
+  MStep ms;
+  ms.dom = g.dom_dev[j];
+  ms.nd = (int)g.idx.size();
+  ms.pre = g.pre.data();
+  ms.grid = g.grid;
+  reset_multi(ms, s);
+  lists_multi(ms, 0, s);
+  g.ops.sweep_multi(ms, g.vmask, g.cells, g.frc, s);
+  g.ops.convert_multi(ms, s);
+  g.ops.label_multi(ms, s);
+  g.ops.geometry_multi(ms, g.mlp, s);
 }
 
 int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out) {
@@ -1069,14 +1246,8 @@ int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out) {
   hipError_t e = hipStreamCreateWithFlags(&b->sb, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
-  b->ss.assign(n, nullptr);
   b->ev_in.assign(n, nullptr);
-  b->ev_join.assign(n, nullptr);
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    e = hipStreamCreateWithFlags(&b->ss[i], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in[i], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming);
-  }
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&b->ev_in[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     mf_batch_destroy(b);
     return batch_fail("creating the batch streams failed", e);
@@ -1089,11 +1260,9 @@ int mf_batch_destroy(mf_batch *b) {
   if (!b) return MF_EINVAL;
   if (b->sb) (void)hipStreamSynchronize(b->sb);
   batch_drop_graph(b);
-  for (size_t i = 0; i < b->ss.size(); ++i) {
-    if (b->ss[i]) (void)hipStreamDestroy(b->ss[i]);
-    if (b->ev_in[i]) (void)hipEventDestroy(b->ev_in[i]);
-    if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
-  }
+  batch_free_groups(b);
+  for (hipEvent_t e : b->ev_in)
+    if (e) (void)hipEventDestroy(e);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->sb) (void)hipStreamDestroy(b->sb);
@@ -1101,34 +1270,32 @@ int mf_batch_destroy(mf_batch *b) {
   return MF_OK;
 }
 
-// two time steps of every domain as one graph: each domain's kernels on its own stream,
-// forked from and joined back into the batch stream
+// two time steps of every domain as one graph: each group's batched launches on its own
+// branch, forked from and joined back into the batch stream
 static hipError_t batch_capture(mf_batch *b) {
   for (mf_ctx *c : b->ctx)
     if (c->sword_dirty || c->gas_dirty) c->ops.geometry(*c, b->sb);  // idempotent
-  hipError_t e = hipStreamBeginCapture(b->sb, hipStreamCaptureModeThreadLocal);
+  hipError_t e = batch_group(b);
+  if (e == hipSuccess) e = batch_tables(b);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(b->sb, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   (void)hipEventRecord(b->ev_fork, b->sb);
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
-    mf_ctx *c = b->ctx[i];
-    (void)hipStreamWaitEvent(b->ss[i], b->ev_fork, 0);
-    hipStream_t own = c->stream;
-    c->stream = b->ss[i];
-    step_once(c, nullptr, false);
-    step_once(c, nullptr, false);
-    c->stream = own;
-    c->step -= 2;  // counted when the graph runs
-    (void)hipEventRecord(b->ev_join[i], b->ss[i]);
-    (void)hipStreamWaitEvent(b->sb, b->ev_join[i], 0);
+  for (BatchGroup &g : b->groups) {
+    (void)hipStreamWaitEvent(g.stream, b->ev_fork, 0);
+    group_step(g, 0, g.stream);
+    group_step(g, 1, g.stream);
+    (void)hipEventRecord(g.ev_join, g.stream);
+    (void)hipStreamWaitEvent(b->sb, g.ev_join, 0);
   }
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(b->sb, &g);
+  hipGraph_t gr = nullptr;
+  e = hipStreamEndCapture(b->sb, &gr);
   if (e != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
+    if (gr) (void)hipGraphDestroy(gr);
     return e;
   }
-  b->graph = g;
-  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  b->graph = gr;
+  e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     batch_drop_graph(b);
     return e;
@@ -1154,15 +1321,18 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
   bool stale = b->exec == nullptr;
   for (size_t i = 0; i < b->ctx.size() && !stale; ++i)
     stale = b->epoch[i] != b->ctx[i]->epoch || b->cur[i] != b->ctx[i]->cur || b->par[i] != b->ctx[i]->parity;
-  if (stale && b->exec) batch_drop_graph(b);
   // the batch waits for the work already queued on the domains' own streams
   for (size_t i = 0; i < b->ctx.size(); ++i) {
+    join_side(b->ctx[i]);
     (void)hipEventRecord(b->ev_in[i], b->ctx[i]->stream);
     (void)hipStreamWaitEvent(b->sb, b->ev_in[i], 0);
   }
   const int pairs = nsteps / 2;
   if (pairs > 0) {
-    if (!b->exec) {
+    if (stale) {
+      // the tables of a graph in flight stay allocated until the batch stream is idle
+      (void)hipStreamSynchronize(b->sb);
+      batch_drop_graph(b);
       const hipError_t e = batch_capture(b);
       if (e != hipSuccess) return batch_fail("capturing the batched step failed", e);
     }
@@ -1170,7 +1340,11 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
       const hipError_t e = hipGraphLaunch(b->exec, b->sb);
       if (e != hipSuccess) return batch_fail("launching the batched step failed", e);
     }
-    for (mf_ctx *c : b->ctx) c->step += 2 * pairs;
+    for (mf_ctx *c : b->ctx) {
+      c->step += 2 * pairs;
+      c->gas_dirty = false;
+      c->sword_fresh = false;
+    }
   }
   if (nsteps & 1) {
     // an odd step runs outside the graph (and flips the buffer parity the graph expects)
@@ -1193,28 +1367,84 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
 
 int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants) {
   if (!b || reps < 1) return MF_EINVAL;
-  // one tuning run per distinct domain shape and storage form
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
-    mf_ctx *c = b->ctx[i];
-    int v = -2;
-    for (size_t j = 0; j < i; ++j) {
-      const mf_ctx *o = b->ctx[j];
-      if (o->kp.dim == c->kp.dim && o->kp.nx == c->kp.nx && o->kp.ny == c->kp.ny && o->kp.nz == c->kp.nz &&
-          o->P.precision == c->P.precision && o->kp.rheology == c->kp.rheology) {
-        v = o->sweep_variant;
-        break;
+  // Per group and per domain shape (size class): time the batched bulk launch over the
+  // class's domains in every launch shape that fits them, keep the fastest. The bulk
+  // kernel writes only the spare population buffer, so timing changes no state.
+  HIPCHK_B(hipStreamSynchronize(b->sb));
+  for (mf_ctx *c : b->ctx) {
+    join_side(c);
+    HIPCHK_B(hipStreamSynchronize(c->stream));
+  }
+  batch_drop_graph(b);
+  HIPCHK_B(batch_group(b));
+  HIPCHK_B(batch_tables(b));
+  hipEvent_t e0, e1;
+  HIPCHK_B(hipEventCreate(&e0));
+  HIPCHK_B(hipEventCreate(&e1));
+  int rc = MF_OK;
+  for (BatchGroup &g : b->groups) {
+    if (g.cells) continue;
+    const int nd = (int)g.idx.size();
+    std::vector<int> done(nd, 0);
+    for (int i = 0; i < nd && rc == MF_OK; ++i) {
+      if (done[i]) continue;
+      const mf_ctx *ci = b->ctx[g.idx[i]];
+      std::vector<int> cls;
+      for (int k = i; k < nd; ++k) {
+        const mf_ctx *ck = b->ctx[g.idx[k]];
+        if (!done[k] && ck->kp.nx == ci->kp.nx && ck->kp.ny == ci->kp.ny && ck->kp.nz == ci->kp.nz) {
+          cls.push_back(k);
+          done[k] = 1;
+        }
+      }
+      int best = -1;
+      float bt = 0.0f;
+      for (int v = 0; v < kNumSweepVariants && rc == MF_OK; ++v) {
+        if (!bulk_shape_ok(ci->kp, ci->P.precision, kSweepVariants[v].vw)) continue;
+        // the class's domains only, in shape v
+        std::vector<int> pre((size_t)MK_COUNT * (nd + 1), 0);
+        const int kind = MK_BULK0 + v;
+        for (int k = 0; k < nd; ++k) {
+          const bool in = std::find(cls.begin(), cls.end(), k) != cls.end();
+          pre[(size_t)kind * (nd + 1) + k + 1] =
+              pre[(size_t)kind * (nd + 1) + k] + (in ? kind_blocks(b->ctx[g.idx[k]], kind, v) : 0);
+        }
+        int grid[MK_COUNT] = {};
+        grid[kind] = pre[(size_t)kind * (nd + 1) + nd];
+        MStep ms;
+        ms.dom = g.dom_dev[0];
+        ms.nd = nd;
+        ms.pre = pre.data();
+        ms.grid = grid;
+        g.ops.bulk_multi(ms, v, g.frc, b->sb);  // warm-up launch
+        (void)hipEventRecord(e0, b->sb);
+        for (int r = 0; r < reps; ++r) g.ops.bulk_multi(ms, v, g.frc, b->sb);
+        (void)hipEventRecord(e1, b->sb);
+        float ms_t = 0.0f;
+        hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms_t, e0, e1);
+        if (e != hipSuccess) {
+          rc = batch_fail("timing the batched bulk sweep failed", e);
+          break;
+        }
+        if (best < 0 || ms_t < bt) {
+          best = v;
+          bt = ms_t;
+        }
+      }
+      for (int k : cls) {
+        mf_ctx *c = b->ctx[g.idx[k]];
+        c->sweep_variant = best;
+        c->epoch++;
       }
     }
-    if (v == -2) {
-      int32_t best = -1;
-      const int rc = mf_tune(c, reps, &best, nullptr);
-      if (rc) return rc;
-    } else {
-      c->sweep_variant = v;
-      c->epoch++;
-    }
-    if (variants) variants[i] = c->sweep_variant;
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  batch_drop_graph(b);  // the graph is captured again with the chosen shapes
+  if (rc) return rc;
+  for (size_t i = 0; i < b->ctx.size(); ++i)
+    if (variants) variants[i] = b->ctx[i]->sweep_variant;
   return MF_OK;
 }
 

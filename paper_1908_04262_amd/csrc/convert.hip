@@ -29,7 +29,7 @@ __device__ __forceinline__ int wave_reserve(int32_t *counter, int n) {
 // (a) every gas neighbour of a filled cell becomes a new interface cell; an emptied
 // neighbour of a filled cell stays an interface cell
 template <int D>
-__global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
+__device__ __forceinline__ void b_fill_scatter(const GridPos &gp, KP p, DA d) {
   using L = Lat<D>;
   SPREAD_LOOP(k, d.cnt + C_CONV) {
     bool act = false;
@@ -72,11 +72,15 @@ __global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
       if (!(old[i] & CF_NEWI)) d.nilist[at++] = (int32_t)yy[i];
   }
 }
+template <int D>
+__global__ __launch_bounds__(256) void k_fill_scatter(KP p, DA d) {
+  b_fill_scatter<D>(GridPos::hw(), p, d);
+}
 
 // (b) every liquid neighbour of a (still) emptied cell becomes an interface cell and
 // takes the smallest bubble id among its emptied neighbours
 template <int D>
-__global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
+__device__ __forceinline__ void b_empty_scatter(const GridPos &gp, KP p, DA d) {
   using L = Lat<D>;
   SPREAD_LOOP(k, d.cnt + C_CONV) {
     bool act = false;
@@ -121,12 +125,16 @@ __global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
       if (!(old[i] & CF_L2I)) d.l2ilist[at++] = (int32_t)yy[i];
   }
 }
+template <int D>
+__global__ __launch_bounds__(256) void k_empty_scatter(KP p, DA d) {
+  b_empty_scatter<D>(GridPos::hw(), p, d);
+}
 
 // (c) apply the new types; (e) an emptied cell hands its dissolved gas to its bubble; a
 // liquid cell turned interface takes M = rho, with rho and u the moments of its
 // post-collision populations
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
+__device__ __forceinline__ void b_apply(const GridPos &gp, KP p, DA d, int cur) {
   using SG = typename Prec<P>::SG;
   using SF = typename Prec<P>::SF;
   using R = typename Prec<P>::R;
@@ -177,13 +185,17 @@ __global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
     wave_count_add(d.bng, emptied && lab > 0 && lab < p.cap, lab, 1);  // one more gas cell
   }
 }
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_apply(KP p, DA d, int cur) {
+  b_apply<D, P>(GridPos::hw(), p, d, cur);
+}
 
 // (d) a new interface cell from gas takes the mean density and velocity of its liquid
 // and old-interface neighbours (moments of their post-collision populations), the
 // equilibrium populations of that state, M = 0, and dissolved gas at the Henry value of
 // its bubble, which the bubble gives up
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
+__device__ __forceinline__ void b_ni_init(const GridPos &gp, KP p, DA d, int cur) {
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
   using SG = typename Prec<P>::SG;
@@ -256,11 +268,15 @@ __global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
     wave_count_add(d.bng, act && lab > 0 && lab < p.cap, lab, -1);  // one gas cell fewer
   }
 }
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_ni_init(KP p, DA d, int cur) {
+  b_ni_init<D, P>(GridPos::hw(), p, d, cur);
+}
 
 // excess of each converted cell: e = M* - rho (filled) or M* (emptied), split over its
 // interface neighbours under the new types; none -> lost-liquid ledger
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
+__device__ __forceinline__ void b_excess_prep(const GridPos &gp, KP p, DA d) {
   using R = typename Prec<P>::R;
   using L = Lat<D>;
   SPREAD_LOOP(k, d.cnt + C_CONV) {
@@ -296,6 +312,10 @@ __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
     wave_fx_add(d.led, lost, 0, fx3((double)e));
   }
 }
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
+  b_excess_prep<D, P>(GridPos::hw(), p, d);
+}
 
 // Every interface cell of the new types gathers the shares of its converted neighbours in
 // ascending direction order; alpha = M / rho. With the learned curvature, the pass also
@@ -307,7 +327,7 @@ __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
 // and it clears the conversion flags of the cells it visits (the converted cells, whose
 // flags its neighbours read here, are cleared by the next pass).
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
+__device__ __forceinline__ void b_excess_gather(const GridPos &gp, KP p, DA d) {
   using R = typename Prec<P>::R;
   using L = Lat<D>;
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
@@ -315,8 +335,8 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
   const bool fast = !*(volatile int32_t *)(d.cnt + C_TOPO);
   const int64_t total = (int64_t)nI + nNI + nL;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
-       k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)gp.bid * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
+       k += (int64_t)gp.nblk * blockDim.x) {
     bool act = false;
     int lab = 0;
     Fx3 v = {0, 0, 0};
@@ -352,12 +372,19 @@ __global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
     if (fast) wave_fx_add_runs(d.vacc, act, lab, v);
   }
 }
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_excess_gather(KP p, DA d) {
+  b_excess_gather<D, P>(GridPos::hw(), p, d);
+}
 
 // the flags of the cells that filled or emptied
-__global__ __launch_bounds__(256) void k_conv_clear(DA d) {
+__device__ __forceinline__ void b_conv_clear(const GridPos &gp, DA d) {
   SPREAD_LOOP(k, d.cnt + C_CONV) {
     if (k < *(volatile int32_t *)(d.cnt + C_CONV)) d.cflag[d.clist[k]] = 0;
   }
+}
+__global__ __launch_bounds__(256) void k_conv_clear(DA d) {
+  b_conv_clear(GridPos::hw(), d);
 }
 
 // Whether this step's conversions can have changed the connected components of the gas
@@ -456,7 +483,7 @@ template <int D> struct RowWindow {
 // cheap per-cell tests over the converted cells: joining cells are decided here, filling
 // cells that need the window test are listed
 template <int D>
-__global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
+__device__ __forceinline__ void b_topo_check(const GridPos &gp, KP p, DA d) {
   using L = Lat<D>;
   const int nI = *(volatile int32_t *)(d.cnt + C_CONV);  // the cells that fill or empty
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
@@ -509,14 +536,18 @@ __global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
   }
   if (__ballot(change) != 0 && lane_id() == 0) d.cnt[C_TOPO] = 1;
 }
+template <int D>
+__global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
+  b_topo_check<D>(GridPos::hw(), p, d);
+}
 
 // the window tests of the listed filling cells, one wave per cell: the lanes load the
 // window, the whole wave runs the floods
 template <int D>
-__global__ __launch_bounds__(256) void k_topo_window(KP p, DA d) {
+__device__ __forceinline__ void b_topo_window(const GridPos &gp, KP p, DA d) {
   const int nc = min(*(volatile int32_t *)(d.cnt + C_TCAND), TCAND_CAP);
-  const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+  const int wave = (int)(gp.bid * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int nwaves = (int)(gp.nblk * (blockDim.x >> 6));
   if (wave >= nc || *(volatile int32_t *)(d.cnt + C_TOPO)) return;  // wave-uniform
   const RowWindow<D> w;
   for (int c = wave; c < nc; c += nwaves) {
@@ -529,6 +560,71 @@ __global__ __launch_bounds__(256) void k_topo_window(KP p, DA d) {
       return;
     }
   }
+}
+template <int D>
+__global__ __launch_bounds__(256) void k_topo_window(KP p, DA d) {
+  b_topo_window<D>(GridPos::hw(), p, d);
+}
+
+// batched forms: the same passes for every domain of a batch, one launch each
+template <int D>
+__global__ __launch_bounds__(256) void km_fill_scatter(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_fill_scatter<D>(gp, m.kp, m.d);
+}
+template <int D>
+__global__ __launch_bounds__(256) void km_empty_scatter(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_empty_scatter<D>(gp, m.kp, m.d);
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void km_apply(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_apply<D, P>(gp, m.kp, m.d, m.cur ^ 1);
+}
+template <int D>
+__global__ __launch_bounds__(256) void km_topo_check(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_topo_check<D>(gp, m.kp, m.d);
+}
+template <int D>
+__global__ __launch_bounds__(256) void km_topo_window(MLaunch ml) {
+  MF_MULTI(MK_TOPOW)
+  b_topo_window<D>(gp, m.kp, m.d);
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void km_ni_init(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_ni_init<D, P>(gp, m.kp, m.d, m.cur ^ 1);
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void km_excess_prep(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_excess_prep<D, P>(gp, m.kp, m.d);
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void km_excess_gather(MLaunch ml) {
+  MF_MULTI(MK_LIST)
+  b_excess_gather<D, P>(gp, m.kp, m.d);
+}
+__global__ __launch_bounds__(256) void km_conv_clear(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_conv_clear(gp, m.d);
+}
+
+// the conversions of every domain of a batch (after its sweep: the post-collision
+// populations are in buffer cur ^ 1), in the order of convert()
+template <int D, int P>
+void Ops<D, P>::convert_multi(const MStep &ms, hipStream_t s) {
+  hipLaunchKernelGGL((km_fill_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_empty_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_apply<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_topo_check<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_topo_window<D>), dim3(ms.grid[MK_TOPOW]), dim3(256), 0, s, ms.at(MK_TOPOW));
+  hipLaunchKernelGGL((km_ni_init<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_excess_prep<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_excess_gather<D, P>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
+  hipLaunchKernelGGL(km_conv_clear, dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
 }
 
 template <int D, int P>
@@ -551,7 +647,9 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   c.sword_fresh = c.d.sword != nullptr;  // the excess pass wrote the list cells' stencil words
 }
 
-#define MF_INST(D, P) template void Ops<D, P>::convert(Ctx &, hipStream_t);
+#define MF_INST(D, P)                                    \
+  template void Ops<D, P>::convert(Ctx &, hipStream_t); \
+  template void Ops<D, P>::convert_multi(const MStep &, hipStream_t);
 MF_FOR_ALL(MF_INST)
 
 }  // namespace mf

@@ -150,15 +150,15 @@ __device__ __forceinline__ R alpha_seen(const DA &d, int64_t y, R ac) {
   const int _nNI = *(volatile int32_t *)(d.cnt + C_NI);                               \
   const int _nL2 = *(volatile int32_t *)(d.cnt + C_L2I);                              \
   const int64_t _tot = (int64_t)_nI + _nNI + _nL2;                                    \
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < _tot;         \
-       k += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t k = gp.bid * blockDim.x + threadIdx.x; k < _tot;                      \
+       k += gp.nblk * blockDim.x)
 
 #define NEWI_CELL(k)                                                                  \
   (k < _nI ? (int64_t)d.ilist[k]                                                      \
            : (k < (int64_t)_nI + _nNI ? (int64_t)d.nilist[k - _nI] : (int64_t)d.l2ilist[k - _nI - _nNI]))
 
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_normals(KP p, DA d, int words) {
+__device__ __forceinline__ void b_normals(const GridPos &gp, KP p, DA d, int words) {
   using R = typename Prec<P>::R;
   NEWI_LOOP(k, n) {
     const int64_t n = NEWI_CELL(k);
@@ -192,6 +192,10 @@ __global__ __launch_bounds__(256) void k_normals(KP p, DA d, int words) {
     ((R *)d.mz)[n] = mz;
     ((R *)d.soff)[n] = off;
   }
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_normals(KP p, DA d, int words) {
+  b_normals<D, P>(GridPos::hw(), p, d, words);
 }
 
 // Gaussian elimination with partial pivoting (first maximum on ties); fails when a pivot
@@ -422,7 +426,7 @@ __device__ __forceinline__ void disjoining_cell(const KP &p, DA &d, int64_t n, t
 // per interface cell: curvature (the plain fit, unless the network already gave it),
 // disjoining pressure and gas side
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
+__device__ __forceinline__ void b_curvature(const GridPos &gp, KP p, DA d) {
   using R = typename Prec<P>::R;
   NEWI_LOOP(k, n) {
     const int64_t n = NEWI_CELL(k);
@@ -437,6 +441,10 @@ __global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
     }
     disjoining_cell<D, P>(p, d, n, kap);
   }
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_curvature(KP p, DA d) {
+  b_curvature<D, P>(GridPos::hw(), p, d);
 }
 
 // stencil words (learned curvature) over the whole grid, after a state change made
@@ -466,6 +474,26 @@ void Ops<D, P>::geometry_curv(Ctx &c, hipStream_t s) {
   c.sword_fresh = false;
 }
 
+// batched forms (time step: the stencil words come from the excess pass)
+template <int D, int P>
+__global__ __launch_bounds__(256) void km_normals(MLaunch ml) {
+  MF_MULTI(MK_LIST)
+  b_normals<D, P>(gp, m.kp, m.d, 0);
+}
+template <int D, int P>
+__global__ __launch_bounds__(256) void km_curvature(MLaunch ml) {
+  MF_MULTI(MK_LIST)
+  b_curvature<D, P>(gp, m.kp, m.d);
+}
+
+// the geometry of every domain of a batch, in the order of geometry() inside a step
+template <int D, int P>
+void Ops<D, P>::geometry_multi(const MStep &ms, bool mlp, hipStream_t s) {
+  hipLaunchKernelGGL((km_normals<D, P>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
+  if (mlp) mlp_curv_multi(ms, P, s);
+  hipLaunchKernelGGL((km_curvature<D, P>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
+}
+
 template <int D, int P>
 void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
   // stencil words: over the whole grid after a state change made outside the time step,
@@ -483,7 +511,8 @@ void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
 #define MF_INST(D, P)                                                     \
   template void Ops<D, P>::geometry(Ctx &, hipStream_t);                  \
   template void Ops<D, P>::geometry_normals(Ctx &, hipStream_t, bool);    \
-  template void Ops<D, P>::geometry_curv(Ctx &, hipStream_t);
+  template void Ops<D, P>::geometry_curv(Ctx &, hipStream_t);           \
+  template void Ops<D, P>::geometry_multi(const MStep &, bool, hipStream_t);
 
 MF_FOR_ALL(MF_INST)
 

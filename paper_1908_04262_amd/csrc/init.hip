@@ -267,19 +267,23 @@ template <int WHICH> __device__ __forceinline__ bool list_skipped(const DA &d) {
 }
 
 template <int WHICH>
-__global__ __launch_bounds__(256) void k_list_count(KP p, DA d, int nchunks) {
+__device__ __forceinline__ void b_list_count(const GridPos &gp, KP p, DA d, int nchunks) {
   if (list_skipped<WHICH>(d)) return;
-  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  for (int ch = gp.bid; ch < nchunks; ch += gp.nblk) {
     const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
     int si = __popcll(list_mask<WHICH>(p, d, c0));
     const int tot = block_scan(si);
     if (threadIdx.x == 0) list_counts<WHICH>(d)[ch] = tot;
   }
 }
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_list_count(KP p, DA d, int nchunks) {
+  b_list_count<WHICH>(GridPos::hw(), p, d, nchunks);
+}
 
 // exclusive scan of the per-chunk counts (in place) and the list length
 template <int WHICH>
-__global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
+__device__ __forceinline__ void b_list_scan(const GridPos &gp, DA d, int nchunks) {
   if (list_skipped<WHICH>(d)) return;
   __shared__ int s_w[16];
   const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -307,12 +311,16 @@ __global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
   }
   if (threadIdx.x == 0) d.cnt[WHICH == 0 ? C_I : C_B] = ti;
 }
+template <int WHICH>
+__global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
+  b_list_scan<WHICH>(GridPos::hw(), d, nchunks);
+}
 
 template <int WHICH>
-__global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
+__device__ __forceinline__ void b_list_write(const GridPos &gp, KP p, DA d, int nchunks) {
   if (list_skipped<WHICH>(d)) return;
   int32_t *list = WHICH == 0 ? d.ilist : d.blist;
-  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  for (int ch = gp.bid; ch < nchunks; ch += gp.nblk) {
     const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
     unsigned long long mk = list_mask<WHICH>(p, d, c0);
     const int ci = __popcll(mk);
@@ -332,6 +340,10 @@ __global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
     }
   }
 }
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
+  b_list_write<WHICH>(GridPos::hw(), p, d, nchunks);
+}
 
 template <int WHICH> static void launch_list(const Ctx &c, hipStream_t s) {
   const int nch = list_blocks_of(c.kp);
@@ -342,6 +354,33 @@ template <int WHICH> static void launch_list(const Ctx &c, hipStream_t s) {
 }
 
 void build_bubble_list(const Ctx &c, hipStream_t s) { launch_list<1>(c, s); }
+
+// batched forms of the list builder
+__device__ __forceinline__ int list_chunks(const KP &p) { return (int)((p.N + LIST_CHUNK - 1) / LIST_CHUNK); }
+template <int WHICH>
+__global__ __launch_bounds__(256) void km_list_count(MLaunch ml) {
+  MF_MULTI(MK_LISTGRID)
+  b_list_count<WHICH>(gp, m.kp, m.d, list_chunks(m.kp));
+}
+template <int WHICH>
+__global__ __launch_bounds__(1024) void km_list_scan(MLaunch ml) {
+  MF_MULTI(MK_ONE)
+  b_list_scan<WHICH>(gp, m.d, list_chunks(m.kp));
+}
+template <int WHICH>
+__global__ __launch_bounds__(256) void km_list_write(MLaunch ml) {
+  MF_MULTI(MK_LISTGRID)
+  b_list_write<WHICH>(gp, m.kp, m.d, list_chunks(m.kp));
+}
+template <int WHICH> static void launch_list_multi(const MStep &ms, hipStream_t s) {
+  hipLaunchKernelGGL(km_list_count<WHICH>, dim3(ms.grid[MK_LISTGRID]), dim3(256), 0, s, ms.at(MK_LISTGRID));
+  hipLaunchKernelGGL(km_list_scan<WHICH>, dim3(ms.grid[MK_ONE]), dim3(1024), 0, s, ms.at(MK_ONE));
+  hipLaunchKernelGGL(km_list_write<WHICH>, dim3(ms.grid[MK_LISTGRID]), dim3(256), 0, s, ms.at(MK_LISTGRID));
+}
+void lists_multi(const MStep &ms, int which, hipStream_t s) {
+  if (which == 0) launch_list_multi<0>(ms, s);
+  else launch_list_multi<1>(ms, s);
+}
 
 int list_blocks_of(const KP &kp) { return (int)((kp.N + LIST_CHUNK - 1) / LIST_CHUNK); }
 

@@ -43,11 +43,11 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
 // (gas / interface with a non-zero id), listed at the start of a relabelling step
 #define CLIST_LOOP(k, n, total)                                                   \
   const int64_t total = *(volatile int32_t *)(d.cnt + C_B);                       \
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                 \
-       k < ((total + 63) & ~(int64_t)63); k += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t k = gp.bid * blockDim.x + threadIdx.x;                              \
+       k < ((total + 63) & ~(int64_t)63); k += gp.nblk * blockDim.x)
 
 template <int D>
-__global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
+__device__ __forceinline__ void b_ccl_hook(const GridPos &gp, KP p, DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   using L = Lat<D>;
   CLIST_LOOP(k, n, total) {
@@ -66,6 +66,10 @@ __global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
     }
     if (atm) flag_or(d.cflag, n, CF_ATM);
   }
+}
+template <int D>
+__global__ __launch_bounds__(256) void k_ccl_hook(KP p, DA d) {
+  b_ccl_hook<D>(GridPos::hw(), p, d);
 }
 
 __device__ __forceinline__ int hash_insert(const KP &p, DA &d, unsigned long long key) {
@@ -92,7 +96,7 @@ __device__ __forceinline__ int hash_insert(const KP &p, DA &d, unsigned long lon
 // final roots (a cell next to the atmosphere marks its root), and the volume share
 // (1 - alpha) of every bubble cell summed per (component root, old id)
 template <int P>
-__global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
+__device__ __forceinline__ void b_ccl_accum(const GridPos &gp, KP p, DA d) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   using R = typename Prec<P>::R;
   CLIST_LOOP(k, n, total) {
@@ -139,6 +143,10 @@ __global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
       act = act && !mine;
     }
   }
+}
+template <int P>
+__global__ __launch_bounds__(256) void k_ccl_accum(KP p, DA d) {
+  b_ccl_accum<P>(GridPos::hw(), p, d);
 }
 
 __device__ __forceinline__ __int128 join3(const long long *a) { return fx3_join(a[0], a[1], a[2]); }
@@ -191,7 +199,7 @@ __device__ void write_bubble(const KP &p, DA &d, int id, double m, __int128 vk) 
 // volumes and pressures. Components whose ids appear nowhere else are handled in
 // parallel; the few whose ids are shared with another component (splits) are done in
 // ascending root order by one thread, which is the order the assignment rule needs.
-__global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_flux) {
+__device__ __forceinline__ void b_bubble_update(const GridPos &gp, KP p, DA d, int apply_flux) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   const int tid = threadIdx.x, nt = blockDim.x;
   const int cap = p.cap;
@@ -403,12 +411,15 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
     d.balive[0] = 1;
   }
 }
+__global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_flux) {
+  b_bubble_update(GridPos::hw(), p, d, apply_flux);
+}
 
 // new ids onto every cell from its root, the gas cells of every bubble counted under the
 // new ids (kept up to date by the conversions on the steps that do not relabel), and the
 // labelling flags cleared
 template <int P>
-__global__ __launch_bounds__(256) void k_ccl_relabel(KP p, DA d) {
+__device__ __forceinline__ void b_ccl_relabel(const GridPos &gp, KP p, DA d) {
   using R = typename Prec<P>::R;
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
   CLIST_LOOP(k, n, total) {
@@ -428,6 +439,10 @@ __global__ __launch_bounds__(256) void k_ccl_relabel(KP p, DA d) {
     }
     wave_count_add(d.bng, gas, lab, 1);
   }
+}
+template <int P>
+__global__ __launch_bounds__(256) void k_ccl_relabel(KP p, DA d) {
+  b_ccl_relabel<P>(GridPos::hw(), p, d);
 }
 
 __global__ void k_fill_words(int32_t *p, int64_t n, int32_t v) {
@@ -462,20 +477,20 @@ void recount_gas(const Ctx &c, hipStream_t s) {
 // identical to what the full labelling would give.
 // Several work-groups over the ids; the first also folds the atmosphere's terms and the
 // step's ledgers into the running totals.
-__global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
+__device__ __forceinline__ void b_bubble_fast(const GridPos &gp, KP p, DA d) {
   if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
   const int tid = threadIdx.x;
   __shared__ long long s_atm[3];
   int jmax = *(volatile int32_t *)d.nextid;
   if (jmax > p.cap) jmax = p.cap;
-  if (blockIdx.x == 0 && tid < 64) {
+  if (gp.bid == 0 && tid < 64) {
     long long sa[3];
     take_atm_copies(d, sa);
     if (tid == 0)
       for (int c = 0; c < 3; ++c) s_atm[c] = d.phi[c] + d.gam[c] + sa[c];
   }
   __syncthreads();
-  for (int j = blockIdx.x * blockDim.x + tid; j < jmax; j += gridDim.x * blockDim.x) {
+  for (int j = gp.bid * blockDim.x + tid; j < jmax; j += gp.nblk * blockDim.x) {
     if (j > 0 && d.balive[j]) {
       const double mp = d.bm[j] + fx_to_double(join3(&d.phi[3 * j]) + join3(&d.gam[3 * j]));
       // volume: one per gas cell, 1 - alpha per interface cell (fixed point, 2^64 = 1)
@@ -483,7 +498,7 @@ __global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
     }
     for (int c = 0; c < 3; ++c) d.phi[3 * j + c] = d.gam[3 * j + c] = d.vacc[3 * j + c] = 0;
   }
-  if (blockIdx.x == 0 && tid == 0) {
+  if (gp.bid == 0 && tid == 0) {
     d.ledtot[0] += join3(&d.led[0]);
     d.ledtot[1] += join3(&d.led[3]) + fx3_join(s_atm[0], s_atm[1], s_atm[2]);
     d.ledtot[2] += join3(&d.led[6]);
@@ -493,9 +508,48 @@ __global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
     d.cnt[C_CONTESTED] = 0;
   }
 }
+__global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
+  b_bubble_fast(GridPos::hw(), p, d);
+}
 
 // outside the time step (nucleation, refresh) the full labelling always runs
 __global__ void k_force_full(DA d) { d.cnt[C_TOPO] = 1; }
+
+// batched forms (time-step labelling: the flux of the step is applied)
+__global__ __launch_bounds__(256) void km_bubble_fast(MLaunch ml) {
+  MF_MULTI(MK_BFAST)
+  b_bubble_fast(gp, m.kp, m.d);
+}
+template <int D>
+__global__ __launch_bounds__(256) void km_ccl_hook(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_ccl_hook<D>(gp, m.kp, m.d);
+}
+template <int P>
+__global__ __launch_bounds__(256) void km_ccl_accum(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_ccl_accum<P>(gp, m.kp, m.d);
+}
+__global__ __launch_bounds__(1024) void km_bubble_update(MLaunch ml) {
+  MF_MULTI(MK_ONE)
+  b_bubble_update(gp, m.kp, m.d, 1);
+}
+template <int P>
+__global__ __launch_bounds__(256) void km_ccl_relabel(MLaunch ml) {
+  MF_MULTI(MK_SHORT)
+  b_ccl_relabel<P>(gp, m.kp, m.d);
+}
+
+// the labelling of every domain of a batch, in the order of label(c, s, 1)
+template <int D, int P>
+void Ops<D, P>::label_multi(const MStep &ms, hipStream_t s) {
+  hipLaunchKernelGGL(km_bubble_fast, dim3(ms.grid[MK_BFAST]), dim3(256), 0, s, ms.at(MK_BFAST));
+  lists_multi(ms, 1, s);
+  hipLaunchKernelGGL((km_ccl_hook<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_ccl_accum<P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL(km_bubble_update, dim3(ms.grid[MK_ONE]), dim3(1024), 0, s, ms.at(MK_ONE));
+  hipLaunchKernelGGL((km_ccl_relabel<P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+}
 
 template <int D, int P>
 void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
@@ -512,7 +566,9 @@ void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   hipLaunchKernelGGL((k_ccl_relabel<P>), dim3(nf), dim3(256), 0, s, c.kp, c.d);
 }
 
-#define MF_INST(D, P) template void Ops<D, P>::label(Ctx &, hipStream_t, int);
+#define MF_INST(D, P)                                         \
+  template void Ops<D, P>::label(Ctx &, hipStream_t, int);    \
+  template void Ops<D, P>::label_multi(const MStep &, hipStream_t);
 MF_FOR_ALL(MF_INST)
 
 }  // namespace mf

@@ -378,11 +378,21 @@ __device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y,
   z = (int)(r / p.ny);
 }
 
+// ------------------------------------------------------------------ launch geometry
+// Position of a work-group in the grid of one domain. A launch for one domain uses the
+// hardware indices; a launch over several domains (a batch) gives each domain a range
+// of work-groups and maps every work-group to its domain and local index. Kernel bodies
+// take it as `gp` and never read blockIdx / gridDim themselves.
+struct GridPos {
+  int64_t bid, nblk;
+  static __device__ __forceinline__ GridPos hw() { return GridPos{(int64_t)blockIdx.x, (int64_t)gridDim.x}; }
+};
+
 // grid-stride loop bounds over a device-counted list
 #define LIST_LOOP(idx, countptr)                                                   \
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x,               \
+  for (int64_t idx = gp.bid * blockDim.x + threadIdx.x,                             \
                _n = (int64_t)(*(volatile int32_t *)(countptr));                    \
-       idx < ((_n + 63) & ~(int64_t)63); idx += (int64_t)gridDim.x * blockDim.x)
+       idx < ((_n + 63) & ~(int64_t)63); idx += gp.nblk * blockDim.x)
 
 // The same over a short list (a few thousand entries), with the entries dealt lane-major
 // over the waves of the grid: lanes of one wave take entries a wave-count apart, so the
@@ -390,15 +400,16 @@ __device__ __forceinline__ void cell_xyz(const KP &p, int64_t n, int &x, int &y,
 // neighbouring cells do not meet in one instruction. Wave-uniform bounds; idx may exceed
 // the count (test it).
 #define SPREAD_LOOP_N(idx, count)                                                              \
-  for (int64_t _T = (int64_t)gridDim.x * blockDim.x, _n = (int64_t)(count), _r0 = 0, idx = 0;    \
+  for (int64_t _T = gp.nblk * blockDim.x, _n = (int64_t)(count), _r0 = 0, idx = 0;               \
        _r0 < _n && (idx = _r0 + (int64_t)(threadIdx.x & 63) * (_T >> 6) +                      \
-                          (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6), true);       \
+                          ((gp.bid * blockDim.x + threadIdx.x) >> 6), true);                    \
        _r0 += _T)
 #define SPREAD_LOOP(idx, countptr) SPREAD_LOOP_N(idx, *(volatile int32_t *)(countptr))
 
 // ------------------------------------------------------------------ launchers
 // every kernel family is a template over (D, P); the dispatcher picks one instance
 struct Ctx;
+struct MStep;
 template <int D, int P> struct Ops {
   // the lattice sweep: the bulk kernel (liquid cells; false when the domain takes the
   // per-cell kernel instead), the interface kernel (this step's interface list; after the
@@ -428,6 +439,14 @@ template <int D, int P> struct Ops {
   static void bubble_stats(Ctx &c, hipStream_t s);
   // overwrite one element of a field in its storage form
   static void poke(Ctx &c, hipStream_t s, int field, int64_t cell, int comp, double value);
+  // batched forms (one launch per kernel for all domains of a batched step): the sweep (bulk kernel in every launch shape of vmask and the interface
+  // kernel, or the per-cell kernel), the conversions, the labelling, the geometry
+  static void sweep_multi(const MStep &ms, unsigned vmask, bool cells, bool frc, hipStream_t s);
+  static void convert_multi(const MStep &ms, hipStream_t s);
+  static void label_multi(const MStep &ms, hipStream_t s);
+  static void geometry_multi(const MStep &ms, bool mlp, hipStream_t s);
+  // the bulk kernel alone in launch shape v (it writes only the spare population buffer)
+  static void bulk_multi(const MStep &ms, int v, bool frc, hipStream_t s);
 };
 
 struct Ctx {
@@ -479,8 +498,105 @@ struct SweepVariant { int vw, bs; };
 constexpr SweepVariant kSweepVariants[] = {{4, 256}, {2, 256}, {4, 128}, {2, 128}, {8, 256}, {8, 128}, {8, 64}, {4, 64}};
 constexpr int kNumSweepVariants = 8;
 
+// whether the bulk kernel with vw cells per thread can sweep a domain: 16-bit or binary32
+// storage, closed axes, rows a multiple of vw long
+inline bool bulk_shape_ok(const KP &kp, int precision, int vw) {
+  if (precision == 0) return false;
+  if (kp.per[0] || kp.per[1] || kp.per[2]) return false;
+  return kp.nx % vw == 0 && kp.nx >= 2 * vw && kp.ny >= 3 && (kp.dim == 2 || kp.nz >= 3);
+}
+// the launch shape used when none was chosen by the tuner: one wave per work-group, with
+// 16-byte population accesses per lane for 16-bit storage (8 cells per thread) and for
+// binary32 (4 cells per thread); measured fastest on the 384^3 foam
+inline int default_sweep_variant(int precision) { return precision == 1 ? 7 : 6; }
+// the launch shape a domain is swept with: the tuned one, else the default, else narrower
+// vectors for rows whose length is not a multiple of 8 cells; -1: the per-cell kernel
+inline int effective_sweep_variant(const KP &kp, int precision, int tuned) {
+  const int order[4] = {tuned, default_sweep_variant(precision), 7, 1};
+  for (int v : order)
+    if (v >= 0 && bulk_shape_ok(kp, precision, kSweepVariants[v].vw)) return v;
+  return -1;
+}
+
 // work-groups of the list builder (one per chunk of cells)
 int list_blocks_of(const KP &kp);
+
+// ------------------------------------------------------------------ batched launches
+// A batch advances many domains with one launch per kernel of the step: every domain
+// takes the range of work-groups it would take alone, and each work-group finds its
+// domain by a binary search over the ranges. One domain of such a launch, for one step:
+// its parameters, its arrays (with the counters and interface list of the step's
+// parity) and the buffer holding the post-collision populations the step starts from.
+struct MDom {
+  KP kp;
+  DA d;
+  int cur;
+};
+// launch kinds of a step (the grid formula of each launch of one domain); the bulk sweep
+// has one kind per launch shape, with no work-groups for domains that use another shape
+enum MKind {
+  MK_ONE = 0,   // one work-group
+  MK_LISTGRID,  // list builder passes: min(chunks, 1024)
+  MK_LIST,      // passes over the interface list: list_blocks
+  MK_SHORT,     // passes over short lists: min(list_blocks, 1024)
+  MK_TOPOW,     // topology windows: 256
+  MK_BFAST,     // bubble table pass: min(ceil(cap / 256), 64)
+  MK_MLP,       // learned curvature: min(list_blocks, 768)
+  MK_CELLS,     // per-cell sweep: 64 x 4 tiles
+  MK_BULK0,     // bulk sweep in launch shape v: MK_BULK0 + v
+  MK_COUNT = MK_BULK0 + kNumSweepVariants
+};
+constexpr int kMaxBatchDomains = 64;  // domains per batched launch
+// the launch arguments: the domain table and, for the launch's kind, the first
+// work-group of every domain (passed by value, so the search reads the kernel arguments)
+struct MLaunch {
+  const MDom *dom;  // device [nd]
+  int nd;
+  int pre[kMaxBatchDomains + 1];
+};
+// the domain of this work-group, and its local position
+__device__ __forceinline__ GridPos multi_pos(const MLaunch &ml, int kind, int &dom) {
+  (void)kind;
+  const int *pre = ml.pre;
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = ml.nd;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  dom = __builtin_amdgcn_readfirstlane(lo);
+  return GridPos{(int64_t)(b - pre[dom]), (int64_t)(pre[dom + 1] - pre[dom])};
+}
+#define MF_MULTI(kind)                                   \
+  int _dom = 0;                                          \
+  const GridPos gp = multi_pos(ml, (kind), _dom);        \
+  const MDom &m = ml.dom[_dom];
+
+// the arguments of a batched launch of kind k: pre holds the prefix sums of every kind,
+// [MK_COUNT][nd + 1]
+inline MLaunch mlaunch(const MDom *dom, int nd, const int *pre, int kind) {
+  MLaunch ml;
+  ml.dom = dom;
+  ml.nd = nd;
+  for (int i = 0; i <= nd; ++i) ml.pre[i] = pre[kind * (nd + 1) + i];
+  return ml;
+}
+// A batched step: the domain table of the step, the prefix sums of every kind and the
+// work-groups of every kind over the batch
+struct MStep {
+  const MDom *dom;
+  int nd;
+  const int *pre;   // host [MK_COUNT][nd + 1]
+  const int *grid;  // host [MK_COUNT]
+  MLaunch at(int kind) const { return mlaunch(dom, nd, pre, kind); }
+};
+
+// batched launches of the list builder (which: 0 interface list, 1 bubble list) and of
+// the counter reset
+void lists_multi(const MStep &ms, int which, hipStream_t s);
+void reset_multi(const MStep &ms, hipStream_t s);
+void mlp_curv_multi(const MStep &ms, int precision, hipStream_t s);
 // the bubble list (gas / interface cells with a non-zero id) on a relabelling step
 void build_bubble_list(const Ctx &c, hipStream_t s);
 // gas cells of every bubble id counted over the whole grid

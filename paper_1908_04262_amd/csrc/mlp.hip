@@ -23,6 +23,7 @@ constexpr int OW1 = 0, OB1 = NPD * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 
 constexpr int NPARAM = OB3 + 1;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __host__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -223,51 +224,95 @@ __global__ void k_mlp_canon(const float *raw, int64_t n, float *out) {
 }
 
 // ---------------------------------------------------------------- matrix products
-// C[M][N] (row stride ldc) = op(A)[M][K] op(B)[K][N] on v_mfma_f32_16x16x16_bf16: element
+// C[M][N] (row stride ldc) = op(A)[M][K] op(B)[K][N] on v_mfma_f32_16x16x32_bf16: element
 // A(m,k) at A[m*sam + k*sak], B(k,n) at B[k*sbk + n*sbn], both binary32 in memory and
-// rounded to bfloat16 on load. One wave per 16x16 output tile.
-// EPI 0: C = acc; EPI 1: C = acc + bias[n] and Hout = GELU(C) rounded to bfloat16.
+// rounded to bfloat16 when staged. A work-group of four waves computes a 64 x 16 tile:
+// per 32-wide slice of the sum it stages the A tile [64][32] and the B tile (transposed,
+// [16][32]) in LDS, read along the operand's contiguous axis, and each wave runs one
+// matrix-core product for its 16 rows. M % 64 == 0, N % 16 == 0, K % 32 == 0.
+// With split-K (gridDim.y > 1) the work-group of slice z sums k in [z Ks, (z+1) Ks) and
+// writes its partial tile to part[z][M][N]; k_gemm_reduce adds the partials in order.
+// EPI 0: C = acc; EPI 1: C = acc + bias[n] and Hout = GELU(C) rounded to bfloat16;
+// EPI 2: part[z] = acc.
+constexpr int GBM = 64, GBN = 16, GBK = 32;
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
-                                              int64_t sbn, float *C, int64_t ldc, int M, int N, int K,
-                                              const float *bias, float *Hout) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
-  const int tilesN = N >> 4;
-  const int tm = wave / tilesN, tn = wave % tilesN;
-  if (tm * 16 >= M) return;
-  const int r = lane & 15, kq = (lane >> 4) * 4;
+                                              int64_t sbn, float *C, int64_t ldc, int M, int N, int K, int Ks,
+                                              const float *bias, float *Hout, float *part) {
+  __shared__ __attribute__((aligned(16))) __bf16 sA[GBM][GBK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[GBN][GBK + 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tilesN = N / GBN;
+  const int tm = (int)blockIdx.x / tilesN, tn = (int)blockIdx.x % tilesN;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int kbeg = (int)blockIdx.y * Ks, kend = kbeg + Ks;
+  const int r = lane & 15, q = lane >> 4;
+  // staging: A along k when k is contiguous, else along m; B along k or along n
+  const bool a_k = sak == 1, b_k = sbk == 1;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a, b;
-    for (int j = 0; j < 4; j++) {
-      const int k = k0 + kq + j;
-      a[j] = (short)bf16_bits(A[(int64_t)(tm * 16 + r) * sam + (int64_t)k * sak]);
-      b[j] = (short)bf16_bits(B[(int64_t)k * sbk + (int64_t)(tn * 16 + r) * sbn]);
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+#pragma unroll
+    for (int j = 0; j < GBM * GBK / 256; ++j) {
+      const int e = tid + 256 * j;
+      const int mm = a_k ? e / GBK : e % GBM, kk = a_k ? e % GBK : e / GBM;
+      sA[mm][kk] = (__bf16)__uint_as_float(((uint32_t)bf16_bits(A[(int64_t)(m0 + mm) * sam + (int64_t)(k0 + kk) * sak])) << 16);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < GBN * GBK / 256; ++j) {
+      const int e = tid + 256 * j;
+      const int nn = b_k ? e / GBK : e % GBN, kk = b_k ? e % GBK : e / GBN;
+      sB[nn][kk] = (__bf16)__uint_as_float(((uint32_t)bf16_bits(B[(int64_t)(k0 + kk) * sbk + (int64_t)(n0 + nn) * sbn])) << 16);
+    }
+    __syncthreads();
+    const bf16x8 a = *(const bf16x8 *)&sA[wave * 16 + r][q * 8];
+    const bf16x8 b = *(const bf16x8 *)&sB[r][q * 8];
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    __syncthreads();
   }
   for (int j = 0; j < 4; j++) {
-    const int row = tm * 16 + kq + j, col = tn * 16 + r;
+    const int row = m0 + wave * 16 + q * 4 + j, col = n0 + r;
     if (EPI == 0) {
       C[(int64_t)row * ldc + col] = acc[j];
-    } else {
+    } else if (EPI == 1) {
       const float zz = acc[j] + bias[col];
       C[(int64_t)row * ldc + col] = zz;
       Hout[(int64_t)row * ldc + col] = bf16_round(gelu(zz));
+    } else {
+      part[((int64_t)blockIdx.y * M + row) * N + col] = acc[j];
     }
   }
 }
 
+// C[m][n] = sum over the ks partial tiles, in slice order
+__global__ void k_gemm_reduce(const float *part, int ks, int M, int N, float *C, int64_t ldc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * N) return;
+  float acc = 0.0f;
+  for (int z = 0; z < ks; ++z) acc += part[(int64_t)z * M * N + i];
+  C[(int64_t)(i / N) * ldc + i % N] = acc;
+}
+
+// slices of the sum for a product of K terms: one per 128 terms when K is long (the
+// weight gradients sum over the whole batch), so that the few output tiles still fill
+// the GPU; part must then hold ks * M * N floats
+static int gemm_slices(int K, const float *part) { return part && K >= 1024 ? K / 128 : 1; }
+
 static void gemm(hipStream_t s, int epi, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
                  int64_t sbn, float *C, int64_t ldc, int M, int N, int K, const float *bias = nullptr,
-                 float *H = nullptr) {
-  const int tiles = (M / 16) * (N / 16);
-  const unsigned blocks = (unsigned)((tiles + 3) / 4);
-  if (epi == 0)
-    hipLaunchKernelGGL(k_gemm<0>, dim3(blocks), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, H);
-  else
-    hipLaunchKernelGGL(k_gemm<1>, dim3(blocks), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, H);
+                 float *H = nullptr, float *part = nullptr) {
+  const unsigned tiles = (unsigned)((M / GBM) * (N / GBN));
+  const int ks = epi == 0 ? gemm_slices(K, part) : 1;
+  if (ks > 1) {
+    hipLaunchKernelGGL(k_gemm<2>, dim3(tiles, ks), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, K / ks,
+                       bias, H, part);
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((M * N + 255) / 256), dim3(256), 0, s, (const float *)part, ks, M, N, C, ldc);
+  } else if (epi == 0) {
+    hipLaunchKernelGGL(k_gemm<0>, dim3(tiles), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, K, bias, H,
+                       part);
+  } else {
+    hipLaunchKernelGGL(k_gemm<1>, dim3(tiles), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, K, bias, H,
+                       part);
+  }
 }
 
 // output layer: out[b] = sum_j bf16(h2[b][j]) bf16(W3[j]) + b3 (ascending j, binary32)
@@ -356,6 +401,7 @@ struct Net {
   float *theta = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   float *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *out = nullptr, *dout = nullptr;
   float *dZ1 = nullptr, *dZ2 = nullptr, *X = nullptr, *Y = nullptr;
+  float *gpart = nullptr;  // split-K partial tiles of the weight gradients
   double *loss = nullptr;
   int cap = 0;
   std::string err;
@@ -377,6 +423,10 @@ static hipError_t ensure_batch(Net &n, int B) {
   }
   if (n.X) (void)hipFree(n.X);
   hipError_t e = hipMalloc(&n.X, sizeof(float) * (size_t)B * NPD);
+  if (e) return e;
+  if (n.gpart) (void)hipFree(n.gpart);
+  const size_t ks = (size_t)(B >= 1024 ? B / 128 : 1);
+  e = hipMalloc(&n.gpart, sizeof(float) * ks * NPD * NH);
   if (e) return e;
   n.cap = B;
   return hipSuccess;
@@ -430,13 +480,13 @@ static void backward(Net &n, hipStream_t s, const float *X, const float *Y, int 
   hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.H2, NH, NH, n.dout, B, n.g, OW3);
   hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(256), 0, s, n.dout, B, n.g, OB3);
   // W2 = H1^T dZ2, b2
-  gemm(s, 0, n.H1, 1, NH, n.dZ2, NH, 1, n.g + OW2, NH, NH, NH, B);
+  gemm(s, 0, n.H1, 1, NH, n.dZ2, NH, 1, n.g + OW2, NH, NH, NH, B, nullptr, nullptr, n.gpart);
   hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.dZ2, NH, NH, (const float *)nullptr, B, n.g, OB2);
   // dZ1 = (dZ2 W2^T) * GELU'(Z1)
   gemm(s, 0, n.dZ2, NH, 1, n.theta + OW2, 1, NH, n.dZ1, NH, B, NH, NH);
   hipLaunchKernelGGL(k_mul_gelu_grad, dim3(256), dim3(256), 0, s, n.dZ1, n.Z1, (int64_t)B * NH);
   // W1 = X^T dZ1, b1
-  gemm(s, 0, X, 1, NPD, n.dZ1, NH, 1, n.g + OW1, NH, NPD, NH, B);
+  gemm(s, 0, X, 1, NPD, n.dZ1, NH, 1, n.g + OW1, NH, NPD, NH, B, nullptr, nullptr, n.gpart);
   hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.dZ1, NH, NH, (const float *)nullptr, B, n.g, OB1);
 }
 
@@ -453,12 +503,12 @@ static void backward(Net &n, hipStream_t s, const float *X, const float *Y, int 
 // gathers of the next 16 cells are issued before the products of the current ones. A cell whose stencil meets a wall, leaves the domain
 // or meets a gas / interface cell of another bubble, or whose network curvature exceeds
 // the trained range |kappa| <= 1/2, is left to the plain fit.
-struct MlpWaveLds {
+struct alignas(16) MlpWaveLds {
   // canonical stencils of 16 cells; the first hidden layer overwrites them once the
   // wave's layer-1 products have read them
   union {
-    short a[16][NPD + 4];
-    short h[16][NH + 4];
+    short a[16][NPD + 8];
+    short h[16][NH + 8];
   };
   // the 64 cells of the wave's tile
   // per cell: index, coordinates, id + 1, flags, packed canonical-slot coefficients,
@@ -494,10 +544,10 @@ template <class T> __device__ __forceinline__ T uniform(T v) {
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
+__device__ __forceinline__ void b_mlp_curv(const GridPos &gp, KP p, DA d) {
   using R = typename Prec<P>::R;
-  __shared__ short sW1[NH][NPD + 4];  // W1 transposed: [unit][input]
-  __shared__ short sW2[NH][NH + 4];   // W2 transposed: [unit][input]
+  __shared__ __attribute__((aligned(16))) short sW1[NH][NPD + 8];  // W1 transposed: [unit][input]
+  __shared__ __attribute__((aligned(16))) short sW2[NH][NH + 8];   // W2 transposed: [unit][input]
   __shared__ float sB1[NH], sB2[NH], sW3[NH];
   __shared__ MlpWaveLds sw[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -521,7 +571,10 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
   const int64_t total = (int64_t)nI + nNI + nL;
   const int64_t nxy = (int64_t)p.nx * p.ny;
   const bool periodic = p.per[0] || p.per[1] || p.per[2];
-  const int r = lane & 15, kq = (lane >> 4) * 4;
+  // lane (r, q = lane / 16): row r of the A operand and column r of B, with the eight
+  // inputs 8 q .. 8 q + 7 of each 32-wide slice of the sum (v_mfma_f32_16x16x32_bf16);
+  // it receives the results of rows 4 q .. 4 q + 3, column r
+  const int r = lane & 15, kq = (lane >> 4) * 4, kq8 = (lane >> 4) * 8;
   // the lane's two stencil elements j = lane and lane + 64: offsets and index offsets
   const int j1 = lane + 64;
   const int dx0 = lane % 5 - 2, dy0 = (lane / 5) % 5 - 2, dz0 = lane / 25 - 2;
@@ -559,7 +612,7 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       }
     }
   };
-  for (int64_t t0 = ((int64_t)blockIdx.x * 4 + wave) * 64; t0 < total; t0 += (int64_t)gridDim.x * 4 * 64) {
+  for (int64_t t0 = ((int64_t)gp.bid * 4 + wave) * 64; t0 < total; t0 += (int64_t)gp.nblk * 4 * 64) {
     // set-up, one cell per lane: the cell and its six axis neighbours are loaded
     // together once the list entry is known
     {
@@ -644,12 +697,12 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       floatx4 acc[4];
       for (int tn = 0; tn < 4; tn++) acc[tn] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int k0 = 0; k0 < NPD; k0 += 16) {
-        const bf16x4 a = *(const bf16x4 *)&M.a[r][k0 + kq];
+      for (int k0 = 0; k0 < NPD; k0 += 32) {
+        const bf16x8 a = *(const bf16x8 *)&M.a[r][k0 + kq8];
 #pragma unroll
         for (int tn = 0; tn < 4; tn++) {
-          const bf16x4 b = *(const bf16x4 *)&sW1[tn * 16 + r][k0 + kq];
-          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tn], 0, 0, 0);
+          const bf16x8 b = *(const bf16x8 *)&sW1[tn * 16 + r][k0 + kq8];
+          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tn], 0, 0, 0);
         }
       }
       wave_lds_sync();  // every lane has read its stencil rows before they are overwritten
@@ -661,12 +714,12 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       // second hidden layer
       for (int tn = 0; tn < 4; tn++) acc[tn] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int k0 = 0; k0 < NH; k0 += 16) {
-        const bf16x4 a = *(const bf16x4 *)&M.h[r][k0 + kq];
+      for (int k0 = 0; k0 < NH; k0 += 32) {
+        const bf16x8 a = *(const bf16x8 *)&M.h[r][k0 + kq8];
 #pragma unroll
         for (int tn = 0; tn < 4; tn++) {
-          const bf16x4 b = *(const bf16x4 *)&sW2[tn * 16 + r][k0 + kq];
-          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tn], 0, 0, 0);
+          const bf16x8 b = *(const bf16x8 *)&sW2[tn * 16 + r][k0 + kq8];
+          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tn], 0, 0, 0);
         }
       }
       // output layer: lane (r, kq) holds units tn*16 + r of cells kq .. kq+3
@@ -696,6 +749,26 @@ __global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
       }
       wave_lds_sync();
     }
+  }
+}
+template <int P>
+__global__ __launch_bounds__(256) void k_mlp_curv(KP p, DA d) {
+  b_mlp_curv<P>(GridPos::hw(), p, d);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void km_mlp_curv(MLaunch ml) {
+  MF_MULTI(MK_MLP)
+  b_mlp_curv<P>(gp, m.kp, m.d);
+}
+
+// the learned curvature of every domain of a batch (3D, networks attached)
+void mlp_curv_multi(const MStep &ms, int precision, hipStream_t s) {
+  switch (precision) {
+    case 0: hipLaunchKernelGGL(km_mlp_curv<0>, dim3(ms.grid[MK_MLP]), dim3(256), 0, s, ms.at(MK_MLP)); break;
+    case 1: hipLaunchKernelGGL(km_mlp_curv<1>, dim3(ms.grid[MK_MLP]), dim3(256), 0, s, ms.at(MK_MLP)); break;
+    case 2: hipLaunchKernelGGL(km_mlp_curv<2>, dim3(ms.grid[MK_MLP]), dim3(256), 0, s, ms.at(MK_MLP)); break;
+    default: hipLaunchKernelGGL(km_mlp_curv<3>, dim3(ms.grid[MK_MLP]), dim3(256), 0, s, ms.at(MK_MLP)); break;
   }
 }
 
@@ -780,7 +853,8 @@ int mf_mlp_create(uint64_t init_seed, mf_mlp **out) {
 
 int mf_mlp_destroy(mf_mlp *m) {
   if (!m) return MF_OK;
-  float *bufs[] = {m->theta, m->m, m->v, m->g, m->Z1, m->H1, m->Z2, m->H2, m->out, m->dout, m->dZ1, m->dZ2, m->X, m->Y};
+  float *bufs[] = {m->theta, m->m, m->v, m->g, m->Z1, m->H1, m->Z2, m->H2, m->out, m->dout, m->dZ1, m->dZ2, m->X, m->Y,
+                   m->gpart};
   for (float *b : bufs)
     if (b) (void)hipFree(b);
   if (m->loss) (void)hipFree(m->loss);

@@ -445,10 +445,17 @@ __device__ __forceinline__ uint8_t store_interface(const KP &p, DA &d, int64_t n
   return cl;
 }
 
+// index offset of the lattice neighbour x + e_i on a grid without periodic wrap
+template <int D>
+__device__ __forceinline__ int64_t dir_offset(const KP &p, int i) {
+  return (int64_t)Lat<D>::ex[i] + (int64_t)p.nx * ((int64_t)Lat<D>::ey[i] + (D == 3 ? (int64_t)p.ny * Lat<D>::ez[i] : 0));
+}
+
 // The whole update of one cell (x, y, z) = n with type byte tb and bubble id lab; lanes
 // with fluid == false only take part in the wave-level gas-ledger sum. Called by the
-// whole wave.
-template <int D, int P, bool FRC>
+// whole wave. CLOSED: the grid has no periodic axis and the cell is not on its outer
+// layer, so neighbours are plain index offsets (x, y, z are not used).
+template <int D, int P, bool FRC, bool CLOSED = false>
 __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool fluid, int x, int y, int z, int64_t n,
                                            uint8_t tb, int32_t lab) {
   using L = Lat<D>;
@@ -470,17 +477,23 @@ __device__ __forceinline__ void sweep_cell(const KP &p, DA &d, int cur, bool flu
     SG *gout = (SG *)d.g[cur ^ 1];
     const int64_t Np = p.Np;
     R ft[Q], gt[Qg];
+    auto src = [&](int i) {
+      if constexpr (CLOSED) return n - dir_offset<D>(p, i);
+      else return nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
+    };
+    auto dst = [&](int i) {
+      if constexpr (CLOSED) return n + dir_offset<D>(p, i);
+      else return nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+    };
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int64_t s = nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]);
+      const int64_t s = src(i);
       ft[i] = FC::dec(fin[(int64_t)i * Np + s], i);
       if (i < Qg) gt[i] = GC::dec(gin[(int64_t)i * Np + s], p);
     }
     R Ms = R(0), pf = R(0), aold = R(0), cx = R(0);
     bool hasG = false, hasF = false;
     if (isI || (tb & NEARWALL)) {
-      auto src = [&](int i) { return nb_index(p, x, y, z, -L::ex[i], -L::ey[i], -L::ez[i]); };
-      auto dst = [&](int i) { return nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]); };
       special_terms<D, P>(p, d, cur, n, isI, lab, src, dst, ft, gt, Ms, hasG, hasF, phic, hasgas, pf, aold);
     }
     if (isI && p.flux_paper) {
@@ -517,11 +530,11 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 
 // ------------------------------------------------------------------ per-cell form
 template <int D, int P, bool FRC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep(KP p, DA d, int cur) {
+__device__ __forceinline__ void b_sweep(const GridPos &gp, KP p, DA d, int cur) {
   // tile of 64 x 4 cells
   const int gx = (p.nx + 63) >> 6, gy = (p.ny + 3) >> 2;
   const int64_t nb = (int64_t)gx * gy * p.nz;
-  const int64_t b = xcd_block(blockIdx.x, nb);
+  const int64_t b = xcd_block(gp.bid, nb);
   const int bx = (int)(b % gx);
   const int64_t rr = b / gx;
   const int by = (int)(rr % gy);
@@ -535,26 +548,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int32_t lab = in && t == TI ? d.label[n] : NOLAB;
   sweep_cell<D, P, FRC>(p, d, cur, in && (t == TL || t == TI), x, y, z, n, tb, lab);
 }
+template <int D, int P, bool FRC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep(KP p, DA d, int cur) {
+  b_sweep<D, P, FRC>(GridPos::hw(), p, d, cur);
+}
 
 // ------------------------------------------------------------------ split form
 // interface cells (this step's interface list) through the per-cell update
 template <int D, int P, bool FRC>
-__global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
+__device__ __forceinline__ void b_sweep_special(const GridPos &gp, KP p, DA d, int cur) {
   LIST_LOOP(k, d.cnt + C_I) {
     int64_t n = 0;
     uint8_t tb = TW;
     bool fluid = false;
     int32_t lab = NOLAB;
-    int x = 0, y = 0, z = 0;
     if (k < *(volatile int32_t *)(d.cnt + C_I)) {
       n = d.ilist[k];
       tb = TI;  // the near-wall bit only matters for liquid cells
       fluid = true;
       lab = d.label[n];
-      cell_xyz(p, n, x, y, z);
     }
-    sweep_cell<D, P, FRC>(p, d, cur, fluid, x, y, z, n, tb, lab);
+    // the domains this kernel serves have closed axes, and interface cells never lie on
+    // the outer (wall) layer
+    sweep_cell<D, P, FRC, true>(p, d, cur, fluid, 0, 0, 0, n, tb, lab);
   }
+}
+template <int D, int P, bool FRC>
+__global__ __launch_bounds__(256) void k_sweep_special(KP p, DA d, int cur) {
+  b_sweep_special<D, P, FRC>(GridPos::hw(), p, d, cur);
 }
 
 template <class T> __device__ __forceinline__ uint32_t lane_bits(T v) {
@@ -644,7 +665,7 @@ __device__ __forceinline__ void load_all(const KP &p, const typename Prec<P>::SF
 // cell index). Requires closed axes (no periodic wrap) and nx % VW == 0, so that every
 // group starts on a VW boundary and the pulls of a fluid cell are plain index offsets.
 template <int D, int P, int VW, int BS, bool FRC>
-__device__ __forceinline__ void sweep_vec_body(const KP &p, const DA &d, int cur) {
+__device__ __forceinline__ void sweep_vec_body(const GridPos &gp, const KP &p, const DA &d, int cur) {
   using L = Lat<D>;
   using R = typename Prec<P>::R;
   using SF = typename Prec<P>::SF;
@@ -658,7 +679,7 @@ __device__ __forceinline__ void sweep_vec_body(const KP &p, const DA &d, int cur
 
   const int64_t N = p.N;
   // plain block order: every XCD streams through neighbouring parts of the grid
-  const int64_t n0 = ((int64_t)blockIdx.x * BS + threadIdx.x) * VW;
+  const int64_t n0 = (gp.bid * BS + threadIdx.x) * VW;
   const int lane = lane_id();
 
   // cell types of the group
@@ -767,26 +788,20 @@ __device__ __forceinline__ void sweep_vec_body(const KP &p, const DA &d, int cur
   }
 }
 
-// cells per thread of the bulk kernel: 8-byte population accesses per lane
-// the variant used when none was chosen by the tuner: 8-byte population accesses per lane
-template <int P> constexpr int default_variant() { return P == 1 ? 1 : 0; }
-
 template <int D, int P, int VW>
 bool vector_ok(const Ctx &c) {
-  if (P == 0) return false;
-  if (c.kp.per[0] || c.kp.per[1] || c.kp.per[2]) return false;
-  return c.kp.nx % VW == 0 && c.kp.nx >= 2 * VW && c.kp.ny >= 3 && (D == 2 || c.kp.nz >= 3);
+  return bulk_shape_ok(c.kp, P, VW);
 }
 
 // the bulk kernel without and with the body-force term; the forced one is held to the
 // register budget of four waves per SIMD, which the memory-bound sweep needs
 template <int D, int P, int VW, int BS>
 __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
-  sweep_vec_body<D, P, VW, BS, false>(p, d, cur);
+  sweep_vec_body<D, P, VW, BS, false>(GridPos::hw(), p, d, cur);
 }
 template <int D, int P, int VW, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_vec_force(KP p, DA d, int cur) {
-  sweep_vec_body<D, P, VW, BS, true>(p, d, cur);
+  sweep_vec_body<D, P, VW, BS, true>(GridPos::hw(), p, d, cur);
 }
 
 template <int D, int P, int VW, int BS>
@@ -824,8 +839,8 @@ bool Ops<D, P>::sweep_bulk_auto(Ctx &c, hipStream_t s) {
   if constexpr (P == 0) {
     return false;
   } else {
-    const int v = c.sweep_variant >= 0 ? c.sweep_variant : default_variant<P>();
-    return sweep_bulk(c, s, v) || (v != default_variant<P>() && sweep_bulk(c, s, default_variant<P>()));
+    const int v = effective_sweep_variant(c.kp, P, c.sweep_variant);
+    return v >= 0 && sweep_bulk(c, s, v);
   }
 }
 
@@ -836,6 +851,76 @@ void Ops<D, P>::sweep_interface(Ctx &c, hipStream_t s) {
   if constexpr (P == 0) return;  // binary64 domains take the per-cell kernel
   if (c.kp.force) hipLaunchKernelGGL((k_sweep_special<D, P, true>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
   else hipLaunchKernelGGL((k_sweep_special<D, P, false>), dim3(list_blocks(c)), dim3(256), 0, s, c.kp, c.d, c.cur);
+}
+
+// batched forms of the sweep
+template <int D, int P, bool FRC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void km_sweep(MLaunch ml) {
+  MF_MULTI(MK_CELLS)
+  b_sweep<D, P, FRC>(gp, m.kp, m.d, m.cur);
+}
+template <int D, int P, bool FRC>
+__global__ __launch_bounds__(256) void km_sweep_special(MLaunch ml) {
+  MF_MULTI(MK_LIST)
+  b_sweep_special<D, P, FRC>(gp, m.kp, m.d, m.cur);
+}
+template <int D, int P, int VW, int BS, int V>
+__global__ __launch_bounds__(BS) void km_sweep_vec(MLaunch ml) {
+  MF_MULTI(MK_BULK0 + V)
+  sweep_vec_body<D, P, VW, BS, false>(gp, m.kp, m.d, m.cur);
+}
+template <int D, int P, int VW, int BS, int V>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void km_sweep_vec_force(MLaunch ml) {
+  MF_MULTI(MK_BULK0 + V)
+  sweep_vec_body<D, P, VW, BS, true>(gp, m.kp, m.d, m.cur);
+}
+template <int D, int P, int V>
+void launch_bulk_multi(const MStep &ms, bool frc, hipStream_t s) {
+  constexpr int VW = kSweepVariants[V].vw, BS = kSweepVariants[V].bs;
+  if (!ms.grid[MK_BULK0 + V]) return;
+  if (frc) hipLaunchKernelGGL((km_sweep_vec_force<D, P, VW, BS, V>), dim3(ms.grid[MK_BULK0 + V]), dim3(BS), 0, s, ms.at(MK_BULK0 + V));
+  else hipLaunchKernelGGL((km_sweep_vec<D, P, VW, BS, V>), dim3(ms.grid[MK_BULK0 + V]), dim3(BS), 0, s, ms.at(MK_BULK0 + V));
+}
+
+// the sweep of every domain of a batch: the per-cell kernel (cells), or the bulk kernel
+// in each launch shape of vmask (every domain takes work-groups in its own shape only)
+// followed by the interface kernel
+template <int D, int P>
+void Ops<D, P>::sweep_multi(const MStep &ms, unsigned vmask, bool cells, bool frc, hipStream_t s) {
+  if (cells || P == 0) {
+    if (frc) hipLaunchKernelGGL((km_sweep<D, P, true>), dim3(ms.grid[MK_CELLS]), dim3(256), 0, s, ms.at(MK_CELLS));
+    else hipLaunchKernelGGL((km_sweep<D, P, false>), dim3(ms.grid[MK_CELLS]), dim3(256), 0, s, ms.at(MK_CELLS));
+    return;
+  }
+  if constexpr (P != 0) {
+    if (vmask & 1u) launch_bulk_multi<D, P, 0>(ms, frc, s);
+    if (vmask & 2u) launch_bulk_multi<D, P, 1>(ms, frc, s);
+    if (vmask & 4u) launch_bulk_multi<D, P, 2>(ms, frc, s);
+    if (vmask & 8u) launch_bulk_multi<D, P, 3>(ms, frc, s);
+    if (vmask & 16u) launch_bulk_multi<D, P, 4>(ms, frc, s);
+    if (vmask & 32u) launch_bulk_multi<D, P, 5>(ms, frc, s);
+    if (vmask & 64u) launch_bulk_multi<D, P, 6>(ms, frc, s);
+    if (vmask & 128u) launch_bulk_multi<D, P, 7>(ms, frc, s);
+    if (frc) hipLaunchKernelGGL((km_sweep_special<D, P, true>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
+    else hipLaunchKernelGGL((km_sweep_special<D, P, false>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
+  }
+}
+
+template <int D, int P>
+void Ops<D, P>::bulk_multi(const MStep &ms, int v, bool frc, hipStream_t s) {
+  if constexpr (P != 0) {
+    switch (v) {
+      case 0: launch_bulk_multi<D, P, 0>(ms, frc, s); break;
+      case 1: launch_bulk_multi<D, P, 1>(ms, frc, s); break;
+      case 2: launch_bulk_multi<D, P, 2>(ms, frc, s); break;
+      case 3: launch_bulk_multi<D, P, 3>(ms, frc, s); break;
+      case 4: launch_bulk_multi<D, P, 4>(ms, frc, s); break;
+      case 5: launch_bulk_multi<D, P, 5>(ms, frc, s); break;
+      case 6: launch_bulk_multi<D, P, 6>(ms, frc, s); break;
+      case 7: launch_bulk_multi<D, P, 7>(ms, frc, s); break;
+      default: break;
+    }
+  }
 }
 
 // the per-cell kernel over the whole grid (binary64 and periodic domains)

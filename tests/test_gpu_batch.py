@@ -118,3 +118,45 @@ def test_tuner_picks_a_variant():
     assert v[0] == v[1] and v[0] >= 0 and v[2] == -1
     batch.step(2)
     batch.close()
+
+
+def test_batched_launches_over_many_domains():
+    """Seven domains in two groups: five with binary16 storage and the learned curvature
+    (three grid sizes, four bulk-sweep launch shapes among them, so every batched bulk
+    launch skips the domains of the other shapes) and two binary64 domains on the per-cell
+    kernel. Every kernel of a step runs as one launch per group. The batched states equal
+    stepping each domain alone, bit for bit, after even and odd step counts, and a binary64
+    domain of the batch matches the FP64 oracle."""
+    from paper_1908_04262_amd import Batch, CurvatureNet, Sim
+    net = CurvatureNet(21)
+    shapes = [(64, 40, 36, 4), (72, 36, 40, 6), (80, 40, 36, 7), (64, 40, 36, 0), (72, 36, 40, 6)]
+    cases = [small_case("c2_small", precision="f16s_g16", curvature="mlp", nx=nx, ny=ny, nz=nz, seed=30 + k)
+             for k, (nx, ny, nz, _) in enumerate(shapes)]
+    cases += [small_case("c1_small", precision="fp64", seed=5), small_case("c3_small", precision="fp64")]
+    variants = [v for (_, _, _, v) in shapes] + [-1, -1]
+
+    def make(wl, v):
+        s = Sim(wl)
+        if wl["curvature"] == "mlp":
+            s.attach_mlp(net)
+        s.nucleate(*place_nuclei(wl))
+        if v >= 0:
+            s.set_sweep_variant(v)
+        return s
+
+    solo = [make(w, v) for w, v in zip(cases, variants)]
+    grouped = [make(w, v) for w, v in zip(cases, variants)]
+    orc = Oracle(cases[6])
+    orc.nucleate(*place_nuclei(cases[6]))
+    batch = Batch(grouped)
+    for n in (2, 3, 4):
+        _say(f"batched launches: {n} steps")
+        batch.step(n)
+        for s in solo:
+            s.step(n)
+        for g, s in zip(grouped, solo):
+            _same(g, s)
+    orc.step(9)
+    compare_states(grouped[6], orc, tol_pop=1e-12, tol_cell=1e-10)
+    compare_bubbles(grouped[6], orc, 1e-12)
+    batch.close()
