@@ -47,6 +47,8 @@ struct OpsTable {
   void (*label_multi)(const MStep &, hipStream_t);
   void (*geometry_multi)(const MStep &, bool, hipStream_t);
   void (*bulk_multi)(const MStep &, int, bool, hipStream_t);
+  void (*convert_head)(Ctx &, hipStream_t);
+  void (*convert_tail)(Ctx &, hipStream_t);
 };
 
 template <int D, int P>
@@ -58,7 +60,8 @@ OpsTable make_ops() {
                   &Ops<D, P>::sweep_bulk_auto, &Ops<D, P>::sweep_interface, &Ops<D, P>::sweep_cells,
                   &Ops<D, P>::totals, &Ops<D, P>::bubble_stats, &Ops<D, P>::poke,
                   &Ops<D, P>::sweep_multi, &Ops<D, P>::convert_multi, &Ops<D, P>::label_multi,
-                  &Ops<D, P>::geometry_multi, &Ops<D, P>::bulk_multi};
+                  &Ops<D, P>::geometry_multi, &Ops<D, P>::bulk_multi, &Ops<D, P>::convert_head,
+                  &Ops<D, P>::convert_tail};
 }
 
 OpsTable ops_for(int dim, int prec) {
@@ -331,11 +334,11 @@ static void destroy_side(mf_ctx *c) {
   if (c->side) (void)hipStreamSynchronize(c->side);
   if (c->side2) (void)hipStreamSynchronize(c->side2);
   if (c->side2) (void)hipStreamDestroy(c->side2);
-  if (c->ev_lab) (void)hipEventDestroy(c->ev_lab);
   if (c->ev_start) (void)hipEventDestroy(c->ev_start);
   if (c->ev_list) (void)hipEventDestroy(c->ev_list);
+  if (c->ev_tail) (void)hipEventDestroy(c->ev_tail);
   c->side2 = nullptr;
-  c->ev_lab = c->ev_start = c->ev_list = nullptr;
+  c->ev_start = c->ev_list = c->ev_tail = nullptr;
   if (c->ev_conv) (void)hipEventDestroy(c->ev_conv);
   if (c->ev_side) (void)hipEventDestroy(c->ev_side);
   if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
@@ -418,9 +421,9 @@ int mf_create(const mf_params *p, void *dev_workspace, size_t ws_bytes, void *st
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_conv, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_norm, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_lab, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_list, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_tail, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking);
     if (e != hipSuccess) {
       g_err = std::string("creating the side stream failed: ") + hipGetErrorString(e);
@@ -517,14 +520,12 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 
 // one time step, enqueued on the context stream (host work: launches only, so that it
 // can be captured into a graph); ev: kStepEvents profiling events or NULL.
-// With overlap, a step runs on three streams of the context. The context stream takes the
-// sweep and the conversions. After the conversions, the side stream takes the labelling
-// and the curvature, and the third stream the normals (they read no ids: the excess pass
-// has written the stencil words) and then the next step's counter reset and interface-list
-// build. The next bulk sweep reads only cell types, populations and the wall mask, so it
-// runs beside all of that; it waits for the labelling and the normals, so that the
-// learned-curvature kernel is dispatched beside it rather than into a GPU it already
-// fills. The interface sweep, the first kernel that reads ids, bubble pressures,
+// With overlap, a step runs on three streams of the context (see Ctx). The context stream
+// takes the bulk sweep, the interface sweep and the first half of the conversions. After
+// that, the side stream takes their second half, the labelling and the curvature, and
+// side2 the normals and then the next step's counter reset and interface-list build. The
+// next bulk sweep reads only cell types, populations and the wall mask, so it runs beside
+// all of that. The interface sweep, the first kernel that reads ids, bubble pressures,
 // curvature and the new list, waits for both side streams. The caller joins what the last
 // step left running (join_side) before anything else touches the state. A step whose
 // stencil words need the whole-grid pass, and graph capture (where the domains already
@@ -548,11 +549,7 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
     reset_counters(c);
     c->ops.build_lists(*c, c->stream);
   }
-  if (c->side_pending) {
-    (void)hipStreamWaitEvent(c->stream, c->ev_lab, 0);
-    (void)hipStreamWaitEvent(c->stream, c->ev_norm, 0);
-  }
-  if (ev) (void)hipEventRecord(ev[1], c->stream);  // after the waits: times the bulk kernel alone
+  if (ev) (void)hipEventRecord(ev[1], c->stream);
   if (c->ops.sweep_bulk_auto(*c, c->stream)) {
     if (ev) (void)hipEventRecord(ev[2], c->stream);
     join_side(c);
@@ -569,13 +566,14 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
     }
   }
   c->cur ^= 1;
-  c->ops.convert(*c, c->stream);
   if (aside) {
+    c->ops.convert_head(*c, c->stream);
     (void)hipEventRecord(c->ev_conv, c->stream);
     (void)hipStreamWaitEvent(c->side, c->ev_conv, 0);
-    (void)hipStreamWaitEvent(c->side2, c->ev_conv, 0);
+    c->ops.convert_tail(*c, c->side);
+    (void)hipEventRecord(c->ev_tail, c->side);
+    (void)hipStreamWaitEvent(c->side2, c->ev_tail, 0);
     c->ops.label(*c, c->side, 1);
-    (void)hipEventRecord(c->ev_lab, c->side);
     c->ev_norm_rec = c->ev_norm;
     c->ops.geometry_normals(*c, c->side2, !c->sword_fresh);
     c->ev_norm_rec = nullptr;
@@ -585,6 +583,7 @@ static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
     (void)hipEventRecord(c->ev_side, c->side);
     c->side_pending = true;
   } else {
+    c->ops.convert(*c, c->stream);
     c->ops.label(*c, c->stream, 1);
     c->ops.geometry(*c, c->stream);
     if (ev) (void)hipEventRecord(ev[5], c->stream);
@@ -638,7 +637,7 @@ int mf_tune(mf_ctx *c, int32_t reps, int32_t *best, float *ms) {
         HIPCHK(c, e);
       }
       t /= (float)reps;
-      if (bv < 0 || t < bt) { bv = v; bt = t; }
+      if (step_variant(v) && (bv < 0 || t < bt)) { bv = v; bt = t; }
     }
     if (ms) ms[v] = t;
   }

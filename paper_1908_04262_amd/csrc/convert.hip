@@ -619,36 +619,57 @@ void Ops<D, P>::convert_multi(const MStep &ms, hipStream_t s) {
   hipLaunchKernelGGL((km_fill_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_empty_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_apply<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  hipLaunchKernelGGL((km_ni_init<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_topo_check<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_topo_window<D>), dim3(ms.grid[MK_TOPOW]), dim3(256), 0, s, ms.at(MK_TOPOW));
-  hipLaunchKernelGGL((km_ni_init<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_excess_prep<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_excess_gather<D, P>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
   hipLaunchKernelGGL(km_conv_clear, dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
 }
 
-template <int D, int P>
-void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
+// the passes over the short lists (converted cells and their new neighbours) take at most
+// four work-groups per CU: their entries are dealt one per wave, and a larger grid only
+// costs dispatch time on the step's critical path
+static inline unsigned short_blocks(const Ctx &c) {
   const unsigned nb = list_blocks(c);
-  // the passes over the short lists (converted cells and their new neighbours) take at
-  // most four work-groups per CU: their entries are dealt one per wave, and a larger grid
-  // only costs dispatch time on the step's critical path
-  const unsigned ns = nb < 1024 ? nb : 1024;
+  return nb < 1024 ? nb : 1024;
+}
+
+// the types after the conversions and the populations of the new interface cells: all
+// that the next bulk sweep reads
+template <int D, int P>
+void Ops<D, P>::convert_head(Ctx &c, hipStream_t s) {
+  const unsigned ns = short_blocks(c);
   const int cur = c.cur;  // buffer holding this step's post-collision populations
   hipLaunchKernelGGL((k_fill_scatter<D>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_empty_scatter<D>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_apply<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d, cur);
+  hipLaunchKernelGGL((k_ni_init<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d, cur);
+}
+
+// the topology test, the excess redistribution (fill fractions, stencil words) and the
+// flag clear; they read the new types and ids and write nothing the bulk sweep reads
+template <int D, int P>
+void Ops<D, P>::convert_tail(Ctx &c, hipStream_t s) {
+  const unsigned nb = list_blocks(c), ns = short_blocks(c);
   hipLaunchKernelGGL((k_topo_check<D>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_topo_window<D>), dim3(256), dim3(256), 0, s, c.kp, c.d);
-  hipLaunchKernelGGL((k_ni_init<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d, cur);
   hipLaunchKernelGGL((k_excess_prep<D, P>), dim3(ns), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL((k_excess_gather<D, P>), dim3(nb), dim3(256), 0, s, c.kp, c.d);
   hipLaunchKernelGGL(k_conv_clear, dim3(ns), dim3(256), 0, s, c.d);
   c.sword_fresh = c.d.sword != nullptr;  // the excess pass wrote the list cells' stencil words
 }
 
+template <int D, int P>
+void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
+  convert_head(c, s);
+  convert_tail(c, s);
+}
+
 #define MF_INST(D, P)                                    \
   template void Ops<D, P>::convert(Ctx &, hipStream_t); \
+  template void Ops<D, P>::convert_head(Ctx &, hipStream_t); \
+  template void Ops<D, P>::convert_tail(Ctx &, hipStream_t); \
   template void Ops<D, P>::convert_multi(const MStep &, hipStream_t);
 MF_FOR_ALL(MF_INST)
 

@@ -502,8 +502,8 @@ void Ops<D, P>::geometry(Ctx &c, hipStream_t s) {
   if (sword_all) {
     const int64_t g = (c.kp.N + 255) / 256;
     hipLaunchKernelGGL((k_sword_all<P>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, c.kp, c.d);
-    c.sword_dirty = false;
   }
+  c.sword_dirty = false;  // (a context without words has none to rebuild)
   geometry_normals(c, s, !sword_all && !c.sword_fresh);
   geometry_curv(c, s);
 }

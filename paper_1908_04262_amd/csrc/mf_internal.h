@@ -421,7 +421,12 @@ template <int D, int P> struct Ops {
   // one launch of the bulk sweep kernel in tuning variant v (see kSweepVariants); false
   // when the variant does not apply to this domain (nothing launched)
   static bool sweep_bulk(Ctx &c, hipStream_t s, int v);
+  // the conversions: convert_head() changes the types and initialises the new interface
+  // cells (all the next bulk sweep reads), convert_tail() runs the topology test, the excess
+  // redistribution and the flag clear; convert() is both in order
   static void convert(Ctx &c, hipStream_t s);
+  static void convert_head(Ctx &c, hipStream_t s);
+  static void convert_tail(Ctx &c, hipStream_t s);
   static void label(Ctx &c, hipStream_t s, int apply_flux);
   static void geometry(Ctx &c, hipStream_t s);
   // the two halves of geometry(): normals (words: also the list cells' stencil words), and
@@ -468,21 +473,23 @@ struct Ctx {
   std::string err;
   bool prof = false;
   void *mlp_buf = nullptr;  // device copy of the attached network's weights
-  // Steps overlap: the labelling and curvature of step n run on the side stream, its
-  // normals and then the counter reset and interface-list build of step n+1 on side2, while
-  // the main stream runs the bulk sweep of step n+1 (none of them reads what another
-  // writes). Counters and the interface list alternate between two copies by step parity.
-  // The bulk sweep starts once the labelling (ev_lab) and the normals (ev_norm) are done,
-  // so that the learned-curvature kernel is dispatched beside it instead of into a GPU the
-  // bulk sweep already fills; the interface sweep waits for the side stream (ev_side) and
-  // the list build (ev_list). geometry_normals() records ev_norm_rec, when set.
+  // Steps overlap. After the first half of the conversions of step n (types and new
+  // interface cells, on the context stream), the side stream takes the second half
+  // (topology test, excess redistribution), the labelling and the curvature; side2 takes
+  // the normals and then the counter reset and interface-list build of step n+1; the
+  // context stream goes on with the bulk sweep of step n+1. None of them writes what
+  // another reads. Counters and the interface list alternate between two copies by step
+  // parity. The interface sweep waits for the side stream (ev_side) and the list build
+  // (ev_list). ev_tail marks the end of the conversions' second half (the normals read the
+  // fill fractions it writes). geometry_normals() records ev_norm_rec, when set.
   int32_t *cnt_base = nullptr, *ilist_base = nullptr;
   int parity = 0;
   hipStream_t side = nullptr;
   hipStream_t side2 = nullptr;  // the normals, beside the labelling on the side stream
-  hipEvent_t ev_conv = nullptr, ev_side = nullptr, ev_norm = nullptr, ev_norm_rec = nullptr, ev_lab = nullptr;
+  hipEvent_t ev_conv = nullptr, ev_side = nullptr, ev_norm = nullptr, ev_norm_rec = nullptr;
   bool sword_fresh = false;     // the excess pass of this step wrote the list cells' stencil words
   hipEvent_t ev_start = nullptr, ev_list = nullptr;  // step start (context stream), list built (third stream)
+  hipEvent_t ev_tail = nullptr;
   bool list_pending = false;    // the interface sweep must wait for ev_list
   bool side_pending = false;  // ev_side marks side-stream work the main stream has not joined
 };
@@ -505,14 +512,20 @@ inline bool bulk_shape_ok(const KP &kp, int precision, int vw) {
   if (kp.per[0] || kp.per[1] || kp.per[2]) return false;
   return kp.nx % vw == 0 && kp.nx >= 2 * vw && kp.ny >= 3 && (kp.dim == 2 || kp.nz >= 3);
 }
-// the launch shape used when none was chosen by the tuner: one wave per work-group, with
-// 16-byte population accesses per lane for 16-bit storage (8 cells per thread) and for
-// binary32 (4 cells per thread); measured fastest on the 384^3 foam
-inline int default_sweep_variant(int precision) { return precision == 1 ? 7 : 6; }
+// Inside a time step the bulk kernel runs beside the labelling, normals and curvature
+// kernels of the side streams. Work-groups of 256 threads let those kernels take over the
+// slots of a retired bulk work-group; with one-wave work-groups the bulk kernel refills
+// every freed slot at once and starves them, which costs more than the one-wave shapes
+// gain alone. Hence the tuner of a context chooses among the 256-thread shapes.
+inline bool step_variant(int v) { return kSweepVariants[v].bs == 256; }
+// the launch shape used when none was chosen by the tuner: 16-byte population accesses
+// per lane for 16-bit storage (8 cells per thread) and for binary32 (4 cells per thread);
+// measured fastest inside the step on the 384^3 foam
+inline int default_sweep_variant(int precision) { return precision == 1 ? 0 : 4; }
 // the launch shape a domain is swept with: the tuned one, else the default, else narrower
 // vectors for rows whose length is not a multiple of 8 cells; -1: the per-cell kernel
 inline int effective_sweep_variant(const KP &kp, int precision, int tuned) {
-  const int order[4] = {tuned, default_sweep_variant(precision), 7, 1};
+  const int order[4] = {tuned, default_sweep_variant(precision), 0, 1};
   for (int v : order)
     if (v >= 0 && bulk_shape_ok(kp, precision, kSweepVariants[v].vw)) return v;
   return -1;

@@ -235,3 +235,41 @@ def test_headline_form_against_fp64_oracle(trained_net):
         assert dv.max() < 0.01, dv.max()
         assert dm < 1e-6, dm
     _say(f"worst volume deviation over 500 steps {worst:.2e}")
+
+
+@pytest.mark.timeout(900)
+def test_config4_crop_fp32_learned_curvature(trained_net):
+    """Config 4's foam (config-2 physics: tau 0.7, sigma 5e-4, supersaturation 1.5,
+    disjoining pressure; radii U[3,5], separation 12) with binary32 storage and the learned
+    curvature, on a 64^3 crop with the bubble density of the 256^3 run (8 bubbles), against
+    the FP64 oracle with the plain fit: liquid mass within 1e-6 relative and every bubble
+    volume within 0.5% for 300 steps while the oracle's bubble ids are unchanged."""
+    from paper_1908_04262_amd import Sim
+    from synth import workload
+    n = 64
+    wl64 = workload("c4_foam_256", nx=n, ny=n, nz=n, precision="fp64", curvature="plain", max_ids=1024)
+    wl64["gas_from"] = int(0.75 * n)
+    wl64["nuclei"] = dict(wl64["nuclei"], n=8)
+    wl = dict(wl64, precision="fp32", curvature="mlp")
+    _say("config-4 crop 64^3, fp32 + mlp vs fp64 oracle, 300 steps")
+    gpu = Sim(wl)
+    gpu.attach_mlp(trained_net)
+    orc = Oracle(wl64)
+    c, r, p0 = place_nuclei(wl64)
+    gpu.nucleate(c, r, p0)
+    orc.nucleate(c, r, p0)
+    m0 = _liquid(gpu)
+    compared, worst = 0, 0.0
+    for k in range(6):
+        gpu.step(50)
+        orc.step(50)
+        bg, bo = gpu.bubbles(), orc.bubbles()
+        dm = abs(_liquid(gpu) - m0) / m0
+        assert dm < 1e-6, dm
+        if list(bg["id"]) == list(bo["id"]) and orc.ledgers()["next_id"] == len(r) + 1:
+            dv = np.abs(bg["V"] - bo["V"]) / bo["V"]
+            worst = max(worst, dv.max())
+            assert dv.max() < 0.005, dv.max()
+            compared += 1
+        _say(f"  step {50 * (k + 1)}: mass drift {dm:.2e}, compared {compared}, worst volume {worst:.2e}")
+    assert compared >= 2
