@@ -166,6 +166,7 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.scratch_d = cv.take<double>(cap * 8);
   d.tacc = cv.take<long long>(6 * 8);
   d.bstat = cv.take<long long>(cap * 13 * 8);
+  d.aff = cv.take<uint8_t>(cap);
 }
 
 int validate(const mf_params *p, std::string &why) {

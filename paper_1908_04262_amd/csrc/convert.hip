@@ -154,6 +154,7 @@ __device__ __forceinline__ void b_apply(const GridPos &gp, KP p, DA d, int cur) 
       const uint8_t cl = d.cflag[n];
       if (cl & CF_FILL) {
         d.type[n] = (d.type[n] & ~TMASK) | TL;
+        d.parent[n] = d.label[n];  // the former id, for the topology test
         d.label[n] = NOLAB;
       } else if (cl & CF_EMPTY) {
         d.type[n] = (d.type[n] & ~TMASK) | TG;
@@ -321,9 +322,10 @@ __global__ __launch_bounds__(256) void k_excess_prep(KP p, DA d) {
 // ascending direction order; alpha = M / rho. With the learned curvature, the pass also
 // writes the stencil word of every list cell (converted ones included), whose type, fill
 // fraction or id may have changed this step; the labelling that follows changes ids only
-// when it relabels, and then rewrites the words of every gas and interface cell itself. On a step whose conversions leave every
-// bubble as it was (the topology test passed), the same pass adds each interface cell's
-// volume share 1 - alpha to its bubble (fixed point; the gas cells are counted apart),
+// when it relabels, and then rewrites the words of the cells it relabels itself. For every
+// bubble the labelling will not relabel (all of them when the topology test passed), the
+// same pass adds each interface cell's volume share 1 - alpha to its bubble (fixed point;
+// the gas cells are counted apart),
 // and it clears the conversion flags of the cells it visits (the converted cells, whose
 // flags its neighbours read here, are cleared by the next pass).
 template <int D, int P>
@@ -333,7 +335,10 @@ __device__ __forceinline__ void b_excess_gather(const GridPos &gp, KP p, DA d) {
   const int nI = *(volatile int32_t *)(d.cnt + C_I);
   const int nNI = *(volatile int32_t *)(d.cnt + C_NI);
   const int nL = *(volatile int32_t *)(d.cnt + C_L2I);
-  const bool fast = !*(volatile int32_t *)(d.cnt + C_TOPO);
+  // the volumes of the bubbles the labelling does not relabel (all of them on a step
+  // without topology change, the unmarked ones on a partial relabelling)
+  const bool topo = *(volatile int32_t *)(d.cnt + C_TOPO) != 0;
+  const bool fast = !topo || !*(volatile int32_t *)(d.cnt + C_FULL);
   const int64_t total = (int64_t)nI + nNI + nL;
   for (int64_t k = (int64_t)gp.bid * blockDim.x + threadIdx.x; k < ((total + 63) & ~(int64_t)63);
        k += (int64_t)gp.nblk * blockDim.x) {
@@ -362,7 +367,7 @@ __device__ __forceinline__ void b_excess_gather(const GridPos &gp, KP p, DA d) {
         if (d.sword) d.sword[n] = stencil_word<R>(d.type[n], al, d.label[n]);
         if (fast) {
           lab = d.label[n];
-          if (lab > 0 && lab < p.cap) {
+          if (lab > 0 && lab < p.cap && !(topo && d.aff[lab])) {
             act = true;
             v = fx3((double)(R(1) - al));
           }
@@ -399,8 +404,10 @@ __global__ __launch_bounds__(256) void k_conv_clear(DA d) {
 //    interface lattice neighbours of K. If R is not empty and connected inside the window
 //    without the leaving cells, every path through K has a detour, so nothing splits or
 //    disappears.
-// When any cell fails, the flag is set and the full labelling runs; otherwise ids, merges
-// and splits stay as they were.
+// When any cell fails, the flag is set and the ids of the components around it are marked:
+// the labelling then relabels the cells of the marked ids only (every component a
+// conversion can merge, split or remove carries one of them), and every other bubble keeps
+// its id, its gas and its cells.
 //
 // The window is held one x-row per lane (W bits; lane = (dy + H) + W (dz + H)), so a step
 // of lattice dilation is two shifts along x and a few shuffles for the rows around.
@@ -480,8 +487,15 @@ template <int D> struct RowWindow {
   }
 };
 
+// marks id lab as one whose component the conversions may have changed (any number of
+// threads may mark the same id)
+__device__ __forceinline__ void mark_affected(const KP &p, const DA &d, int32_t lab) {
+  if (lab > 0 && lab < p.cap) d.aff[lab] = 1;
+}
+
 // cheap per-cell tests over the converted cells: joining cells are decided here, filling
-// cells that need the window test are listed
+// cells that need the window test are listed. A joining cell next to other ids marks them
+// and its own; every cell is tested, so that all changed components are marked.
 template <int D>
 __device__ __forceinline__ void b_topo_check(const GridPos &gp, KP p, DA d) {
   using L = Lat<D>;
@@ -491,12 +505,12 @@ __device__ __forceinline__ void b_topo_check(const GridPos &gp, KP p, DA d) {
   // a periodic axis shorter than the widest window would wrap it onto itself: full
   // labelling
   constexpr int WMAX = 7;
-  bool change = total > 0 && ((p.per[0] && p.nx < WMAX) || (p.per[1] && p.ny < WMAX) || (D == 3 && p.per[2] && p.nz < WMAX));
+  bool full = total > 0 && ((p.per[0] && p.nx < WMAX) || (p.per[1] && p.ny < WMAX) || (D == 3 && p.per[2] && p.nz < WMAX));
+  bool change = false;
   SPREAD_LOOP_N(k, total) {
     bool cand = false;
     int64_t n = 0;
-    if (k >= total || change) {
-    } else {
+    if (k < total && !full) {
       // both tests read the types and ids of the lattice neighbours: loaded together
       const bool join = k >= nI;
       n = join ? d.l2ilist[k - nI] : d.clist[k];
@@ -514,9 +528,17 @@ __device__ __forceinline__ void b_topo_check(const GridPos &gp, KP p, DA d) {
         for (int i = 1; i < L::Q; ++i) lb[i] = yy[i] >= 0 ? d.label[yy[i]] : 0;
         if (join) {
           const int32_t lx = d.label[n];
+          bool merges = false;
 #pragma unroll
           for (int i = 1; i < L::Q; ++i)
-            if ((t[i] == TG || t[i] == TI) && lb[i] != lx) change = true;
+            if ((t[i] == TG || t[i] == TI) && lb[i] != lx) {
+              merges = true;
+              mark_affected(p, d, lb[i]);
+            }
+          if (merges) {
+            mark_affected(p, d, lx);
+            change = true;
+          }
         } else {
           // a leaving cell of the atmosphere (a gas / interface neighbour with id 0) changes
           // no bubble: every piece of the atmosphere keeps id 0 and no bubble touches it
@@ -531,10 +553,11 @@ __device__ __forceinline__ void b_topo_check(const GridPos &gp, KP p, DA d) {
     const int slot = wave_append_slot(d.cnt + C_TCAND, cand);
     if (cand) {
       if (slot < TCAND_CAP) d.tcand[slot] = (int32_t)n;
-      else change = true;
+      else full = true;  // not tested: every component is relabelled
     }
   }
-  if (__ballot(change) != 0 && lane_id() == 0) d.cnt[C_TOPO] = 1;
+  if (__ballot(change || full) != 0 && lane_id() == 0) d.cnt[C_TOPO] = 1;
+  if (__ballot(full) != 0 && lane_id() == 0) d.cnt[C_FULL] = 1;
 }
 template <int D>
 __global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
@@ -542,22 +565,31 @@ __global__ __launch_bounds__(256) void k_topo_check(KP p, DA d) {
 }
 
 // the window tests of the listed filling cells, one wave per cell: the lanes load the
-// window, the whole wave runs the floods
+// window, the whole wave runs the floods. A cell that fails marks its former id and the
+// ids of its gas / interface neighbours.
 template <int D>
 __device__ __forceinline__ void b_topo_window(const GridPos &gp, KP p, DA d) {
+  using L = Lat<D>;
   const int nc = min(*(volatile int32_t *)(d.cnt + C_TCAND), TCAND_CAP);
   const int wave = (int)(gp.bid * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const int nwaves = (int)(gp.nblk * (blockDim.x >> 6));
-  if (wave >= nc || *(volatile int32_t *)(d.cnt + C_TOPO)) return;  // wave-uniform
+  if (wave >= nc || *(volatile int32_t *)(d.cnt + C_FULL)) return;  // wave-uniform
   const RowWindow<D> w;
   for (int c = wave; c < nc; c += nwaves) {
+    const int64_t n = d.tcand[c];
     int x, y, z;
-    cell_xyz(p, d.tcand[c], x, y, z);
+    cell_xyz(p, n, x, y, z);
     uint32_t g, f;
     w.load(p, d, x, y, z, g, f);
-    if (w.changes(g, f)) {
-      if (lane_id() == 0) d.cnt[C_TOPO] = 1;
-      return;
+    if (w.changes(g, f) && lane_id() == 0) {
+      d.cnt[C_TOPO] = 1;
+      mark_affected(p, d, d.parent[n]);
+      for (int i = 1; i < L::Q; ++i) {
+        const int64_t yy = nb_index_or_none(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
+        if (yy < 0) continue;
+        const int t = d.type[yy] & TMASK;
+        if (t == TG || t == TI) mark_affected(p, d, d.label[yy]);
+      }
     }
   }
 }

@@ -193,10 +193,14 @@ constexpr int LIST_CPT = 64;
 constexpr int LIST_CHUNK = 256 * LIST_CPT;
 constexpr int LIST_GRID = 1024;
 
-// list 0: interface cells; list 1: gas / interface cells with a non-zero bubble id
+// list 0: interface cells; list 1: gas / interface cells with a non-zero bubble id (of a
+// marked id, on a partial relabelling)
 template <int WHICH>
 __device__ __forceinline__ unsigned long long list_mask(const KP &p, const DA &d, int64_t c0) {
   unsigned long long mk = 0;
+  // the bubble list holds the cells of the marked ids only, unless every component is
+  // relabelled
+  const bool all = WHICH == 1 && *(volatile int32_t *)(d.cnt + C_FULL) != 0;
 #pragma unroll
   for (int g = 0; g < LIST_CPT / 16; ++g) {
     const int64_t n = c0 + g * 16;
@@ -232,7 +236,9 @@ __device__ __forceinline__ unsigned long long list_mask(const KP &p, const DA &d
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (((gi >> (4 * q + k)) & 1u) && lb[k] != 0) mk |= 1ull << (g * 16 + 4 * q + k);
+          if (((gi >> (4 * q + k)) & 1u) && lb[k] != 0 &&
+              (all || (lb[k] > 0 && lb[k] < p.cap && d.aff[lb[k]])))
+            mk |= 1ull << (g * 16 + 4 * q + k);
       }
     }
   }

@@ -7,6 +7,12 @@
 //
 // Only cells with a non-zero bubble id take part in the union-find; the atmosphere is
 // one node that a component joins when one of its cells touches an atmosphere cell.
+// A step's conversions can change only the components around the cells they convert
+// (the topology test marks their ids); a relabelling step then relabels the cells of the
+// marked ids alone, and every other bubble keeps its id and gas and gets its volume from
+// the fast path's sums. The results equal those of relabelling every cell: an unmarked
+// component would come out of the full labelling with its own id, its whole gas and the
+// same fixed-point volume.
 // Volumes and gas are summed in 128-bit fixed point, so all results are independent of
 // the order in which threads run.
 #include "mf_internal.h"
@@ -56,15 +62,17 @@ __device__ __forceinline__ void b_ccl_hook(const GridPos &gp, KP p, DA d) {
     if (!(d.cflag[n] & CF_VALID)) continue;
     int x, y, z;
     cell_xyz(p, n, x, y, z);
-    bool atm = false;
+    bool atm = false, stray = false;
     for (int i = 1; i < L::Q; ++i) {
       const int64_t yy = nb_index(p, x, y, z, L::ex[i], L::ey[i], L::ez[i]);
       const int ty = d.type[yy] & TMASK;
       if (ty != TG && ty != TI) continue;
       if (d.label[yy] == 0) atm = true;
+      else if (!(d.cflag[yy] & CF_VALID)) stray = true;  // an unlisted id next to a listed one
       else if (yy > n) uf_union(d.parent, (int32_t)n, (int32_t)yy);
     }
     if (atm) flag_or(d.cflag, n, CF_ATM);
+    if (stray) raise_status(d.status, ST_INVARIANT);
   }
 }
 template <int D>
@@ -201,6 +209,9 @@ __device__ void write_bubble(const KP &p, DA &d, int id, double m, __int128 vk) 
 // ascending root order by one thread, which is the order the assignment rule needs.
 __device__ __forceinline__ void b_bubble_update(const GridPos &gp, KP p, DA d, int apply_flux) {
   if (!*(volatile int32_t *)(d.cnt + C_TOPO)) return;  // fast path this step
+  // partial: only the marked ids (and the atmosphere) are updated here; the fast-path
+  // kernel has updated the others
+  const bool partial = !*(volatile int32_t *)(d.cnt + C_FULL);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int cap = p.cap;
   __shared__ int s_ncont, s_nroot;
@@ -218,6 +229,7 @@ __device__ __forceinline__ void b_bubble_update(const GridPos &gp, KP p, DA d, i
   __syncthreads();
   // phase 0: gas of each old bubble after this step's flux; clear the table
   for (int j = tid; j < jmax; j += nt) {
+    if (partial && j > 0 && !d.aff[j]) continue;
     const int al = d.balive[j];
     d.alive_prev[j] = al;
     double mp = 0.0;
@@ -333,7 +345,7 @@ __device__ __forceinline__ void b_bubble_update(const GridPos &gp, KP p, DA d, i
   __syncthreads();
   // phase D: atmosphere shares and collapsed bubbles
   for (int j = 1 + tid; j < jmax; j += nt) {
-    if (!d.alive_prev[j]) continue;
+    if ((partial && !d.aff[j]) || !d.alive_prev[j]) continue;
     const int lc = d.lab_cnt[j];
     const bool inatm = (lc & ATMBIT) != 0;
     const int nonatm = lc & ~ATMBIT;
@@ -396,12 +408,14 @@ __device__ __forceinline__ void b_bubble_update(const GridPos &gp, KP p, DA d, i
     d.cnt[C_CONTESTED] = nc;
   }
   __syncthreads();
-  // clear the used root-hash slots; fold this step's ledgers into the running totals
+  // clear the used root-hash slots and the marks; fold this step's ledgers into the
+  // running totals
   for (int u = tid; u < nroot; u += nt) {
     const int s = d.rused[u];
     d.rh_key[s] = REMPTY;
     d.rh_head[s] = -1;
   }
+  for (int j = tid; j < jmax; j += nt) d.aff[j] = 0;
   if (tid == 0) {
     d.ledtot[0] += join3(&d.led[0]);
     d.ledtot[1] += join3(&d.led[3]) + fx3_join(s_atm[0], s_atm[1], s_atm[2]);
@@ -476,14 +490,17 @@ void recount_gas(const Ctx &c, hipStream_t s) {
 // excess pass: the same fixed-point sums as the full path's, so the results are
 // identical to what the full labelling would give.
 // Several work-groups over the ids; the first also folds the atmosphere's terms and the
-// step's ledgers into the running totals.
+// step's ledgers into the running totals. On a partial relabelling the same update serves
+// the unmarked ids only; the relabelling takes the marked ones, the atmosphere and the
+// ledgers.
 __device__ __forceinline__ void b_bubble_fast(const GridPos &gp, KP p, DA d) {
-  if (*(volatile int32_t *)(d.cnt + C_TOPO)) return;
+  const bool partial = *(volatile int32_t *)(d.cnt + C_TOPO) != 0;
+  if (partial && *(volatile int32_t *)(d.cnt + C_FULL)) return;
   const int tid = threadIdx.x;
   __shared__ long long s_atm[3];
   int jmax = *(volatile int32_t *)d.nextid;
   if (jmax > p.cap) jmax = p.cap;
-  if (gp.bid == 0 && tid < 64) {
+  if (!partial && gp.bid == 0 && tid < 64) {
     long long sa[3];
     take_atm_copies(d, sa);
     if (tid == 0)
@@ -491,6 +508,7 @@ __device__ __forceinline__ void b_bubble_fast(const GridPos &gp, KP p, DA d) {
   }
   __syncthreads();
   for (int j = gp.bid * blockDim.x + tid; j < jmax; j += gp.nblk * blockDim.x) {
+    if (partial && (j == 0 || d.aff[j])) continue;
     if (j > 0 && d.balive[j]) {
       const double mp = d.bm[j] + fx_to_double(join3(&d.phi[3 * j]) + join3(&d.gam[3 * j]));
       // volume: one per gas cell, 1 - alpha per interface cell (fixed point, 2^64 = 1)
@@ -498,7 +516,7 @@ __device__ __forceinline__ void b_bubble_fast(const GridPos &gp, KP p, DA d) {
     }
     for (int c = 0; c < 3; ++c) d.phi[3 * j + c] = d.gam[3 * j + c] = d.vacc[3 * j + c] = 0;
   }
-  if (gp.bid == 0 && tid == 0) {
+  if (!partial && gp.bid == 0 && tid == 0) {
     d.ledtot[0] += join3(&d.led[0]);
     d.ledtot[1] += join3(&d.led[3]) + fx3_join(s_atm[0], s_atm[1], s_atm[2]);
     d.ledtot[2] += join3(&d.led[6]);
@@ -513,7 +531,10 @@ __global__ __launch_bounds__(256) void k_bubble_fast(KP p, DA d) {
 }
 
 // outside the time step (nucleation, refresh) the full labelling always runs
-__global__ void k_force_full(DA d) { d.cnt[C_TOPO] = 1; }
+__global__ void k_force_full(DA d) {
+  d.cnt[C_TOPO] = 1;
+  d.cnt[C_FULL] = 1;
+}
 
 // batched forms (time-step labelling: the flux of the step is applied)
 __global__ __launch_bounds__(256) void km_bubble_fast(MLaunch ml) {

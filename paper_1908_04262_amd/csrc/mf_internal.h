@@ -30,9 +30,11 @@ constexpr int ST_NONFINITE = 4;   // non-finite density at an interface cell
 constexpr int ST_BADLABEL = 8;    // interface cell with an invalid bubble id
 
 // counters
-// C_TOPO: set when this step's conversions may have merged, split or removed a component
+// C_TOPO: set when this step's conversions may have merged, split or removed a component;
+// the ids of every such component are then marked in d.aff, unless C_FULL is set too
+// (every component is relabelled)
 // per-step counters (all cleared at the start of a step)
-enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_CONV, C_NCOUNT = 16 };
+enum { C_I = 0, C_B, C_NI, C_L2I, C_ENTRIES, C_ROOTS, C_CONTESTED, C_TOPO, C_TCAND, C_CONV, C_FULL, C_NCOUNT = 16 };
 // capacity of the list of filling cells whose neighbourhood the topology test examines
 constexpr int TCAND_CAP = 65536;
 
@@ -160,7 +162,11 @@ struct DA {
   // gas side of each interface cell for the next sweep: density 3 (p_b - 2 sigma kappa - Pi)
   // and bubble pressure p_b, set with the geometry
   void *rgas, *pbub;
-  int32_t *label, *parent;
+  int32_t *label;
+  // union-find parent of each cell of the bubble list on a relabelling step; a cell that
+  // filled this step holds its former id there until the topology test has read it
+  int32_t *parent;
+  uint8_t *aff;               // ids whose components the conversions may have changed [cap]
   int32_t *ilist, *blist, *nilist, *l2ilist;
   int32_t *clist;             // interface cells that fill or empty this step (sweep appends)
   int32_t *lcnt;              // per-chunk counts / offsets of the list builder [chunks]
