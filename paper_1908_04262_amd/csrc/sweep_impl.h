@@ -794,13 +794,16 @@ bool vector_ok(const Ctx &c) {
 }
 
 // the bulk kernel without and with the body-force term; the forced one is held to the
-// register budget of four waves per SIMD, which the memory-bound sweep needs
+// register budget of four waves per SIMD, which the memory-bound sweep needs, except with
+// eight cells per thread, whose 16-byte population vectors do not fit that budget (held to
+// it, the kernel spills to scratch and moves four times its bytes): three waves there
+template <int VW> constexpr int force_waves() { return VW >= 8 ? 3 : 4; }
 template <int D, int P, int VW, int BS>
 __global__ __launch_bounds__(BS) void k_sweep_vec(KP p, DA d, int cur) {
   sweep_vec_body<D, P, VW, BS, false>(GridPos::hw(), p, d, cur);
 }
 template <int D, int P, int VW, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_vec_force(KP p, DA d, int cur) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(force_waves<VW>()))) void k_sweep_vec_force(KP p, DA d, int cur) {
   sweep_vec_body<D, P, VW, BS, true>(GridPos::hw(), p, d, cur);
 }
 
@@ -870,7 +873,7 @@ __global__ __launch_bounds__(BS) void km_sweep_vec(MLaunch ml) {
   sweep_vec_body<D, P, VW, BS, false>(gp, m.kp, m.d, m.cur);
 }
 template <int D, int P, int VW, int BS, int V>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void km_sweep_vec_force(MLaunch ml) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(force_waves<VW>()))) void km_sweep_vec_force(MLaunch ml) {
   MF_MULTI(MK_BULK0 + V)
   sweep_vec_body<D, P, VW, BS, true>(gp, m.kp, m.d, m.cur);
 }
