@@ -267,7 +267,7 @@ def run_one(wl, steps, warmup, log, net=None, late_steps=0):
     return res
 
 
-def run_ensemble(net, steps, log):
+def run_ensemble(net, steps, log, until=0):
     """The batched ensemble (48 domains of 64^3..160^3, binary16 storage, learned
     curvature): MLUPS over all domains when every domain is stepped in turn, and with the
     tuned bulk sweep and one graph launch per two steps for all domains."""
@@ -304,6 +304,32 @@ def run_ensemble(net, steps, log):
     batch.step(steps)
     torch.cuda.synchronize()
     bat = cells * steps / (time.perf_counter() - t2) / 1e6
+    long = None
+    if until > 0:
+        # carry on with the batched launches until every domain has taken `until` steps:
+        # liquid mass (plus the lost-liquid ledger) and total gas are conserved quantities
+        def conserved(s):
+            t = s.ledgers()
+            return (t["liquid"] + t["lost_liquid"],
+                    t["dissolved"] + t["bubble_gas"] + t["atm_gas"] + t["collapsed_gas"])
+        c0 = [conserved(s) for s in sims]
+        done = int(sims[0].ledgers()["step"])
+        left = max(until - done, 0)
+        t3 = time.perf_counter()
+        batch.step(left)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t3
+        c1 = [conserved(s) for s in sims]
+        led = [s.ledgers() for s in sims]
+        long = {"steps_per_domain": int(led[0]["step"]), "batched_steps": left,
+                "mlups_batched": round(cells * left / dt / 1e6, 1) if left else None,
+                "seconds": round(dt, 2),
+                "max_rel_liquid_drift": max(abs(b[0] - a[0]) / a[0] for a, b in zip(c0, c1)),
+                "max_rel_gas_drift": max(abs(b[1] - a[1]) / a[1] for a, b in zip(c0, c1)),
+                "bubbles": int(sum(t["n_bubbles"] for t in led)),
+                "all_at_step": all(int(t["step"]) == int(led[0]["step"]) for t in led)}
+        log(f"[ensemble] {left} more batched steps to step {long['steps_per_domain']}: "
+            f"{long['mlups_batched']} MLUPS, {json.dumps(long)}")
     st = [s.ledgers()["status"] for s in sims]
     log(f"[ensemble] sequential {seq:.0f} MLUPS, batched graph {bat:.0f} MLUPS, variants "
         f"{dict(zip(*np.unique(variants, return_counts=True)))}")
@@ -315,7 +341,7 @@ def run_ensemble(net, steps, log):
     return {"domains": len(wls), "cells": cells, "steps": steps,
             "mlups_sequential": round(seq, 1), "mlups_batched": round(bat, 1),
             "speedup": round(bat / seq, 3), "status_ok": all(x == 0 for x in st),
-            "tuned_variants": [int(v) for v in variants]}
+            "tuned_variants": [int(v) for v in variants], "long_run": long}
 
 
 def crop_workload(n=96):
@@ -434,6 +460,8 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=25)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--ensemble-until", type=int, default=0,
+                    help="continue the batched ensemble until every domain has taken this many steps")
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -462,7 +490,7 @@ def main():
     r16c = run_one(dict(wl, precision="f16s_g16", curvature="mlp", **cy), max(a.steps // 2, 1),
                    a.warmup, log, net=net)
     nuc = time_field_nucleation(wl, log)
-    ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log)
+    ens = None if a.no_ensemble else run_ensemble(net, a.ensemble_steps, log, a.ensemble_until)
     cpu = None if a.no_cpu_baseline else cpu_baseline(log)
     acc = None if a.accuracy_steps <= 0 else crop_accuracy(net, a.accuracy_steps, log)
 
