@@ -1,9 +1,15 @@
-"""The benchmark workload at its full size (384^3 power-law foam, 2000 nuclei, seed 3) in the
-launch configuration bench.py times (binary16 f and g with the learned curvature; binary32
-with the plain fit), checked through properties that hold at any size:
+"""Workloads at their full sizes, checked through properties that hold at any size:
+
+* the benchmark workload (384^3 power-law foam, 2000 nuclei, seed 3) in the launch
+  configuration bench.py times (binary16 f and g with the learned curvature; binary32 with
+  the plain fit), 40 steps;
+* the 128^3 binary32 foam with 32 nuclei and disjoining pressure, its full 5000 steps;
+* the 256^3 foam with 500 nuclei and the learned curvature (binary32), 1000 steps.
+
+The properties:
 
 * liquid mass (populations of liquid cells plus M of interface cells, plus the lost-liquid
-  ledger) conserved to 1e-6 relative;
+  ledger) conserved to 1e-6 relative (1e-5 over the runs of 1000 steps and more);
 * the ideal-gas law p = m RT / max(V, 1/2) on every bubble (binary64 table, 1e-12);
 * every bubble's volume equal to the sum over its cells of 1 - alpha (gas cells 1), summed
   on the host from the label and fill-fraction fields read back (1e-6 relative);
@@ -36,11 +42,16 @@ def _liquid(sim):
     return rho_l + M[T == 1].sum() + sim.ledgers()["lost_liquid"]
 
 
-@pytest.mark.parametrize("prec,curv", [("f16s_g16", "mlp"), ("fp32", "plain")])
-def test_full_size_foam_properties(prec, curv):
+@pytest.mark.parametrize("name,prec,curv,steps,min_bubbles", [
+    ("c3_foam_384", "f16s_g16", "mlp", 40, 1500),
+    ("c3_foam_384", "fp32", "plain", 40, 1500),
+    ("c2_3d_128", "fp32", "plain", 5000, 1),
+    ("c4_foam_256", "fp32", "mlp", 1000, 100),
+])
+def test_full_size_foam_properties(name, prec, curv, steps, min_bubbles):
     from paper_1908_04262_amd import CurvatureNet, Sim
-    wl = workload("c3_foam_384", precision=prec, curvature=curv)
-    _say(f"full size {prec}/{curv}: create and nucleate")
+    wl = workload(name, precision=prec, curvature=curv)
+    _say(f"full size {name} {prec}/{curv}: create and nucleate")
     sim = Sim(wl)
     if curv == "mlp":
         net = CurvatureNet(5)
@@ -48,21 +59,21 @@ def test_full_size_foam_properties(prec, curv):
         sim.attach_mlp(net)
     sim.nucleate(*place_nuclei(wl))
     m0 = _liquid(sim)
-    _say(f"full size {prec}/{curv}: 40 steps")
-    sim.step(40)
+    _say(f"full size {name} {prec}/{curv}: {steps} steps")
+    sim.step(steps)
     sim.sync()
     m1 = _liquid(sim)
-    assert abs(m1 - m0) / m0 < 1e-6, (m0, m1)
+    assert abs(m1 - m0) / m0 < (1e-6 if steps < 1000 else 1e-5), (m0, m1)
 
     b = sim.bubbles()
     ids, V, m, p = b["id"], b["V"], b["m"], b["p"]
     live = ids > 0
-    assert live.sum() > 1500
+    assert live.sum() >= min_bubbles
     RT = wl["RT"]
     want_p = m[live] * RT / np.maximum(V[live], 0.5)
     assert np.allclose(p[live], want_p, rtol=1e-12, atol=0)
 
-    _say(f"full size {prec}/{curv}: volumes and components from the fields")
+    _say(f"full size {name} {prec}/{curv}: volumes and components from the fields")
     T = sim.read("type")
     lab = sim.read("label")
     al = sim.read("alpha")
@@ -82,5 +93,7 @@ def test_full_size_foam_properties(prec, curv):
     bubbles_only = ids_of[ids_of > 0]
     assert len(np.unique(bubbles_only)) == len(bubbles_only), "two components share a bubble id"
     assert set(bubbles_only.tolist()) == set(ids[live].tolist())
-    _say(f"full size {prec}/{curv}: {nc} components, {live.sum()} bubbles, mass drift {abs(m1 - m0) / m0:.2e}")
+    npi = int(np.count_nonzero(sim.read("pi"))) if wl.get("k_pi", 0.0) > 0.0 else 0
+    _say(f"full size {name} {prec}/{curv}: {nc} components, {live.sum()} bubbles, "
+         f"mass drift {abs(m1 - m0) / m0:.2e}, {npi} cells with disjoining pressure")
     sim.close()
