@@ -248,6 +248,23 @@ KP make_kp(const mf_params &P) {
   k.cy_n = P.cy_n;
   k.cy_lk = (float)(P.cy_lambda * 2.1213203435596424);
   k.cy_m = (float)((P.cy_n - 1.0) / (P.cy_a > 0.0 ? P.cy_a : 1.0));
+  k.omega_f = (float)k.omega;
+  k.omega_g_f = (float)k.omega_g;
+  k.pl_n_f = (float)k.pl_n;
+  k.tau_min_f = (float)k.tau_min;
+  k.tau_max_f = (float)k.tau_max;
+  k.c0_f = (float)k.c0;
+  k.q_f = (float)k.q;
+  k.c0g_f = k.c0_f * k.ginv;
+  k.qg_f = k.q_f * k.ginv;
+  k.cy_tau0_f = (float)k.cy_tau0;
+  k.cy_tau_inf_f = (float)k.cy_tau_inf;
+  k.cy_a_f = (float)k.cy_a;
+  k.cy_w_f = (k.cy_tau0_f - k.cy_tau_inf_f) * (1.0f - (float)k.cy_n);
+  k.pl_ninv = P.pl_n > 0.0 ? (float)(1.0 / P.pl_n) : 1.0f;
+  // iterations for a relative error of tau below 3e-7, from the measured convergence of
+  // the bounded start
+  k.pl_nit = (P.pl_n >= 0.3 && P.pl_n <= 3.0) ? 3 : 5;
   k.ax = P.accel[0];
   k.ay = P.accel[1];
   k.az = P.dim == 3 ? P.accel[2] : 0.0;

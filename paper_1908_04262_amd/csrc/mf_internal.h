@@ -153,6 +153,14 @@ struct KP {
   int flux_paper;   // gas flux of Eq. gascurrent as printed instead of the ledger
   double ax, ay, az;
   float fax, fay, faz;
+  // binary32 copies of the parameters the binary32 collision reads, rounded once on the
+  // host: a binary64 argument converted inside a kernel costs a vector instruction at
+  // every use
+  float omega_f, omega_g_f, pl_n_f, tau_min_f, tau_max_f;
+  float c0_f, q_f, c0g_f, qg_f;               // c0 and q, and both times 1/s_g (instance 4)
+  float cy_tau0_f, cy_tau_inf_f, cy_a_f, cy_w_f;  // Carreau-Yasuda; w = (tau0 - tau_inf)(1 - n)
+  float pl_ninv;                              // 1 / n (power law)
+  int pl_nit;              // Newton iterations of the binary32 power-law tau
 };
 
 struct DA {
