@@ -1,6 +1,7 @@
 """GPU parity on the paths that only some states reach: disjoining pressure on thin
 lamellae (Sec. 3.3, Eq. rhobplusdisjoining, Appendix A Algorithm 1), bubble merge,
-split, burst into the headspace and collapse (Sec. 3.5), and a 1000-step 3D run.
+split, burst into the headspace and collapse (Sec. 3.5), a 1000-step 3D run, and the
+partial relabelling of a time step against a full relabelling of the same state.
 
 Binary64 throughout, through the C ABI, against the FP64 oracle on the same nuclei:
 cell types and bubble labels bit-exact and the bubble table and ledgers within 1e-12
@@ -146,3 +147,48 @@ def test_fp64_parity_3d_1000_steps():
         compare_bubbles(gpu, orc, 1e-12)
         _say(f"  step {100 * (k + 1)}: f {out['f']:.2e} kappa {out['kappa']:.2e} pi {out['pi']:.2e}")
     assert len(orc.bubbles()["id"]) < n0
+
+
+@pytest.mark.parametrize("case,prec,steps,every", [
+    ("neck3d", "fp64", 30, 3),
+    ("burst3d", "fp64", 90, 15),
+    ("dissolve3d", "fp64", 150, 25),
+    ("neck3d", "f16s_g16", 30, 3),
+    ("burst3d", "f16s_g16", 90, 15),
+])
+def test_partial_relabelling_equals_full(case, prec, steps, every):
+    """A time step relabels only the components its conversions may have changed (the ids
+    the topology test marks) and updates every other bubble on the fast path. The state it
+    leaves must be the one a full relabelling of the same cells gives: at every checkpoint
+    the run is relabelled from scratch (mf_refresh with relabel, which lists every gas and
+    interface cell and applies no flux), and the bubble ids of every cell and the bubble
+    table (volume, gas, pressure, alive flags) must come out unchanged, bit for bit."""
+    from paper_1908_04262_amd import Sim
+    wl = small_case(case, precision=prec)
+    sim = Sim(wl)
+    sim.nucleate(*place_nuclei(wl))
+    done, events = 0, 0
+    ids_before = None
+    while done < steps:
+        sim.step(every)
+        done += every
+        lab = sim.read("label")
+        b = sim.bubbles()
+        led = sim.ledgers()
+        ids = set(b["id"].tolist())
+        if ids_before is not None and ids != ids_before:
+            events += 1
+        ids_before = ids
+        sim.refresh(relabel=True)
+        assert np.array_equal(sim.read("label"), lab), f"{case} step {done}: ids differ"
+        b2 = sim.bubbles()
+        for k in ("id", "V", "m", "p"):
+            assert np.array_equal(b[k], b2[k]), (case, done, k)
+        led2 = sim.ledgers()
+        for k in ("n_bubbles", "next_id", "atm_gas", "collapsed_gas", "lost_liquid"):
+            assert led2[k] == led[k], (case, done, k, led[k], led2[k])
+        assert led2["status"] == 0
+    _say(f"partial relabelling {case} {prec}: {steps} steps, bubble set changed between "
+         f"{events} of {steps // every - 1} checkpoints")
+    assert events >= 1, "the run has no topology event"
+    sim.close()
