@@ -183,7 +183,7 @@ def late_window(sim, wl, until, steps, log):
                special_sweep_ms=round(spec_ms / max(nsw, 1), 4),
                interface_fraction=round(float(np.count_nonzero(T == 1)) / ncell, 5),
                gas_fraction=round(float(np.count_nonzero(T == 0)) / ncell, 5),
-               n_bubbles=led["n_bubbles"], advance_seconds=round(adv, 2))
+               n_bubbles=led["n_bubbles"], advance_seconds=round(adv, 2), status=led["status"])
     log(f"[{wl['precision']}] late state {json.dumps(out)}")
     return out
 
@@ -500,7 +500,7 @@ def main():
                 "bulk_sweep_gbs": round(r["bulk_sweep_gbs"], 1),
                 "bulk_sweep_ms": round(r["bulk_sweep_ms"], 4),
                 "special_sweep_ms": round(r["special_sweep_ms"], 4),
-                "bulk_variant": r["bulk_variant"]}
+                "bulk_variant": r["bulk_variant"], "status": r["status"]}
 
     out = {
         "metric": METRIC,
@@ -525,6 +525,7 @@ def main():
         },
         "mlp_training": train_info,
         "hbm_frac_step": round(r16["hbm_frac_step"], 4),
+        "status": r16["status"],
         "fp32_plain": brief(r32),
         "f16_f_only_mlp": brief(r16f),
         "body_force": dict(brief(r16g), accel=list(grav), steps=max(a.steps // 2, 1)),
