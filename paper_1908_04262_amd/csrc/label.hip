@@ -429,9 +429,9 @@ __global__ __launch_bounds__(1024) void k_bubble_update(KP p, DA d, int apply_fl
   b_bubble_update(GridPos::hw(), p, d, apply_flux);
 }
 
-// new ids onto every cell from its root, the gas cells of every bubble counted under the
-// new ids (kept up to date by the conversions on the steps that do not relabel), and the
-// labelling flags cleared
+// new ids onto every listed cell from its root, the gas cells of every relabelled bubble
+// counted under the new ids (the conversions keep the counts of the others up to date), and
+// the labelling flags cleared
 template <int P>
 __device__ __forceinline__ void b_ccl_relabel(const GridPos &gp, KP p, DA d) {
   using R = typename Prec<P>::R;
@@ -575,8 +575,9 @@ void Ops<D, P>::label_multi(const MStep &ms, hipStream_t s) {
 template <int D, int P>
 void Ops<D, P>::label(Ctx &c, hipStream_t s, int apply_flux) {
   const unsigned nb = list_blocks(c);
-  // the relabelling kernels return at once on most steps: a smaller grid keeps those
-  // launches cheap, and their grid-stride loops cover the list when they do run
+  // the relabelling kernels return at once on steps without topology change and list few
+  // cells on the others: a smaller grid keeps those launches cheap, and their grid-stride
+  // loops cover the list when it is long
   const unsigned nf = nb < 1024 ? nb : 1024;
   if (!apply_flux) hipLaunchKernelGGL(k_force_full, dim3(1), dim3(1), 0, s, c.d);
   hipLaunchKernelGGL(k_bubble_fast, dim3((unsigned)((c.kp.cap + 255) / 256 < 64 ? (c.kp.cap + 255) / 256 : 64)), dim3(256), 0, s, c.kp, c.d);
