@@ -394,9 +394,11 @@ int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launch
 
 /* Time every applicable variant of the bulk sweep on the context's current state (reps
  * launches each; the kernel writes only the spare population buffer, so the state is not
- * changed), select the fastest of those with 256-thread work-groups (0, 1, 4: inside a
- * step the bulk kernel shares the GPU with the labelling and curvature kernels, which
- * one-wave work-groups starve) for later steps and return it in *best_variant (-1 when
+ * changed), select one of those with 256-thread work-groups (0, 1, 4: inside a step the
+ * bulk kernel shares the GPU with the labelling and curvature kernels, which one-wave
+ * work-groups starve) for later steps: the default shape (4 for 16-bit storage, 0 for
+ * binary32), unless another is more than 5% faster alone, then the fastest; inside a step
+ * the default runs faster than shapes that tie with it alone. Return it in *best_variant (-1 when
  * none applies: binary64, periodic axes, or rows that are not a multiple of the vector
  * width). ms_per_variant (MF_SWEEP_VARIANTS floats, nullable) receives the mean time per
  * launch of every variant, -1 for variants that do not apply. Synchronises the context

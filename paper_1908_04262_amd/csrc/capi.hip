@@ -638,8 +638,7 @@ int mf_tune(mf_ctx *c, int32_t reps, int32_t *best, float *ms) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  int bv = -1;
-  float bt = 0.0f;
+  float tv[kNumSweepVariants];
   for (int v = 0; v < kNumSweepVariants; ++v) {
     float t = -1.0f;
     // the bulk kernel writes only the other population buffer: timing it changes no state
@@ -655,13 +654,28 @@ int mf_tune(mf_ctx *c, int32_t reps, int32_t *best, float *ms) {
         HIPCHK(c, e);
       }
       t /= (float)reps;
-      if (step_variant(v) && (bv < 0 || t < bt)) { bv = v; bt = t; }
     }
+    tv[v] = t;
     if (ms) ms[v] = t;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHK(c, hipGetLastError());
+  // The default shape stays unless another 256-thread shape is faster alone by more than
+  // kTuneMargin. Launched alone, four and eight cells per thread come within 1% of each
+  // other on 16-bit storage, and noise would pick either; inside a step, beside the
+  // labelling and curvature kernels, four cells per thread (four waves per SIMD) delay
+  // those kernels until the bulk sweep ends, and the step takes 4% (early foam) to 10% (the
+  // grown foam) longer.
+  constexpr float kTuneMargin = 0.05f;
+  int bv = effective_sweep_variant(c->kp, c->P.precision, -1);
+  if (bv >= 0 && (!step_variant(bv) || tv[bv] < 0.0f)) bv = -1;
+  float bt = bv >= 0 ? tv[bv] * (1.0f - kTuneMargin) : 0.0f;
+  for (int v = 0; v < kNumSweepVariants; ++v)
+    if (v != bv && step_variant(v) && tv[v] >= 0.0f && (bv < 0 || tv[v] < bt)) {
+      bv = v;
+      bt = tv[v];
+    }
   c->sweep_variant = bv;  // -1 when no variant applies (per-cell sweep)
   c->epoch++;
   *best = bv;

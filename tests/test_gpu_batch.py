@@ -112,9 +112,11 @@ def test_tuner_picks_a_variant():
             _make(small_case("c1_small", precision="fp64"))]
     best, ms = sims[0].tune(3)
     _say("tuner:", best, ms)
-    # a context chooses among the 256-thread work-group shapes (0, 1, 4)
+    # a context chooses among the 256-thread work-group shapes (0, 1, 4): the default (8
+    # cells per thread for 16-bit storage) unless another is more than 5% faster alone
     assert best in (0, 1, 4) and ms[best] > 0
-    assert ms[best] == min(ms[v] for v in (0, 1, 4) if ms[v] > 0)
+    faster = [v for v in (0, 1) if 0 < ms[v] < ms[4] * 0.95]
+    assert best == (min(faster, key=lambda v: ms[v]) if faster else 4)
     batch = Batch(sims)
     v = batch.tune(3)
     assert v[0] == v[1] and v[0] >= 0 and v[2] == -1
