@@ -16,7 +16,8 @@ metric's workload itself is a power-law liquid without body force.
 
 A third measurement covers the batched ensemble (48 independent domains of 64^3 to 160^3,
 binary16 storage, learned curvature): MLUPS over all domains stepped one after another,
-and with the tuned bulk sweep and one graph launch per two steps of all domains.
+and with the tuned bulk sweep and one launch per kernel for all domains, overlapped as in
+a single domain's step.
 
 The roofline entry is the bulk sweep kernel: algorithmic bytes per launch over its
 average duration inside the timed steps, measured with events on its stream; there it
@@ -270,7 +271,7 @@ def run_one(wl, steps, warmup, log, net=None, late_steps=0):
 def run_ensemble(net, steps, log, until=0):
     """The batched ensemble (48 domains of 64^3..160^3, binary16 storage, learned
     curvature): MLUPS over all domains when every domain is stepped in turn, and with the
-    tuned bulk sweep and one graph launch per two steps for all domains."""
+    tuned bulk sweep and one launch per kernel for all domains."""
     import numpy as np
     import torch
 
@@ -331,7 +332,7 @@ def run_ensemble(net, steps, log, until=0):
         log(f"[ensemble] {left} more batched steps to step {long['steps_per_domain']}: "
             f"{long['mlups_batched']} MLUPS, {json.dumps(long)}")
     st = [s.ledgers()["status"] for s in sims]
-    log(f"[ensemble] sequential {seq:.0f} MLUPS, batched graph {bat:.0f} MLUPS, variants "
+    log(f"[ensemble] sequential {seq:.0f} MLUPS, batched {bat:.0f} MLUPS, variants "
         f"{dict(zip(*np.unique(variants, return_counts=True)))}")
     batch.close()
     for s in sims:

@@ -384,7 +384,8 @@ int mf_profile_get(mf_ctx *ctx, int32_t group, double *ms_total, int64_t *launch
 
 /* ---------------------------------------------------------------- tuning, batching
  * Production forms beyond the paper: a tuner for the launch shape of the bulk lattice
- * sweep, and the advance of many independent domains by one graph launch per two steps.
+ * sweep, and the advance of many independent domains with one launch per kernel for all
+ * of them.
  */
 
 /* Number of launch variants of the bulk lattice sweep (cells per thread x threads per
@@ -427,13 +428,14 @@ int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants);
  * (dimension, storage, bulk or per-cell sweep, body force, learned curvature; at most 64
  * per group), and every kernel of a step runs as one launch for all domains of a group:
  * each domain takes its range of the launch's work-groups, and each work-group finds its
- * domain by a binary search over the ranges passed with the launch. Pairs of steps run as
- * one launch of a graph that holds two steps of all groups (a branch per group); the
- * graph is captured on first use and again after any state change made outside the time
- * step (nucleation, field writes, refresh, network attachment, tuning) or after an odd
- * step count, which runs outside the graph. Results are those of mf_step on each context,
- * bit for bit. Work already queued on the contexts' streams runs first, and later work
- * queued there waits for the batch. Profiling must be off (MF_ESTATE). */
+ * domain by a binary search over the ranges passed with the launch. Each group has two
+ * streams of its own: as in mf_step, the second half of a step's conversions, the labelling
+ * and the geometry run beside the next step's bulk sweep. The per-domain tables are built
+ * on first use and again after any state change made outside the time step (nucleation,
+ * field writes, refresh, network attachment, tuning) or when the domains' buffer parities
+ * no longer agree (a domain stepped alone by an odd count). Results are those of mf_step
+ * on each context, bit for bit. Work already queued on the contexts' streams runs first,
+ * and later work queued there waits for the batch. Profiling must be off (MF_ESTATE). */
 int mf_batch_step(mf_batch *b, int32_t nsteps);
 
 /* Wait for the batch stream and free the batch (not the contexts). */

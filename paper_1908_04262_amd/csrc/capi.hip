@@ -42,8 +42,8 @@ struct OpsTable {
   void (*totals)(Ctx &, hipStream_t);
   void (*bubble_stats)(Ctx &, hipStream_t);
   void (*poke)(Ctx &, hipStream_t, int, int64_t, int, double);
-  void (*sweep_multi)(const MStep &, unsigned, bool, bool, hipStream_t);
-  void (*convert_multi)(const MStep &, hipStream_t);
+  void (*sweep_multi)(const MStep &, unsigned, bool, bool, int, hipStream_t);
+  void (*convert_multi)(const MStep &, int, hipStream_t);
   void (*label_multi)(const MStep &, hipStream_t);
   void (*geometry_multi)(const MStep &, bool, hipStream_t);
   void (*bulk_multi)(const MStep &, int, bool, hipStream_t);
@@ -536,8 +536,8 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
   return device_status(c);
 }
 
-// one time step, enqueued on the context stream (host work: launches only, so that it
-// can be captured into a graph); ev: kStepEvents profiling events or NULL.
+// one time step, enqueued on the context stream (host work: launches only); ev:
+// kStepEvents profiling events or NULL.
 // With overlap, a step runs on three streams of the context (see Ctx). The context stream
 // takes the bulk sweep, the interface sweep and the first half of the conversions. After
 // that, the side stream takes their second half, the labelling and the curvature, and
@@ -546,8 +546,7 @@ int mf_nucleate(mf_ctx *c, int32_t n, const double *centers, const double *radii
 // all of that. The interface sweep, the first kernel that reads ids, bubble pressures,
 // curvature and the new list, waits for both side streams. The caller joins what the last
 // step left running (join_side) before anything else touches the state. A step whose
-// stencil words need the whole-grid pass, and graph capture (where the domains already
-// run as parallel branches), take the plain order.
+// stencil words need the whole-grid pass takes the plain order.
 static void step_once(mf_ctx *c, hipEvent_t *ev, bool overlap) {
   c->parity ^= 1;
   select_parity(c);
@@ -1092,9 +1091,9 @@ int mf_profile_get(mf_ctx *c, int32_t group, double *ms_total, int64_t *launches
 // per-cell or bulk sweep, body force, learned curvature). Every kernel of a step runs as
 // one launch for all domains of a group: each domain takes the work-groups it would take
 // alone, and each work-group finds its domain from a table of per-domain parameters and
-// arrays (MDom) and a prefix sum of work-group counts per launch kind. Two steps of all
-// groups are captured into one graph (a branch per group); the results are those of
-// mf_step on each context, bit for bit.
+// arrays (MDom) and a prefix sum of work-group counts per launch kind. A group swept by the
+// bulk kernel runs its steps on two streams, overlapped as a single domain's step; the
+// results are those of mf_step on each context, bit for bit.
 struct BatchGroup {
   std::vector<int> idx;  // domains of the batch in this group
   OpsTable ops;
@@ -1103,28 +1102,27 @@ struct BatchGroup {
   unsigned vmask = 0;        // bulk launch shapes used by the group's domains
   int grid[MK_COUNT] = {};   // work-groups of each launch kind over the group
   std::vector<int> pre;      // [MK_COUNT][nd + 1] work-group prefix sums
-  MDom *dom_dev[2] = {nullptr, nullptr};  // the two steps of a captured pair
+  MDom *dom_dev[2] = {nullptr, nullptr};  // tables of the two buffer parities
   hipStream_t stream = nullptr;
   hipEvent_t ev_join = nullptr;
+  // the second stream of a group swept by the bulk kernel, and the events that order the two
+  hipStream_t side = nullptr;
+  hipEvent_t ev_conv = nullptr, ev_side = nullptr;
 };
 
 struct mf_batch {
   std::vector<mf_ctx *> ctx;
-  hipStream_t sb = nullptr;  // the batch stream (graph launches)
+  hipStream_t sb = nullptr;  // the batch stream: the groups fork from and join into it
   hipEvent_t ev_fork = nullptr, ev_out = nullptr;
   std::vector<hipEvent_t> ev_in;
   std::vector<BatchGroup> groups;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  std::vector<uint64_t> epoch;  // context epochs and buffer parities at capture
+  bool ready = false;           // groups and tables built
+  std::vector<uint64_t> epoch;  // context epochs and buffer parities when the tables were built
   std::vector<int> cur, par;
 };
 
-static void batch_drop_graph(mf_batch *b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+static void batch_drop_tables(mf_batch *b) {
+  b->ready = false;
   for (BatchGroup &g : b->groups) {
     for (int j = 0; j < 2; ++j) {
       if (g.dom_dev[j]) (void)hipFree(g.dom_dev[j]);
@@ -1137,6 +1135,9 @@ static void batch_free_groups(mf_batch *b) {
   for (BatchGroup &g : b->groups) {
     if (g.stream) (void)hipStreamDestroy(g.stream);
     if (g.ev_join) (void)hipEventDestroy(g.ev_join);
+    if (g.side) (void)hipStreamDestroy(g.side);
+    if (g.ev_conv) (void)hipEventDestroy(g.ev_conv);
+    if (g.ev_side) (void)hipEventDestroy(g.ev_side);
   }
   b->groups.clear();
 }
@@ -1207,6 +1208,9 @@ static hipError_t batch_group(mf_batch *b) {
       g->mlp = mlp;
       hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_conv, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_side, hipEventDisableTiming);
       if (e != hipSuccess) return e;
     }
     g->idx.push_back((int)i);
@@ -1215,8 +1219,8 @@ static hipError_t batch_group(mf_batch *b) {
   return hipSuccess;
 }
 
-// the per-domain tables of each group for the two steps of a pair, from the contexts'
-// current buffer parities
+// the per-domain tables of each group for a step from the contexts' current buffer
+// parities (table 0) and for the step after it (table 1)
 static hipError_t batch_tables(mf_batch *b) {
   for (BatchGroup &g : b->groups) {
     const int nd = (int)g.idx.size();
@@ -1250,19 +1254,59 @@ static hipError_t batch_tables(mf_batch *b) {
   return hipSuccess;
 }
 
-// one time step of every domain of a group, as batched launches on stream s
-static void group_step(const BatchGroup &g, int j, hipStream_t s) {
+static MStep group_mstep(const BatchGroup &g, int j) {
   MStep ms;
   ms.dom = g.dom_dev[j];
   ms.nd = (int)g.idx.size();
   ms.pre = g.pre.data();
   ms.grid = g.grid;
+  return ms;
+}
+
+// one time step of every domain of a group, as batched launches on stream s, in order
+static void group_step(const BatchGroup &g, int j, hipStream_t s) {
+  const MStep ms = group_mstep(g, j);
   reset_multi(ms, s);
   lists_multi(ms, 0, s);
-  g.ops.sweep_multi(ms, g.vmask, g.cells, g.frc, s);
-  g.ops.convert_multi(ms, s);
+  g.ops.sweep_multi(ms, g.vmask, g.cells, g.frc, 0, s);
+  g.ops.convert_multi(ms, 0, s);
   g.ops.label_multi(ms, s);
   g.ops.geometry_multi(ms, g.mlp, s);
+}
+
+// n time steps of a group swept by the bulk kernel, the first with table phase, on two
+// streams as a single domain's
+// step: the group stream takes the bulk sweep, the interface sweep and the first half of
+// the conversions; the side stream then takes their second half, the labelling, the
+// geometry and the next step's counter reset and interface list, beside the next bulk
+// sweep (which reads only types, populations and wall masks); the next interface sweep
+// waits for the side stream.
+static void group_steps_overlapped(const BatchGroup &g, int phase, int n) {
+  hipStream_t m = g.stream, sd = g.side;
+  {
+    const MStep ms0 = group_mstep(g, phase);
+    reset_multi(ms0, m);
+    lists_multi(ms0, 0, m);
+  }
+  for (int t = 0; t < n; ++t) {
+    const MStep ms = group_mstep(g, (phase + t) & 1);
+    g.ops.sweep_multi(ms, g.vmask, false, g.frc, 1, m);
+    if (t > 0) (void)hipStreamWaitEvent(m, g.ev_side, 0);
+    g.ops.sweep_multi(ms, g.vmask, false, g.frc, 2, m);
+    g.ops.convert_multi(ms, 1, m);
+    (void)hipEventRecord(g.ev_conv, m);
+    (void)hipStreamWaitEvent(sd, g.ev_conv, 0);
+    g.ops.convert_multi(ms, 2, sd);
+    g.ops.label_multi(ms, sd);
+    g.ops.geometry_multi(ms, g.mlp, sd);
+    if (t + 1 < n) {
+      const MStep mn = group_mstep(g, (phase + t + 1) & 1);
+      reset_multi(mn, sd);
+      lists_multi(mn, 0, sd);
+    }
+    (void)hipEventRecord(g.ev_side, sd);
+  }
+  (void)hipStreamWaitEvent(m, g.ev_side, 0);
 }
 
 int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out) {
@@ -1290,7 +1334,7 @@ int mf_batch_create(int32_t n, mf_ctx *const *ctxs, mf_batch **out) {
 int mf_batch_destroy(mf_batch *b) {
   if (!b) return MF_EINVAL;
   if (b->sb) (void)hipStreamSynchronize(b->sb);
-  batch_drop_graph(b);
+  batch_drop_tables(b);
   batch_free_groups(b);
   for (hipEvent_t e : b->ev_in)
     if (e) (void)hipEventDestroy(e);
@@ -1301,36 +1345,11 @@ int mf_batch_destroy(mf_batch *b) {
   return MF_OK;
 }
 
-// two time steps of every domain as one graph: each group's batched launches on its own
-// branch, forked from and joined back into the batch stream
-static hipError_t batch_capture(mf_batch *b) {
-  for (mf_ctx *c : b->ctx)
-    if (c->sword_dirty || c->gas_dirty) c->ops.geometry(*c, b->sb);  // idempotent
+// the groups and their tables for the contexts' current state
+static hipError_t batch_prepare(mf_batch *b) {
   hipError_t e = batch_group(b);
   if (e == hipSuccess) e = batch_tables(b);
   if (e != hipSuccess) return e;
-  e = hipStreamBeginCapture(b->sb, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return e;
-  (void)hipEventRecord(b->ev_fork, b->sb);
-  for (BatchGroup &g : b->groups) {
-    (void)hipStreamWaitEvent(g.stream, b->ev_fork, 0);
-    group_step(g, 0, g.stream);
-    group_step(g, 1, g.stream);
-    (void)hipEventRecord(g.ev_join, g.stream);
-    (void)hipStreamWaitEvent(b->sb, g.ev_join, 0);
-  }
-  hipGraph_t gr = nullptr;
-  e = hipStreamEndCapture(b->sb, &gr);
-  if (e != hipSuccess) {
-    if (gr) (void)hipGraphDestroy(gr);
-    return e;
-  }
-  b->graph = gr;
-  e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    batch_drop_graph(b);
-    return e;
-  }
   b->epoch.resize(b->ctx.size());
   b->cur.resize(b->ctx.size());
   b->par.resize(b->ctx.size());
@@ -1339,6 +1358,7 @@ static hipError_t batch_capture(mf_batch *b) {
     b->cur[i] = b->ctx[i]->cur;
     b->par[i] = b->ctx[i]->parity;
   }
+  b->ready = true;
   return hipSuccess;
 }
 
@@ -1348,46 +1368,54 @@ int mf_batch_step(mf_batch *b, int32_t nsteps) {
     if (c->kp.curvature == MF_CURV_MLP && !c->d.mlp_w) return batch_fail("a domain uses the learned curvature without a network", hipSuccess);
     if (c->prof) return batch_fail("profiling is not available in batched steps", hipSuccess);
   }
-  // a graph captured before a state change made outside the time step is rebuilt
-  bool stale = b->exec == nullptr;
-  for (size_t i = 0; i < b->ctx.size() && !stale; ++i)
-    stale = b->epoch[i] != b->ctx[i]->epoch || b->cur[i] != b->ctx[i]->cur || b->par[i] != b->ctx[i]->parity;
+  if (nsteps == 0) return MF_OK;
+  // Tables built before a state change made outside the time step are rebuilt. Every
+  // step flips a context's population buffer and counter parity, so the table of the
+  // next step is the one whose buffer matches; all contexts must agree on it.
+  bool stale = !b->ready;
+  int phase = -1;
+  for (size_t i = 0; i < b->ctx.size() && !stale; ++i) {
+    const mf_ctx *c = b->ctx[i];
+    const int ph = c->cur ^ b->cur[i];
+    stale = b->epoch[i] != c->epoch || (c->parity ^ b->par[i]) != ph || (phase >= 0 && ph != phase);
+    phase = ph;
+  }
   // the batch waits for the work already queued on the domains' own streams
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     join_side(b->ctx[i]);
     (void)hipEventRecord(b->ev_in[i], b->ctx[i]->stream);
     (void)hipStreamWaitEvent(b->sb, b->ev_in[i], 0);
   }
-  const int pairs = nsteps / 2;
-  if (pairs > 0) {
-    if (stale) {
-      // the tables of a graph in flight stay allocated until the batch stream is idle
-      (void)hipStreamSynchronize(b->sb);
-      batch_drop_graph(b);
-      const hipError_t e = batch_capture(b);
-      if (e != hipSuccess) return batch_fail("capturing the batched step failed", e);
-    }
-    for (int k = 0; k < pairs; ++k) {
-      const hipError_t e = hipGraphLaunch(b->exec, b->sb);
-      if (e != hipSuccess) return batch_fail("launching the batched step failed", e);
-    }
-    for (mf_ctx *c : b->ctx) {
-      c->step += 2 * pairs;
-      c->gas_dirty = false;
-      c->sword_fresh = false;
-    }
+  if (stale) {
+    // tables in use stay allocated until the batch stream is idle
+    HIPCHK_B(hipStreamSynchronize(b->sb));
+    batch_drop_tables(b);
+    HIPCHK_B(batch_prepare(b));
+    phase = 0;
   }
-  if (nsteps & 1) {
-    // an odd step runs outside the graph (and flips the buffer parity the graph expects)
-    for (mf_ctx *c : b->ctx) {
-      hipStream_t own = c->stream;
-      c->stream = b->sb;
-      if (c->gas_dirty) c->ops.geometry(*c, c->stream);
-      step_once(c, nullptr, false);
-      c->stream = own;
+  for (mf_ctx *c : b->ctx)
+    if (c->sword_dirty || c->gas_dirty) c->ops.geometry(*c, b->sb);  // idempotent
+  (void)hipEventRecord(b->ev_fork, b->sb);
+  for (BatchGroup &g : b->groups) {
+    (void)hipStreamWaitEvent(g.stream, b->ev_fork, 0);
+    if (g.cells) {
+      for (int t = 0; t < nsteps; ++t) group_step(g, (phase + t) & 1, g.stream);
+    } else {
+      (void)hipStreamWaitEvent(g.side, b->ev_fork, 0);
+      group_steps_overlapped(g, phase, nsteps);
     }
+    (void)hipEventRecord(g.ev_join, g.stream);
+    (void)hipStreamWaitEvent(b->sb, g.ev_join, 0);
   }
-  for (mf_ctx *c : b->ctx) c->stepped = c->stepped || nsteps > 0;
+  for (mf_ctx *c : b->ctx) {
+    c->step += nsteps;
+    c->cur ^= nsteps & 1;
+    c->parity ^= nsteps & 1;
+    select_parity(c);
+    c->gas_dirty = false;
+    c->sword_fresh = false;
+    c->stepped = true;
+  }
   // the domains' own streams wait for the batch
   (void)hipEventRecord(b->ev_out, b->sb);
   for (mf_ctx *c : b->ctx) (void)hipStreamWaitEvent(c->stream, b->ev_out, 0);
@@ -1406,7 +1434,7 @@ int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants) {
     join_side(c);
     HIPCHK_B(hipStreamSynchronize(c->stream));
   }
-  batch_drop_graph(b);
+  batch_drop_tables(b);
   HIPCHK_B(batch_group(b));
   HIPCHK_B(batch_tables(b));
   hipEvent_t e0, e1;
@@ -1428,10 +1456,10 @@ int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants) {
           done[k] = 1;
         }
       }
-      int best = -1;
-      float bt = 0.0f;
+      float tv[kNumSweepVariants];
+      for (int v = 0; v < kNumSweepVariants; ++v) tv[v] = -1.0f;
       for (int v = 0; v < kNumSweepVariants && rc == MF_OK; ++v) {
-        if (!bulk_shape_ok(ci->kp, ci->P.precision, kSweepVariants[v].vw)) continue;
+        if (!step_variant(v) || !bulk_shape_ok(ci->kp, ci->P.precision, kSweepVariants[v].vw)) continue;
         // the class's domains only, in shape v
         std::vector<int> pre((size_t)MK_COUNT * (nd + 1), 0);
         const int kind = MK_BULK0 + v;
@@ -1458,11 +1486,18 @@ int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants) {
           rc = batch_fail("timing the batched bulk sweep failed", e);
           break;
         }
-        if (best < 0 || ms_t < bt) {
-          best = v;
-          bt = ms_t;
-        }
+        tv[v] = ms_t;
       }
+      // as for a single context: the default shape unless another 256-thread shape is more
+      // than 5% faster alone (inside an overlapped step the shapes that tie alone do not)
+      int best = effective_sweep_variant(ci->kp, ci->P.precision, -1);
+      if (best >= 0 && tv[best] < 0.0f) best = -1;
+      float bt = best >= 0 ? tv[best] * 0.95f : 0.0f;
+      for (int v = 0; v < kNumSweepVariants; ++v)
+        if (v != best && tv[v] >= 0.0f && (best < 0 || tv[v] < bt)) {
+          best = v;
+          bt = tv[v];
+        }
       for (int k : cls) {
         mf_ctx *c = b->ctx[g.idx[k]];
         c->sweep_variant = best;
@@ -1472,7 +1507,7 @@ int mf_batch_tune(mf_batch *b, int32_t reps, int32_t *variants) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  batch_drop_graph(b);  // the graph is captured again with the chosen shapes
+  batch_drop_tables(b);  // the tables are built again with the chosen shapes
   if (rc) return rc;
   for (size_t i = 0; i < b->ctx.size(); ++i)
     if (variants) variants[i] = b->ctx[i]->sweep_variant;

@@ -647,11 +647,14 @@ __global__ __launch_bounds__(256) void km_conv_clear(MLaunch ml) {
 // the conversions of every domain of a batch (after its sweep: the post-collision
 // populations are in buffer cur ^ 1), in the order of convert()
 template <int D, int P>
-void Ops<D, P>::convert_multi(const MStep &ms, hipStream_t s) {
-  hipLaunchKernelGGL((km_fill_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
-  hipLaunchKernelGGL((km_empty_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
-  hipLaunchKernelGGL((km_apply<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
-  hipLaunchKernelGGL((km_ni_init<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+void Ops<D, P>::convert_multi(const MStep &ms, int part, hipStream_t s) {
+  if (part != 2) {
+    hipLaunchKernelGGL((km_fill_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+    hipLaunchKernelGGL((km_empty_scatter<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+    hipLaunchKernelGGL((km_apply<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+    hipLaunchKernelGGL((km_ni_init<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
+  }
+  if (part == 1) return;
   hipLaunchKernelGGL((km_topo_check<D>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
   hipLaunchKernelGGL((km_topo_window<D>), dim3(ms.grid[MK_TOPOW]), dim3(256), 0, s, ms.at(MK_TOPOW));
   hipLaunchKernelGGL((km_excess_prep<D, P>), dim3(ms.grid[MK_SHORT]), dim3(256), 0, s, ms.at(MK_SHORT));
@@ -702,7 +705,7 @@ void Ops<D, P>::convert(Ctx &c, hipStream_t s) {
   template void Ops<D, P>::convert(Ctx &, hipStream_t); \
   template void Ops<D, P>::convert_head(Ctx &, hipStream_t); \
   template void Ops<D, P>::convert_tail(Ctx &, hipStream_t); \
-  template void Ops<D, P>::convert_multi(const MStep &, hipStream_t);
+  template void Ops<D, P>::convert_multi(const MStep &, int, hipStream_t);
 MF_FOR_ALL(MF_INST)
 
 }  // namespace mf

@@ -460,8 +460,8 @@ template <int D, int P> struct Ops {
   static void poke(Ctx &c, hipStream_t s, int field, int64_t cell, int comp, double value);
   // batched forms (one launch per kernel for all domains of a batched step): the sweep (bulk kernel in every launch shape of vmask and the interface
   // kernel, or the per-cell kernel), the conversions, the labelling, the geometry
-  static void sweep_multi(const MStep &ms, unsigned vmask, bool cells, bool frc, hipStream_t s);
-  static void convert_multi(const MStep &ms, hipStream_t s);
+  static void sweep_multi(const MStep &ms, unsigned vmask, bool cells, bool frc, int part, hipStream_t s);
+  static void convert_multi(const MStep &ms, int part, hipStream_t s);
   static void label_multi(const MStep &ms, hipStream_t s);
   static void geometry_multi(const MStep &ms, bool mlp, hipStream_t s);
   // the bulk kernel alone in launch shape v (it writes only the spare population buffer)

@@ -896,21 +896,25 @@ void launch_bulk_multi(const MStep &ms, bool frc, hipStream_t s) {
 // in each launch shape of vmask (every domain takes work-groups in its own shape only)
 // followed by the interface kernel
 template <int D, int P>
-void Ops<D, P>::sweep_multi(const MStep &ms, unsigned vmask, bool cells, bool frc, hipStream_t s) {
+void Ops<D, P>::sweep_multi(const MStep &ms, unsigned vmask, bool cells, bool frc, int part, hipStream_t s) {
   if (cells || P == 0) {
+    if (part == 2) return;
     if (frc) hipLaunchKernelGGL((km_sweep<D, P, true>), dim3(ms.grid[MK_CELLS]), dim3(256), 0, s, ms.at(MK_CELLS));
     else hipLaunchKernelGGL((km_sweep<D, P, false>), dim3(ms.grid[MK_CELLS]), dim3(256), 0, s, ms.at(MK_CELLS));
     return;
   }
   if constexpr (P != 0) {
-    if (vmask & 1u) launch_bulk_multi<D, P, 0>(ms, frc, s);
-    if (vmask & 2u) launch_bulk_multi<D, P, 1>(ms, frc, s);
-    if (vmask & 4u) launch_bulk_multi<D, P, 2>(ms, frc, s);
-    if (vmask & 8u) launch_bulk_multi<D, P, 3>(ms, frc, s);
-    if (vmask & 16u) launch_bulk_multi<D, P, 4>(ms, frc, s);
-    if (vmask & 32u) launch_bulk_multi<D, P, 5>(ms, frc, s);
-    if (vmask & 64u) launch_bulk_multi<D, P, 6>(ms, frc, s);
-    if (vmask & 128u) launch_bulk_multi<D, P, 7>(ms, frc, s);
+    if (part != 2) {
+      if (vmask & 1u) launch_bulk_multi<D, P, 0>(ms, frc, s);
+      if (vmask & 2u) launch_bulk_multi<D, P, 1>(ms, frc, s);
+      if (vmask & 4u) launch_bulk_multi<D, P, 2>(ms, frc, s);
+      if (vmask & 8u) launch_bulk_multi<D, P, 3>(ms, frc, s);
+      if (vmask & 16u) launch_bulk_multi<D, P, 4>(ms, frc, s);
+      if (vmask & 32u) launch_bulk_multi<D, P, 5>(ms, frc, s);
+      if (vmask & 64u) launch_bulk_multi<D, P, 6>(ms, frc, s);
+      if (vmask & 128u) launch_bulk_multi<D, P, 7>(ms, frc, s);
+    }
+    if (part == 1) return;
     if (frc) hipLaunchKernelGGL((km_sweep_special<D, P, true>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
     else hipLaunchKernelGGL((km_sweep_special<D, P, false>), dim3(ms.grid[MK_LIST]), dim3(256), 0, s, ms.at(MK_LIST));
   }

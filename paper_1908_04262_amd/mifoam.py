@@ -330,7 +330,8 @@ class Sim:
 
 
 class Batch:
-    """Several domains (Sim objects) advanced together, one graph launch per two steps."""
+    """Several domains (Sim objects) advanced together, one launch per kernel for all
+    domains of a group."""
 
     def __init__(self, sims):
         self.lib = load_library()
