@@ -1170,7 +1170,9 @@ static int kind_blocks(const mf_ctx *c, int kind, int variant) {
     case MK_SHORT: return clampi(N / 65536, 1, 1024);
     case MK_TOPOW: return clampi(N / 65536, 1, 256);
     case MK_BFAST: return (c->kp.cap + 255) / 256 < 64 ? (c->kp.cap + 255) / 256 : 64;
-    case MK_MLP: return clampi(N / 16384, 1, 768);
+    // each work-group of the learned curvature stages the network's weights in LDS once: about
+    // as many cells per work-group as the single-domain launch gives the 384^3 foam
+    case MK_MLP: return clampi(N / 65536, 1, 768);
     case MK_CELLS:
       return variant < 0 ? (int)((int64_t)((c->kp.nx + 63) / 64) * ((c->kp.ny + 3) / 4) * c->kp.nz) : 0;
     default: {

@@ -568,7 +568,7 @@ enum MKind {
   MK_SHORT,     // passes over short lists: min(list_blocks, 1024)
   MK_TOPOW,     // topology windows: 256
   MK_BFAST,     // bubble table pass: min(ceil(cap / 256), 64)
-  MK_MLP,       // learned curvature: min(list_blocks, 768)
+  MK_MLP,       // learned curvature: one work-group per 65536 cells, at most 768
   MK_CELLS,     // per-cell sweep: 64 x 4 tiles
   MK_BULK0,     // bulk sweep in launch shape v: MK_BULK0 + v
   MK_COUNT = MK_BULK0 + kNumSweepVariants
