@@ -125,7 +125,6 @@ void layout(const mf_params &P, const KP &kp, Carve &cv, DA &d) {
   d.clist = cv.take<int32_t>(Np * 4);
   d.wmask = cv.take<uint32_t>(Np * 4);
   d.lcnt = cv.take<int32_t>((size_t)list_blocks_of(kp) * 4);
-  d.lcnt_b = cv.take<int32_t>((size_t)list_blocks_of(kp) * 4);
   d.sword = P.curvature == MF_CURV_MLP ? cv.take<uint32_t>(Np * 4) : nullptr;
   d.cnt = cv.take<int32_t>(2 * C_NCOUNT * 4);  // two sets, alternating by step parity
   d.nextid = cv.take<int32_t>(4);

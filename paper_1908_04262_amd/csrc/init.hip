@@ -181,14 +181,16 @@ __global__ __launch_bounds__(256) void k_nuc_fix2(KP p, DA d) {
   }
 }
 
-// Cell lists in cell order, without atomics: the interface list (type I) at the start of
-// every step, and the bubble list (gas or interface with a non-zero bubble id) on the
-// steps that relabel. The grid is cut into chunks of 16384 cells, each classified by a
-// work-group whose threads take 64 consecutive cells (16-byte type loads; labels only
-// where there is gas or interface); a count pass writes the per-chunk totals, one
+// Cell lists: the interface list (type I) at the start of every step, and the bubble list
+// (gas or interface with a non-zero bubble id) on the steps that relabel. The grid is cut
+// into chunks of 16384 cells, each classified by a work-group whose threads take 64
+// consecutive cells (16-byte type loads; labels only where there is gas or interface).
+// The interface list is kept in cell order, without atomics (the interface sweep gathers
+// faster from neighbouring cells): a count pass writes the per-chunk totals, one
 // work-group scans them, and a write pass places every entry at its chunk's offset plus
-// its rank inside the chunk. The work-groups step over the chunks, so the passes that
-// return at once (the bubble list on a step without relabelling) cost one small launch.
+// its rank inside the chunk. The bubble list is built in one pass (below). The work-groups
+// step over the chunks, so a pass that returns at once (the bubble list on a step without
+// relabelling) costs one small launch.
 constexpr int LIST_CPT = 64;
 constexpr int LIST_CHUNK = 256 * LIST_CPT;
 constexpr int LIST_GRID = 1024;
@@ -264,10 +266,6 @@ __device__ __forceinline__ int block_scan(int &si) {
   return tot;
 }
 
-// each list has its own chunk counts: the bubble list is built while the next step's
-// interface list may be under construction
-template <int WHICH> __device__ __forceinline__ int32_t *list_counts(const DA &d) { return WHICH == 0 ? d.lcnt : d.lcnt_b; }
-
 template <int WHICH> __device__ __forceinline__ bool list_skipped(const DA &d) {
   return WHICH == 1 && !*(volatile int32_t *)(d.cnt + C_TOPO);
 }
@@ -279,7 +277,7 @@ __device__ __forceinline__ void b_list_count(const GridPos &gp, KP p, DA d, int 
     const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
     int si = __popcll(list_mask<WHICH>(p, d, c0));
     const int tot = block_scan(si);
-    if (threadIdx.x == 0) list_counts<WHICH>(d)[ch] = tot;
+    if (threadIdx.x == 0) d.lcnt[ch] = tot;
   }
 }
 template <int WHICH>
@@ -295,7 +293,7 @@ __device__ __forceinline__ void b_list_scan(const GridPos &gp, DA d, int nchunks
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int per = (nchunks + 1023) / 1024;
   const int b0 = threadIdx.x * per;
-  int32_t *lc = list_counts<WHICH>(d);
+  int32_t *lc = d.lcnt;
   int si = 0;
   for (int k = 0; k < per && b0 + k < nchunks; ++k) si += lc[b0 + k];
   const int ci = si;
@@ -315,7 +313,7 @@ __device__ __forceinline__ void b_list_scan(const GridPos &gp, DA d, int nchunks
     lc[b0 + k] = oi;
     oi += a;
   }
-  if (threadIdx.x == 0) d.cnt[WHICH == 0 ? C_I : C_B] = ti;
+  if (threadIdx.x == 0) d.cnt[C_I] = ti;
 }
 template <int WHICH>
 __global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
@@ -325,30 +323,64 @@ __global__ __launch_bounds__(1024) void k_list_scan(DA d, int nchunks) {
 template <int WHICH>
 __device__ __forceinline__ void b_list_write(const GridPos &gp, KP p, DA d, int nchunks) {
   if (list_skipped<WHICH>(d)) return;
-  int32_t *list = WHICH == 0 ? d.ilist : d.blist;
+  int32_t *list = d.ilist;
   for (int ch = gp.bid; ch < nchunks; ch += gp.nblk) {
     const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
     unsigned long long mk = list_mask<WHICH>(p, d, c0);
     const int ci = __popcll(mk);
     int si = ci;
     block_scan(si);
-    int o = list_counts<WHICH>(d)[ch] + si - ci;
+    int o = d.lcnt[ch] + si - ci;
     while (mk) {
       const int b = __ffsll((long long)mk) - 1;
       mk &= mk - 1;
       const int32_t n = (int32_t)(c0 + b);
       list[o++] = n;
-      if (WHICH == 1) {
-        // union-find start of the relabelling: each bubble cell its own root
-        d.parent[n] = n;
-        flag_or(d.cflag, n, CF_VALID);
-      }
     }
   }
 }
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_list_write(KP p, DA d, int nchunks) {
   b_list_write<WHICH>(GridPos::hw(), p, d, nchunks);
+}
+
+// The bubble list in one pass: its order does not matter (the union-find hooks every
+// root under the smaller cell index, and the per-(root, id) sums are fixed point and
+// grouped by root afterwards), so each chunk takes its slots with one atomic on the list
+// length and writes its entries in cell order there. This saves the count pass, a second
+// read of the types and ids of the whole grid on every relabelling step.
+__device__ __forceinline__ void b_list_clear1(DA d) {
+  if (threadIdx.x == 0 && !list_skipped<1>(d)) d.cnt[C_B] = 0;
+}
+__global__ void k_list_clear1(DA d) { b_list_clear1(d); }
+
+__device__ __forceinline__ void b_list_append1(const GridPos &gp, KP p, DA d, int nchunks) {
+  if (list_skipped<1>(d)) return;
+  __shared__ int s_base;
+  for (int ch = gp.bid; ch < nchunks; ch += gp.nblk) {
+    const int64_t c0 = (int64_t)ch * LIST_CHUNK + (int64_t)threadIdx.x * LIST_CPT;
+    unsigned long long mk = list_mask<1>(p, d, c0);
+    const int ci = __popcll(mk);
+    int si = ci;
+    const int tot = block_scan(si);  // the same for every thread of the block
+    if (tot == 0) continue;
+    if (threadIdx.x == 0) s_base = atomicAdd(d.cnt + C_B, tot);
+    __syncthreads();
+    int o = s_base + si - ci;
+    while (mk) {
+      const int b = __ffsll((long long)mk) - 1;
+      mk &= mk - 1;
+      const int32_t n = (int32_t)(c0 + b);
+      d.blist[o++] = n;
+      // union-find start of the relabelling: each bubble cell its own root
+      d.parent[n] = n;
+      flag_or(d.cflag, n, CF_VALID);
+    }
+    __syncthreads();  // s_base is taken again by the next chunk
+  }
+}
+__global__ __launch_bounds__(256) void k_list_append1(KP p, DA d, int nchunks) {
+  b_list_append1(GridPos::hw(), p, d, nchunks);
 }
 
 template <int WHICH> static void launch_list(const Ctx &c, hipStream_t s) {
@@ -359,7 +391,12 @@ template <int WHICH> static void launch_list(const Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL(k_list_write<WHICH>, dim3(g), dim3(256), 0, s, c.kp, c.d, nch);
 }
 
-void build_bubble_list(const Ctx &c, hipStream_t s) { launch_list<1>(c, s); }
+void build_bubble_list(const Ctx &c, hipStream_t s) {
+  const int nch = list_blocks_of(c.kp);
+  const unsigned g = (unsigned)(nch < LIST_GRID ? nch : LIST_GRID);
+  hipLaunchKernelGGL(k_list_clear1, dim3(1), dim3(64), 0, s, c.d);
+  hipLaunchKernelGGL(k_list_append1, dim3(g), dim3(256), 0, s, c.kp, c.d, nch);
+}
 
 // batched forms of the list builder
 __device__ __forceinline__ int list_chunks(const KP &p) { return (int)((p.N + LIST_CHUNK - 1) / LIST_CHUNK); }
@@ -383,9 +420,22 @@ template <int WHICH> static void launch_list_multi(const MStep &ms, hipStream_t 
   hipLaunchKernelGGL(km_list_scan<WHICH>, dim3(ms.grid[MK_ONE]), dim3(1024), 0, s, ms.at(MK_ONE));
   hipLaunchKernelGGL(km_list_write<WHICH>, dim3(ms.grid[MK_LISTGRID]), dim3(256), 0, s, ms.at(MK_LISTGRID));
 }
+__global__ void km_list_clear1(MLaunch ml) {
+  MF_MULTI(MK_ONE)
+  (void)gp;
+  b_list_clear1(m.d);
+}
+__global__ __launch_bounds__(256) void km_list_append1(MLaunch ml) {
+  MF_MULTI(MK_LISTGRID)
+  b_list_append1(gp, m.kp, m.d, list_chunks(m.kp));
+}
 void lists_multi(const MStep &ms, int which, hipStream_t s) {
-  if (which == 0) launch_list_multi<0>(ms, s);
-  else launch_list_multi<1>(ms, s);
+  if (which == 0) {
+    launch_list_multi<0>(ms, s);
+  } else {
+    hipLaunchKernelGGL(km_list_clear1, dim3(ms.grid[MK_ONE]), dim3(64), 0, s, ms.at(MK_ONE));
+    hipLaunchKernelGGL(km_list_append1, dim3(ms.grid[MK_LISTGRID]), dim3(256), 0, s, ms.at(MK_LISTGRID));
+  }
 }
 
 int list_blocks_of(const KP &kp) { return (int)((kp.N + LIST_CHUNK - 1) / LIST_CHUNK); }

@@ -178,7 +178,6 @@ struct DA {
   int32_t *ilist, *blist, *nilist, *l2ilist;
   int32_t *clist;             // interface cells that fill or empty this step (sweep appends)
   int32_t *lcnt;              // per-chunk counts / offsets of the list builder [chunks]
-  int32_t *lcnt_b;            // the same for the bubble list (built on the side stream)
   int32_t *nextid;            // next unused bubble id (persistent)
   int32_t *bng;               // gas cells of each bubble id [cap]
   uint32_t *wmask;            // static: bit i set when the source x - e_i of the cell is a wall
