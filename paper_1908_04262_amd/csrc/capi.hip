@@ -1275,13 +1275,12 @@ static void group_step(const BatchGroup &g, int j, hipStream_t s) {
   g.ops.geometry_multi(ms, g.mlp, s);
 }
 
-// n time steps of a group swept by the bulk kernel, the first with table phase, on two
-// streams as a single domain's
-// step: the group stream takes the bulk sweep, the interface sweep and the first half of
-// the conversions; the side stream then takes their second half, the labelling, the
-// geometry and the next step's counter reset and interface list, beside the next bulk
-// sweep (which reads only types, populations and wall masks); the next interface sweep
-// waits for the side stream.
+// n time steps of a group swept by the bulk kernel, the first with table `phase`, on two
+// streams as in a single domain's step: the group stream takes the bulk sweep, the
+// interface sweep and the first half of the conversions; the side stream then takes their
+// second half, the labelling, the geometry and the next step's counter reset and
+// interface list, beside the next bulk sweep (which reads only types, populations and
+// wall masks); the next interface sweep waits for the side stream.
 static void group_steps_overlapped(const BatchGroup &g, int phase, int n) {
   hipStream_t m = g.stream, sd = g.side;
   {
